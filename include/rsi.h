@@ -1,0 +1,188 @@
+/*
+ * rsi.h -- C ABI of the MI355X (gfx950) segment / triangle-mesh intersection
+ * library (librsi.so).
+ *
+ * The problem (paper, Section 1): N_r line segments l_i = (r_start_i, r_end_i)
+ * in R^3 are tested against a surface of N_t triangles, each an index triplet
+ * into N_v vertices.  The default answer is one crossing flag per segment;
+ * the paper's extended usage (Section 2.4) returns the crossing point and
+ * triangle (`barycentric`) or the number of crossings (`intercept_count`).
+ * Inputs use the layouts of the paper's input files (Section 2.5): vertices
+ * FP32 x,y,z interleaved, triangles int32 triplets, segment starts and ends
+ * FP32 x,y,z interleaved.
+ *
+ * The library builds a linear BVH over the triangles (Section 2: centroids,
+ * quantisation to 2^21 levels per axis, 64-bit Morton codes, sort, binary
+ * radix tree with bottom-up bounds and a per-node arrival counter, Section
+ * 3.1) and answers queries by stack traversal with a Moller-Trumbore test at
+ * the leaves (Section 2, Section 3.2, Section 3.3).
+ *
+ * Conventions for every call
+ *   - Pointers named as device pointers must be device memory on the current
+ *     HIP device (for example torch CUDA tensors); host structs are read
+ *     before the call returns and may be freed afterwards.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is enqueued on it; calls return without waiting unless stated.
+ *   - No exception crosses the ABI; every call returns an rsi_status and
+ *     rsi_last_error() describes the last failure on the calling thread.
+ *   - A handle serves one call at a time.
+ */
+#ifndef RSI_H
+#define RSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rsi_bvh *rsi_handle;
+
+typedef enum {
+    RSI_OK = 0,
+    RSI_E_INVALID = 1,   /* bad argument: negative size, null pointer, out-of-range index, bad mode */
+    RSI_E_NOMEM = 2,     /* a device allocation failed */
+    RSI_E_HIP = 3,       /* a HIP runtime call or kernel launch failed */
+    RSI_E_OVERFLOW = 4   /* a caller-sized buffer is too small; counts stay exact */
+} rsi_status;
+
+/* Query modes (bit mask).  RSI_FIRST_HIT and RSI_ALL_HITS may be combined;
+ * RSI_BOOL may be added to either and is then derived from the same pass. */
+enum {
+    RSI_BOOL = 1u,       /* crossing flag per segment (paper Section 1, default output) */
+    RSI_FIRST_HIT = 2u,  /* crossing with the smallest t; exact ties go to the smaller
+                            triangle id (our reading of `barycentric`, Section 2.4) */
+    RSI_ALL_HITS = 4u    /* exact count plus every crossing, ordered by (t, id)
+                            (`intercept_count`, Section 2.4 and 2.6) */
+};
+
+/* Build / query options; a zero field selects the default. */
+typedef struct {
+    int32_t leaf_size;    /* max triangles per BVH leaf, 1..16 (default 1) */
+    int32_t block_size;   /* traversal workgroup size, multiple of 64 in 64..1024 (default 256) */
+    int32_t reserved0;
+    int32_t reserved1;
+} rsi_opts;
+
+/* Output buffers of rsi_query (host struct of device pointers, each [n_r...]).
+ * Pointers for modes not requested are ignored and may be NULL. */
+typedef struct {
+    uint8_t *hit;      /* RSI_BOOL      [n_r]    1 if the segment crosses the mesh, else 0 */
+    int32_t *tri;      /* RSI_FIRST_HIT [n_r]    triangle id (row of T) of the first hit; -1 on a miss */
+    float *t;          /*               [n_r]    fraction along the segment, P = S + t (E - S); +inf on a miss */
+    float *uv;         /*               [n_r*2]  weights of the triangle's 2nd and 3rd vertex; 0 on a miss */
+    float *point;      /*               [n_r*3]  hit point P; 0 on a miss */
+    int32_t *count;    /* RSI_ALL_HITS  [n_r]    exact number of crossings */
+    int32_t *ids;      /*               [n_r*capacity] first min(count, capacity) crossings by (t, id); -1 padding */
+    float *ts;         /*               [n_r*capacity] their t; +inf padding */
+    int32_t capacity;  /* K >= 1 slots per segment for RSI_ALL_HITS */
+    int32_t reserved;
+} rsi_outputs;
+
+/* Build a BVH over the mesh (paper Section 2: Morton-ordered binary radix
+ * tree; Section 3.1 node definitions; Table 2 lists the build steps).
+ *   V  device, float32 [n_v*3] vertex coordinates x,y,z (Section 2.5 layout)
+ *   T  device, int32   [n_t*3] vertex indices per triangle, each in [0, n_v)
+ *   opts host, may be NULL.
+ * The handle keeps its own packed copy of the geometry; V and T may be freed
+ * afterwards.  Blocks until the build has finished on `stream` (to validate
+ * the indices and size the traversal stack).
+ * Errors: RSI_E_INVALID for n_v < 0, n_t < 0, n_t >= 2^27, a NULL pointer with
+ * a nonzero size or an index outside [0, n_v); RSI_E_NOMEM; RSI_E_HIP.
+ * n_t == 0 gives a handle whose queries report no crossing. */
+rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
+                     const rsi_opts *opts, void *stream, rsi_handle *out);
+
+/* Rebuild the tree of an existing handle for new geometry with the same
+ * triangle count n_t (all build steps of rsi_build, reusing the handle's
+ * device memory, so nothing is allocated).  V, T, n_v as for rsi_build;
+ * blocks until done.  Errors as for rsi_build. */
+rsi_status rsi_rebuild(rsi_handle h, const float *V, int64_t n_v, const int32_t *T, void *stream);
+
+/* Recompute every bound and the packed geometry from new vertex positions
+ * with the same triangles and the same tree topology (the bottom-up pass of
+ * Section 3.1 with its arrival counters).  V: device float32 [n_v*3].
+ * Asynchronous on `stream`. */
+rsi_status rsi_refit(rsi_handle h, const float *V, void *stream);
+
+/* Test n_r segments (paper Section 1; traversal of Section 3.2, kernel of
+ * Section 3.3).
+ *   S, E  device, float32 [n_r*3] segment starts and ends
+ *   mode  bit mask of RSI_BOOL / RSI_FIRST_HIT / RSI_ALL_HITS (nonzero)
+ *   out   host struct of device output pointers (see rsi_outputs)
+ * RSI_BOOL alone stops each segment at its first crossing.  RSI_ALL_HITS keeps
+ * up to `capacity` crossings per segment in `ids`/`ts`; a segment with more
+ * is appended to an overflow list and traversed again into a library-owned
+ * spill pool holding all its crossings (read it with rsi_spill_*).  With
+ * RSI_ALL_HITS the call waits once on `stream` to size that pool; otherwise it
+ * is asynchronous.  Reported t, u, v and P are re-solved in FP64 from the FP32
+ * inputs; the crossing decisions are the FP32 test.
+ * Errors: RSI_E_INVALID (n_r < 0, mode 0 or unknown bits, missing output
+ * pointer, capacity < 1), RSI_E_NOMEM, RSI_E_HIP. */
+rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
+                     uint32_t mode, const rsi_outputs *out, void *stream);
+
+/* After an RSI_ALL_HITS query: number of overflowed segments and total
+ * crossings held in the spill pool (host out-parameters). */
+rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossings);
+
+/* Copy the spill pool into caller device buffers:
+ *   seg    int32 [n_segments]  segment index
+ *   offset int64 [n_segments]  first crossing of that segment in ids/ts
+ *   count  int32 [n_segments]  its number of crossings
+ *   ids    int32 [n_crossings] triangle ids, per segment ordered by (t, id)
+ *   ts     float [n_crossings] their t
+ * Asynchronous on `stream`.  Entries are grouped per segment; the order of
+ * the segments themselves is unspecified. */
+rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *count,
+                          int32_t *ids, float *ts, void *stream);
+
+/* Work counters of the last query when it ran with counting enabled
+ * (rsi_set_counting(h, 1)): node visits (internal nodes whose two child boxes
+ * were tested), child box tests and triangle tests, summed over segments. */
+typedef struct {
+    uint64_t node_visits;
+    uint64_t box_tests;
+    uint64_t tri_tests;
+    uint64_t segments;
+} rsi_counters;
+rsi_status rsi_set_counting(rsi_handle h, int enable);
+rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);
+
+/* Tree description for validation (host out-parameters / host buffers).
+ *   n_nodes: number of node records (n_t, the last one being the entry node
+ *   whose left child is the root, as in the paper's Section 2), height: levels
+ *   of internal nodes below the entry node, leaf_size: as built. */
+typedef struct {
+    int64_t n_t;
+    int64_t n_nodes;
+    int32_t height;
+    int32_t leaf_size;
+    int32_t entry;
+    int32_t reserved;
+} rsi_tree_info;
+rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out);
+
+/* Copy the tree to host buffers (blocking):
+ *   boxes  float  [n_nodes*12] per node: left child lo xyz, hi xyz, right child lo xyz, hi xyz
+ *   refs   int32  [n_nodes*2]  left and right child references: >= 0 internal
+ *                              node index; < 0 leaf, with first sorted triangle
+ *                              (ref & 0x07FFFFFF) and count ((ref >> 27) & 15) + 1
+ *   order  int32  [n_t]        original triangle id at each sorted position
+ *   keys   uint64 [n_t]        sorted Morton codes
+ * Any pointer may be NULL to skip it. */
+rsi_status rsi_export_tree(rsi_handle h, float *boxes, int32_t *refs, int32_t *order, uint64_t *keys);
+
+/* Release the handle and its device memory (waits for its pending work). */
+void rsi_destroy(rsi_handle h);
+
+const char *rsi_status_str(rsi_status s);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *rsi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSI_H */

@@ -1,0 +1,253 @@
+// sort.hip -- stable LSD radix sort of (uint64 key, uint32 value) pairs,
+// 8-bit digits, LDS-staged (the "sort Morton codes" step of the paper's
+// Table 2, which there ran on the host).
+//
+// One pass per digit, three launches per pass:
+//   k_hist     per-tile digit histogram in LDS -> hist[digit][tile]
+//   k_scan     one workgroup turns hist into exclusive global offsets
+//              (digit-major, so the offset of (digit, tile) is the count of
+//              all smaller digits plus this digit in earlier tiles)
+//   k_scatter  per tile: stable rank of every element among equal digits
+//              via wave64 ballots, reorder the tile in LDS by digit, then
+//              write each digit run to its global offset (contiguous runs)
+// Tiles are 256 threads x 8 items in striped order (item r of thread x is
+// element r*256 + x), which fixes the stable order (r, wave, lane).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsi_host.h"
+
+namespace rsi {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;
+constexpr int kRadix = 256;
+constexpr int kWaves = kThreads / 64;
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                   uint32_t *__restrict__ hist, int ntiles)
+{
+    __shared__ uint32_t h[kRadix];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * kThreads + tid;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+// Exclusive scan of n counts in place by one workgroup of 1024 threads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS,
+// then each thread rewrites its chunk.
+__global__ __launch_bounds__(1024) void k_scan(uint32_t *__restrict__ a, int64_t n)
+{
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = tid * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    uint32_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += a[i];
+    part[tid] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over 1024 partial sums
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = tid >= off ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = tid ? part[tid - 1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__device__ inline uint64_t lanemask_lt()
+{
+    const uint32_t lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin,
+                                                      const uint32_t *__restrict__ vin,
+                                                      uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                      int64_t n, int shift, const uint32_t *__restrict__ offs,
+                                                      int ntiles)
+{
+    __shared__ uint32_t run[kRadix];          // elements of each digit ranked so far in this tile
+    __shared__ uint32_t wcnt[kWaves][kRadix]; // per-wave digit counts of the current round
+    __shared__ uint32_t start[kRadix];        // exclusive scan of the tile's digit counts
+    __shared__ uint32_t gbase[kRadix];        // global offset of (digit, this tile)
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    __syncthreads();
+
+    uint64_t key[kItems];
+    uint32_t val[kItems];
+    uint32_t dig[kItems];
+    uint32_t rank[kItems];
+    const uint64_t lt = lanemask_lt();
+
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kThreads + tid;
+        const bool valid = i < n;
+        key[r] = valid ? kin[i] : 0ull;
+        val[r] = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+        dig[r] = d;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        if (valid && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t before = run[d];
+        for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+        rank[r] = before + below;
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+
+    // exclusive scan of the tile's per-digit counts (run[]) into start[]
+    if (tid < 64) {
+        uint32_t c0 = run[4 * tid], c1 = run[4 * tid + 1], c2 = run[4 * tid + 2], c3 = run[4 * tid + 3];
+        uint32_t s4 = c0 + c1 + c2 + c3;
+        uint32_t incl = s4;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t v = __shfl_up(incl, off, 64);
+            if ((int)__lane_id() >= off) incl += v;
+        }
+        uint32_t ex = incl - s4;
+        start[4 * tid] = ex;
+        start[4 * tid + 1] = ex + c0;
+        start[4 * tid + 2] = ex + c0 + c1;
+        start[4 * tid + 3] = ex + c0 + c1 + c2;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kThreads + tid;
+        if (i < n) {
+            const uint32_t p = start[dig[r]] + rank[r];
+            skey[p] = key[r];
+            sval[p] = val[r];
+        }
+    }
+    __syncthreads();
+
+    const int64_t rem = n - base;
+    const int cnt = rem < kTile ? (int)rem : kTile;
+    for (int p = tid; p < cnt; p += kThreads) {
+        const uint64_t k = skey[p];
+        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+        const int64_t dst = (int64_t)gbase[d] + (p - start[d]);
+        kout[dst] = k;
+        vout[dst] = sval[p];
+    }
+}
+
+__global__ void k_copy_pairs(const uint64_t *__restrict__ ks, const uint32_t *__restrict__ vs,
+                             uint64_t *__restrict__ kd, uint32_t *__restrict__ vd, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+}  // namespace
+
+hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
+{
+    hipError_t e = hipSuccess;
+    if (n > sc.cap) {
+        if (sc.keys_alt) (void)hipFree(sc.keys_alt);
+        if (sc.vals_alt) (void)hipFree(sc.vals_alt);
+        sc.keys_alt = nullptr;
+        sc.vals_alt = nullptr;
+        sc.cap = 0;
+        if ((e = hipMalloc(&sc.keys_alt, sizeof(uint64_t) * n)) != hipSuccess) return e;
+        if ((e = hipMalloc(&sc.vals_alt, sizeof(uint32_t) * n)) != hipSuccess) return e;
+        sc.cap = n;
+    }
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    const int64_t hn = ntiles * kRadix;
+    if (hn > sc.hist_cap) {
+        if (sc.hist) (void)hipFree(sc.hist);
+        sc.hist = nullptr;
+        sc.hist_cap = 0;
+        if ((e = hipMalloc(&sc.hist, sizeof(uint32_t) * hn)) != hipSuccess) return e;
+        sc.hist_cap = hn;
+    }
+    return e;
+}
+
+void free_sort_scratch(SortScratch &sc)
+{
+    if (sc.keys_alt) (void)hipFree(sc.keys_alt);
+    if (sc.vals_alt) (void)hipFree(sc.vals_alt);
+    if (sc.hist) (void)hipFree(sc.hist);
+    sc = SortScratch();
+}
+
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &sc,
+                            hipStream_t s)
+{
+    if (n <= 1) return hipSuccess;
+    hipError_t e = ensure_sort_scratch(sc, n);
+    if (e != hipSuccess) return e;
+    const int ntiles = (int)((n + kTile - 1) / kTile);
+    const int passes = (key_bits + 7) / 8;
+    uint64_t *ka = keys, *kb = sc.keys_alt;
+    uint32_t *va = vals, *vb = sc.vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, n, shift, sc.hist, ntiles);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, (int64_t)ntiles * kRadix);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift, sc.hist,
+                           ntiles);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        const int blk = 256;
+        hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, s, ka, va, keys,
+                           vals, n);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rsi

@@ -1,0 +1,299 @@
+"""Thin ctypes binding of librsi.so (include/rsi.h).
+
+Argument marshalling only: every step of the build and the queries runs in
+the library's HIP kernels.  torch supplies device memory and the stream.  If
+librsi.so has not been built, every call raises RuntimeError; there is no
+fallback path.
+
+Low-level functions carry the C names (rsi_build, rsi_query, ...).  `Mesh`
+wraps a handle and allocates output tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsi.so")
+
+RSI_OK, RSI_E_INVALID, RSI_E_NOMEM, RSI_E_HIP, RSI_E_OVERFLOW = range(5)
+RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS = 1, 2, 4
+MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS}
+
+EXPORTED = [
+    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_spill_info", "rsi_spill_read",
+    "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_export_tree",
+    "rsi_destroy", "rsi_status_str", "rsi_last_error",
+]
+
+
+class RsiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class rsi_opts(ctypes.Structure):
+    _fields_ = [("leaf_size", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class rsi_outputs(ctypes.Structure):
+    _fields_ = [("hit", ctypes.c_void_p), ("tri", ctypes.c_void_p), ("t", ctypes.c_void_p),
+                ("uv", ctypes.c_void_p), ("point", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("ids", ctypes.c_void_p), ("ts", ctypes.c_void_p), ("capacity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class rsi_counters(ctypes.Structure):
+    _fields_ = [("node_visits", ctypes.c_uint64), ("box_tests", ctypes.c_uint64),
+                ("tri_tests", ctypes.c_uint64), ("segments", ctypes.c_uint64)]
+
+
+class rsi_tree_info(ctypes.Structure):
+    _fields_ = [("n_t", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("height", ctypes.c_int32),
+                ("leaf_size", ctypes.c_int32), ("entry", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librsi.so (raises RuntimeError when it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(hipcc --offload-arch=gfx950); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+    H = ctypes.c_void_p
+    L.rsi_build.argtypes = [P, i64, P, i64, ctypes.POINTER(rsi_opts), P, ctypes.POINTER(H)]
+    L.rsi_rebuild.argtypes = [H, P, i64, P, P]
+    L.rsi_refit.argtypes = [H, P, P]
+    L.rsi_query.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
+    L.rsi_spill_info.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.rsi_spill_read.argtypes = [H, P, P, P, P, P, P]
+    L.rsi_set_counting.argtypes = [H, ctypes.c_int]
+    L.rsi_get_counters.argtypes = [H, ctypes.POINTER(rsi_counters)]
+    L.rsi_get_tree_info.argtypes = [H, ctypes.POINTER(rsi_tree_info)]
+    L.rsi_export_tree.argtypes = [H, P, P, P, P]
+    L.rsi_destroy.argtypes = [H]
+    L.rsi_destroy.restype = None
+    L.rsi_status_str.argtypes = [ctypes.c_int]
+    L.rsi_status_str.restype = ctypes.c_char_p
+    L.rsi_last_error.argtypes = []
+    L.rsi_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("rsi_destroy", "rsi_status_str", "rsi_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != RSI_OK:
+        L = lib()
+        raise RsiError(status, (L.rsi_last_error() or b"").decode() or L.rsi_status_str(status).decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(x, name, cols=3):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2 or x.shape[1] != cols:
+        raise TypeError(f"{name} must be a contiguous float32 [n, {cols}] tensor")
+    return x
+
+
+def _dev_i32(x, name):
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.int32 or not x.is_contiguous() or x.dim() != 2 or x.shape[1] != 3:
+        raise TypeError(f"{name} must be a contiguous int32 [n, 3] tensor")
+    return x
+
+
+# ------------------------------------------------------------ C functions --
+
+def rsi_build(V, T, leaf_size=0, block_size=0, stream=None):
+    V = _dev_f32(V, "V")
+    T = _dev_i32(T, "T")
+    h = ctypes.c_void_p()
+    o = rsi_opts(leaf_size, block_size, 0, 0)
+    _check(lib().rsi_build(_ptr(V), V.shape[0], _ptr(T), T.shape[0], ctypes.byref(o), _stream(stream),
+                           ctypes.byref(h)))
+    return h
+
+
+def rsi_rebuild(h, V, T, stream=None):
+    V = _dev_f32(V, "V")
+    T = _dev_i32(T, "T")
+    _check(lib().rsi_rebuild(h, _ptr(V), V.shape[0], _ptr(T), _stream(stream)))
+
+
+def rsi_refit(h, V, stream=None):
+    V = _dev_f32(V, "V")
+    _check(lib().rsi_refit(h, _ptr(V), _stream(stream)))
+
+
+def rsi_query(h, S, E, mode, out: rsi_outputs, stream=None):
+    S = _dev_f32(S, "S")
+    E = _dev_f32(E, "E")
+    if S.shape != E.shape:
+        raise ValueError("S and E must have the same shape")
+    _check(lib().rsi_query(h, _ptr(S), _ptr(E), S.shape[0], mode, ctypes.byref(out), _stream(stream)))
+
+
+def rsi_spill_info(h):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rsi_spill_info(h, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def rsi_spill_read(h, seg, offset, count, ids, ts, stream=None):
+    _check(lib().rsi_spill_read(h, _ptr(seg), _ptr(offset), _ptr(count), _ptr(ids), _ptr(ts),
+                                _stream(stream)))
+
+
+def rsi_set_counting(h, enable: bool):
+    _check(lib().rsi_set_counting(h, 1 if enable else 0))
+
+
+def rsi_get_counters(h):
+    c = rsi_counters()
+    _check(lib().rsi_get_counters(h, ctypes.byref(c)))
+    return {"node_visits": c.node_visits, "box_tests": c.box_tests, "tri_tests": c.tri_tests,
+            "segments": c.segments}
+
+
+def rsi_get_tree_info(h):
+    t = rsi_tree_info()
+    _check(lib().rsi_get_tree_info(h, ctypes.byref(t)))
+    return {"n_t": t.n_t, "n_nodes": t.n_nodes, "height": t.height, "leaf_size": t.leaf_size,
+            "entry": t.entry}
+
+
+def rsi_export_tree(h):
+    import numpy as np
+    info = rsi_get_tree_info(h)
+    n = info["n_nodes"]
+    boxes = np.zeros((max(n, 1), 12), np.float32)
+    refs = np.zeros((max(n, 1), 2), np.int32)
+    order = np.zeros(max(info["n_t"], 1), np.int32)
+    keys = np.zeros(max(info["n_t"], 1), np.uint64)
+    P = ctypes.c_void_p
+    _check(lib().rsi_export_tree(h, boxes.ctypes.data_as(P), refs.ctypes.data_as(P),
+                                 order.ctypes.data_as(P), keys.ctypes.data_as(P)))
+    return {"boxes": boxes[:n], "refs": refs[:n], "order": order[:info["n_t"]], "keys": keys[:info["n_t"]],
+            **info}
+
+
+def rsi_destroy(h):
+    if h:
+        lib().rsi_destroy(h)
+
+
+# ---------------------------------------------------------------- helpers --
+
+def parse_mode(mode) -> int:
+    if isinstance(mode, int):
+        return mode
+    m = 0
+    for part in str(mode).replace("+", "|").split("|"):
+        m |= MODE_NAMES[part.strip()]
+    return m
+
+
+class Mesh:
+    """A BVH over a triangle mesh on the current HIP device."""
+
+    def __init__(self, V, T, leaf_size=0, block_size=0, stream=None):
+        self.V = V
+        self.T = T
+        self.n_t = T.shape[0]
+        self.handle = rsi_build(V, T, leaf_size, block_size, stream)
+
+    def rebuild(self, V, T, stream=None):
+        rsi_rebuild(self.handle, V, T, stream)
+
+    def refit(self, V, stream=None):
+        rsi_refit(self.handle, V, stream)
+
+    def alloc_outputs(self, n_r, mode, capacity=4, device=None):
+        mode = parse_mode(mode)
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        out = {}
+        if mode & RSI_BOOL:
+            out["hit"] = torch.empty(n_r, dtype=torch.uint8, device=dev)
+        if mode & RSI_FIRST_HIT:
+            out["tri"] = torch.empty(n_r, dtype=torch.int32, device=dev)
+            out["t"] = torch.empty(n_r, dtype=torch.float32, device=dev)
+            out["uv"] = torch.empty(n_r, 2, dtype=torch.float32, device=dev)
+            out["point"] = torch.empty(n_r, 3, dtype=torch.float32, device=dev)
+        if mode & RSI_ALL_HITS:
+            out["count"] = torch.empty(n_r, dtype=torch.int32, device=dev)
+            out["ids"] = torch.empty(n_r, capacity, dtype=torch.int32, device=dev)
+            out["ts"] = torch.empty(n_r, capacity, dtype=torch.float32, device=dev)
+        return out
+
+    @staticmethod
+    def outputs_struct(out, capacity=4):
+        return rsi_outputs(_ptr(out.get("hit")), _ptr(out.get("tri")), _ptr(out.get("t")),
+                           _ptr(out.get("uv")), _ptr(out.get("point")), _ptr(out.get("count")),
+                           _ptr(out.get("ids")), _ptr(out.get("ts")), capacity, 0)
+
+    def query_into(self, S, E, mode, out, capacity=4, stream=None):
+        rsi_query(self.handle, S, E, parse_mode(mode), self.outputs_struct(out, capacity), stream)
+        return out
+
+    def query(self, S, E, mode="bool", capacity=4, stream=None):
+        mode = parse_mode(mode)
+        out = self.alloc_outputs(S.shape[0], mode, capacity, S.device)
+        self.query_into(S, E, mode, out, capacity, stream)
+        if mode & RSI_ALL_HITS:
+            nseg, ntot = rsi_spill_info(self.handle)
+            if nseg:
+                dev = S.device
+                sp = {"seg": torch.empty(nseg, dtype=torch.int32, device=dev),
+                      "offset": torch.empty(nseg, dtype=torch.int64, device=dev),
+                      "count": torch.empty(nseg, dtype=torch.int32, device=dev),
+                      "ids": torch.empty(ntot, dtype=torch.int32, device=dev),
+                      "ts": torch.empty(ntot, dtype=torch.float32, device=dev)}
+                rsi_spill_read(self.handle, sp["seg"], sp["offset"], sp["count"], sp["ids"], sp["ts"], stream)
+                out["spill"] = sp
+        return out
+
+    def set_counting(self, enable=True):
+        rsi_set_counting(self.handle, enable)
+
+    def counters(self):
+        return rsi_get_counters(self.handle)
+
+    def tree(self):
+        return rsi_export_tree(self.handle)
+
+    def tree_info(self):
+        return rsi_get_tree_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            rsi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

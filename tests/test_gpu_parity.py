@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Covers the boolean mode of the paper's Section 1, the first-hit and
+crossing-count modes of Section 2.4, the stack traversal of Section 3.2 and
+the build of Section 2 / Section 3.1, on the seeded workloads (a 1,922- and a
+29,768-triangle heightfield, a closed noisy sphere), plus edge cases.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2209_02878_amd import rsi
+from paper_2209_02878_amd import workloads as wl
+import oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+def _mesh(V, T, **kw):
+    return rsi.Mesh(_t(V), _t(T, torch.int32), **kw)
+
+
+def _run(mesh, S, E, mode, cap=4):
+    out = mesh.query(_t(S), _t(E), mode, capacity=cap)
+    torch.cuda.synchronize()
+    return out
+
+
+def _full_lists(V, T, S, E, segs, cap=256):
+    r = oracle.query(V, T, S[segs], E[segs], cap=cap)
+    lists = {}
+    for k, s in enumerate(segs):
+        c = r["count"][k]
+        assert c < cap
+        lists[int(s)] = [(r["list_t"][k, j], int(r["list_tri"][k, j])) for j in range(c)]
+    return lists
+
+
+# ------------------------------------------------------------------ golden --
+
+def test_handbuilt_cases_gpu():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "handbuilt_cases.json")) as f:
+        g = json.load(f)
+    for c in g["cases"]:
+        if c["degenerate"]:
+            continue
+        m = g["meshes"][c["mesh"]]
+        mesh = _mesh(np.array(m["V"], np.float32), np.array(m["T"], np.int32))
+        S = np.array([c["S"]], np.float32)
+        E = np.array([c["E"]], np.float32)
+        out = _run(mesh, S, E, "bool|first|all", cap=4)
+        assert int(out["hit"][0]) == (1 if c["count"] else 0), c["why"]
+        assert int(out["count"][0]) == c["count"], c["why"]
+        for k, (tri, t, u, v) in enumerate(c["list"]):
+            assert int(out["ids"][0, k]) == tri, c["why"]
+            assert abs(float(out["ts"][0, k]) - t) <= 1e-6
+        if c["count"]:
+            tri, t, u, v = c["list"][0]
+            assert int(out["tri"][0]) == tri
+            assert abs(float(out["t"][0]) - t) <= 1e-6
+            np.testing.assert_allclose(out["uv"][0].cpu().numpy(), [u, v], atol=1e-6)
+            np.testing.assert_allclose(out["point"][0].cpu().numpy(), c["P"], atol=1e-6)
+        else:
+            assert int(out["tri"][0]) == -1
+        mesh.close()
+
+
+# -------------------------------------------------------------- workloads ---
+
+@pytest.fixture(scope="module")
+def c1():
+    w = wl.config1()
+    ref = parity.oracle_reference(w.V, w.T, w.S, w.E, cap=8)
+    return w, ref
+
+
+@pytest.mark.parametrize("leaf", [1, 4])
+def test_config1_bool_full(c1, leaf):
+    w, ref = c1
+    mesh = _mesh(w.V, w.T, leaf_size=leaf)
+    out = _run(mesh, w.S, w.E, "bool")
+    rep = parity.compare(ref, out, {"bool"})
+    print(rep)
+    assert rep["degenerate"] < 0.01 * rep["n"]
+    parity.assert_parity(rep)
+
+
+def test_config1_first_and_all(c1):
+    w, ref = c1
+    mesh = _mesh(w.V, w.T)
+    out = _run(mesh, w.S, w.E, "bool|first|all", cap=8)
+    rep = parity.compare(ref, out, {"bool", "first", "all"}, cap=8)
+    print(rep)
+    parity.assert_parity(rep)
+    # separate single-mode passes give the same answers as the combined pass
+    out_b = _run(mesh, w.S, w.E, "bool")
+    out_f = _run(mesh, w.S, w.E, "first")
+    assert torch.equal(out_b["hit"], out["hit"])
+    assert torch.equal(out_f["tri"], out["tri"])
+    assert torch.equal(out_f["t"], out["t"])
+
+
+def test_config2_mesh_100k():
+    w = wl.config2(n_r=100_000)
+    ref = parity.oracle_reference(w.V, w.T, w.S, w.E, cap=4)
+    mesh = _mesh(w.V, w.T)
+    info = mesh.tree_info()
+    assert info["n_t"] == 29_768
+    out = _run(mesh, w.S, w.E, "bool|first|all", cap=4)
+    rep = parity.compare(ref, out, {"bool", "first", "all"}, cap=4)
+    print(rep)
+    assert rep["degenerate"] < 0.01 * rep["n"]
+    parity.assert_parity(rep)
+
+
+def test_config2_full_size_sampled():
+    """10M segments in the benchmark's launch configuration; a seeded sample
+    of 20k segments is checked against the oracle one by one."""
+    w = wl.config2()
+    idx = wl.subset(w.n_r, 20_000, wl.seed_for(2, 3))
+    mesh = _mesh(w.V, w.T)
+    S, E = _t(w.S), _t(w.E)
+    out = mesh.query(S, E, "bool")
+    out_all = mesh.query(S, E, "all", capacity=4)
+    torch.cuda.synchronize()
+    ref = parity.oracle_reference(w.V, w.T, w.S[idx], w.E[idx], cap=4)
+    sub = {"hit": out["hit"].cpu().numpy()[idx], "count": out_all["count"].cpu().numpy()[idx],
+           "ids": out_all["ids"].cpu().numpy()[idx], "ts": out_all["ts"].cpu().numpy()[idx]}
+    rep = parity.compare(ref, sub, {"bool", "all"}, cap=4)
+    print(rep)
+    parity.assert_parity(rep)
+    # property over all 10M: the flag is set exactly when the count is nonzero
+    assert torch.equal(out["hit"].bool(), out_all["count"] > 0)
+
+
+def test_closed_sphere_all_hits_overflow():
+    """All-hits with capacity 1 on a closed surface: most crossing segments
+    overflow, the spill pass must return every crossing in (t, id) order."""
+    V, T = wl.noisy_sphere(24, 99, 0.3)
+    rng = np.random.default_rng(5)
+    S, E = wl.segments_in_box(rng, V.min(0), V.max(0), 20_000, scale=1.5)
+    ref = parity.oracle_reference(V, T, S, E, cap=1)
+    mesh = _mesh(V, T)
+    out = _run(mesh, S, E, "all|first", cap=1)
+    sp = out.get("spill")
+    assert sp is not None and sp["seg"].numel() > 1000
+    segs = sp["seg"].cpu().numpy()
+    ref["full_lists"] = _full_lists(V, T, S, E, np.sort(segs))
+    rep = parity.compare(ref, out, {"all", "first"}, cap=1, spill=sp)
+    print(rep)
+    assert rep["spill_checked"] > 1000
+    parity.assert_parity(rep)
+    # non-degenerate counts are even for segments with both ends outside the surface
+    R = np.linalg.norm(V.astype(np.float64), axis=1).max()
+    outside = (np.linalg.norm(S, axis=1) > R) & (np.linalg.norm(E, axis=1) > R) & (ref["degenerate"] == 0)
+    assert np.all(out["count"].cpu().numpy()[outside] % 2 == 0)
+
+
+# ------------------------------------------------------------------ edges ---
+
+def test_edge_cases():
+    V, T = wl.sinusoid_heightfield(8, 3, 0.1)
+    mesh = _mesh(V, T)
+    # no segments
+    out = mesh.query(torch.zeros(0, 3, device=DEV), torch.zeros(0, 3, device=DEV), "bool|first|all")
+    assert out["hit"].numel() == 0
+    # zero-length segment, segment far away
+    S = np.array([[0.5, 0.5, 0.0], [5, 5, 5]], np.float32)
+    E = np.array([[0.5, 0.5, 0.0], [6, 6, 6]], np.float32)
+    out = _run(mesh, S, E, "bool|first|all")
+    assert out["hit"].tolist() == [0, 0]
+    assert out["count"].tolist() == [0, 0]
+    assert out["tri"].tolist() == [-1, -1]
+    mesh.close()
+    # empty mesh
+    m0 = _mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+    rng = np.random.default_rng(1)
+    S = rng.uniform(size=(100, 3)).astype(np.float32)
+    out = _run(m0, S, S + 1, "bool|first|all")
+    assert int(out["hit"].sum()) == 0 and int(out["count"].sum()) == 0
+    assert bool((out["tri"] == -1).all()) and bool(torch.isinf(out["t"]).all())
+    m0.close()
+    # single triangle
+    V1 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    m1 = _mesh(V1, np.array([[0, 1, 2]], np.int32))
+    S = np.array([[0.25, 0.25, 1], [0.75, 0.75, 1]], np.float32)
+    E = np.array([[0.25, 0.25, -1], [0.75, 0.75, -1]], np.float32)
+    out = _run(m1, S, E, "bool|first")
+    assert out["hit"].tolist() == [1, 0]
+    assert abs(float(out["t"][0]) - 0.5) < 1e-7
+    m1.close()
+
+
+def test_invalid_arguments():
+    V = _t(np.zeros((3, 3), np.float32))
+    with pytest.raises(rsi.RsiError):
+        rsi.Mesh(V, _t(np.array([[0, 1, 3]], np.int32), torch.int32))
+    with pytest.raises(rsi.RsiError):
+        rsi.Mesh(V, _t(np.array([[0, 1, 2]], np.int32), torch.int32), leaf_size=17)
+    m = rsi.Mesh(V, _t(np.array([[0, 1, 2]], np.int32), torch.int32))
+    S = torch.zeros(4, 3, device=DEV)
+    with pytest.raises(rsi.RsiError):
+        m.query_into(S, S, 8, {})
+    with pytest.raises(rsi.RsiError):
+        m.query_into(S, S, rsi.RSI_BOOL, {})
+    m.close()
+
+
+def test_ragged_sizes_and_options():
+    """Sizes that are not multiples of the block or of the sort tile, every
+    leaf size and two block sizes give identical answers."""
+    V, T = wl.noisy_sphere(9, 4, 0.3)
+    rng = np.random.default_rng(8)
+    S, E = wl.segments_in_box(rng, V.min(0), V.max(0), 12_347, scale=1.5)
+    base = None
+    for leaf, block in [(1, 256), (2, 64), (8, 256), (16, 512), (3, 192)]:
+        mesh = _mesh(V, T, leaf_size=leaf, block_size=block)
+        out = _run(mesh, S, E, "bool|first|all", cap=2)
+        res = {k: v.cpu() for k, v in out.items() if k != "spill"}
+        if base is None:
+            base = res
+            ref = parity.oracle_reference(V, T, S, E, cap=2)
+            rep = parity.compare(ref, out, {"bool", "first", "all"}, cap=2)
+            parity.assert_parity(rep)
+        else:
+            for k in ("hit", "tri", "t", "count", "ids", "ts"):
+                assert torch.equal(base[k], res[k]), (leaf, block, k)
+        mesh.close()
+
+
+def test_deterministic_repeat():
+    w = wl.config1(n_r=50_000)
+    mesh = _mesh(w.V, w.T)
+    a = _run(mesh, w.S, w.E, "bool|first|all", cap=4)
+    b = _run(mesh, w.S, w.E, "bool|first|all", cap=4)
+    for k in ("hit", "tri", "t", "uv", "point", "count", "ids", "ts"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_refit_matches_fresh_build():
+    V, T = wl.noise_heightfield(40, 5, 0.2)
+    V2, _ = wl.noise_heightfield(40, 6, 0.2)
+    rng = np.random.default_rng(2)
+    S, E = wl.segments_in_box(rng, [0, 0, -0.3], [1, 1, 0.3], 30_000)
+    m = _mesh(V, T)
+    m.refit(_t(V2))
+    a = _run(m, S, E, "bool|first|all", cap=4)
+    fresh = _mesh(V2, T)
+    b = _run(fresh, S, E, "bool|first|all", cap=4)
+    for k in ("hit", "tri", "t", "count", "ids", "ts"):
+        assert torch.equal(a[k], b[k]), k
+    # rebuild of the first handle with the second geometry: same again
+    m.rebuild(_t(V2), _t(T, torch.int32))
+    c = _run(m, S, E, "bool|first|all", cap=4)
+    for k in ("hit", "tri", "t", "count", "ids", "ts"):
+        assert torch.equal(c[k], b[k]), k
