@@ -59,9 +59,14 @@ enum {
 /* Build / query options; a zero field selects the default. */
 typedef struct {
     int32_t leaf_size;    /* max triangles per BVH leaf, 1..16 (default 1) */
-    int32_t block_size;   /* traversal workgroup size, multiple of 64 in 64..1024 (default 256) */
-    int32_t reserved0;
-    int32_t reserved1;
+    int32_t block_size;   /* traversal workgroup size: 64, 128, 192 or 256 (default 128) */
+    int32_t defer_lanes;  /* a wave tests its lanes' pending triangles once fewer than this many
+                             of its lanes can still visit a node, 1..64 (default 32) */
+    int32_t refill_lanes; /* a wave writes finished segments and takes new ones once this many
+                             of its lanes are done, 1..64 (default 32) */
+    int32_t chunk;        /* segments a wave claims per global atomic, 64..2^20
+                             (default: about eight chunks per resident wave, 64..4096) */
+    int32_t reserved[3];
 } rsi_opts;
 
 /* Output buffers of rsi_query (host struct of device pointers, each [n_r...]).
@@ -117,7 +122,8 @@ rsi_status rsi_refit(rsi_handle h, const float *V, void *stream);
  * RSI_ALL_HITS the call waits once on `stream` to size that pool; otherwise it
  * is asynchronous.  Reported t, u, v and P are re-solved in FP64 from the FP32
  * inputs; the crossing decisions are the FP32 test.
- * Errors: RSI_E_INVALID (n_r < 0, mode 0 or unknown bits, missing output
+ * n_r == 0 is a no-op (output pointers are then not inspected).
+ * Errors: RSI_E_INVALID (n_r < 0 or >= 2^30, mode 0 or unknown bits, missing output
  * pointer, capacity < 1), RSI_E_NOMEM, RSI_E_HIP. */
 rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
                      uint32_t mode, const rsi_outputs *out, void *stream);

@@ -102,13 +102,19 @@ rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
     if (n_t >= (int64_t(1) << rsi::kLeafFirstBits)) return invalid("rsi_build: n_t must be below 2^27");
     if (n_t > 0 && n_v == 0) return invalid("rsi_build: triangles given without vertices");
     if ((n_v > 0 && !V) || (n_t > 0 && !T)) return invalid("rsi_build: NULL pointer with nonzero size");
-    int leaf = 1, block = 256;
+    int leaf = 1, block = 128, defer = 32, refill = 32, chunk = 0;
     if (opts) {
         if (opts->leaf_size) leaf = opts->leaf_size;
         if (opts->block_size) block = opts->block_size;
+        if (opts->defer_lanes) defer = opts->defer_lanes;
+        if (opts->refill_lanes) refill = opts->refill_lanes;
+        if (opts->chunk) chunk = opts->chunk;
     }
+    if (chunk != 0 && (chunk < 64 || chunk > (1 << 20))) return invalid("rsi_build: chunk must be 0 or 64..2^20");
+    if (defer < 1 || defer > 64) return invalid("rsi_build: defer_lanes must be in 1..64");
+    if (refill < 1 || refill > 64) return invalid("rsi_build: refill_lanes must be in 1..64");
     if (leaf < 1 || leaf > rsi::kMaxLeafSize) return invalid("rsi_build: leaf_size must be in 1..16");
-    if (block < 64 || block > 1024 || block % 64) return invalid("rsi_build: block_size must be 64..1024, x64");
+    if (block < 64 || block > 256 || block % 64) return invalid("rsi_build: block_size must be 64, 128, 192 or 256");
 
     rsi_bvh *h = new (std::nothrow) rsi_bvh();
     if (!h) return invalid("rsi_build: host allocation failed");
@@ -117,6 +123,9 @@ rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
     h->n_t = n_t;
     h->leaf_size = leaf;
     h->block_size = block;
+    h->defer_lanes = defer;
+    h->refill_lanes = refill;
+    h->chunk = chunk;
     h->entry = n_t > 0 ? (int32_t)(n_t - 1) : 0;
     hipError_t e = hipGetDevice(&h->device);
     const int64_t n = n_t;
@@ -209,7 +218,8 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
     if (n_r < 0) return invalid("rsi_query: negative n_r");
     if (mode == 0 || (mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS)))
         return invalid("rsi_query: mode must be a nonzero mask of RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS");
-    if (n_r > 0 && (!S || !E)) return invalid("rsi_query: NULL segment pointer");
+    if (n_r == 0) return RSI_OK;  // nothing to read or write; output pointers may be NULL
+    if (!S || !E) return invalid("rsi_query: NULL segment pointer");
     if ((mode & RSI_BOOL) && !out->hit) return invalid("rsi_query: RSI_BOOL needs out->hit");
     if ((mode & RSI_FIRST_HIT) && (!out->tri || !out->t || !out->uv || !out->point))
         return invalid("rsi_query: RSI_FIRST_HIT needs out->tri, t, uv, point");
@@ -217,14 +227,13 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
         if (!out->count || !out->ids || !out->ts) return invalid("rsi_query: RSI_ALL_HITS needs out->count, ids, ts");
         if (out->capacity < 1) return invalid("rsi_query: capacity must be >= 1");
     }
-    if (n_r >= (int64_t(1) << 31)) return invalid("rsi_query: n_r must be below 2^31");
+    if (n_r >= (int64_t(1) << 30)) return invalid("rsi_query: n_r must be below 2^30");
     hipStream_t s = (hipStream_t)stream;
     rsi::QueryOut o = {out->hit, out->tri, out->t, out->uv, out->point, out->count, out->ids, out->ts,
                        out->capacity};
     h->last_ovf_segs = 0;
     h->last_ovf_total = 0;
     hipError_t e;
-    if (n_r == 0) return RSI_OK;
     if (h->n_t == 0) {
         e = rsi::launch_fill_miss(n_r, mode, o, s);
         return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_query");

@@ -1,22 +1,31 @@
 // query.hip -- segment queries against the linear BVH (paper Section 3.2,
 // the traversal and candidate testing, and Section 3.3, the query kernel).
 //
-// One lane per segment.  A lane walks the tree from the entry node with a
-// short stack kept in LDS (laid out [depth][lane] so a wave's pushes and pops
-// hit distinct banks).  Each step loads one 64-byte node, tests the segment
-// against both child boxes, runs the Moller-Trumbore test on the triangles of
-// any leaf child whose box it touches, then descends into the nearer internal
-// child that it touches and pushes the other.  The paper's bounded candidate
-// list with resume (Section 3.2) is not needed: candidates are tested as soon
-// as they are found, so the only bounded buffers left are the stack, sized
-// from the tree height at build time so it cannot overflow, and the per-
-// segment crossing slots of the all-hits mode, whose overflow is detected and
-// retried into a pool sized on the host.
+// Persistent wave64 kernel.  The grid holds as many workgroups as the GPU
+// keeps resident; every lane owns one segment at a time and, when it is done,
+// takes the next unprocessed segment from its wave's chunk; a wave claims a
+// new chunk of segments from a global counter with one atomic.  The paper's
+// kernel strides each thread over the rays instead (Section 3.3); with
+// segments whose traversal lengths vary by an order of magnitude, a wave that
+// waits for its slowest lane leaves most of its lanes idle, which the refill
+// avoids.
+//
+// A lane walks the tree from the entry node with a stack kept in LDS, laid
+// out [depth][lane] so a wave's pushes and pops hit distinct banks; the stack
+// is sized from the tree height, so it cannot overflow.  Each node step loads
+// one 64-byte node, tests the segment against both child boxes, remembers up
+// to two touched leaf children as pending, and descends into the nearer
+// touched internal child (pushing the other) or pops.  Pending leaves are
+// tested once few lanes can still take a node step, so the triangle test runs
+// with most lanes active.  The paper's bounded candidate list with resume
+// (Section 3.2) is therefore not needed: candidates are tested soon after
+// they are found, and the bounded buffers left are the stack and the
+// all-hits slots, whose overflow is detected and retried into a pool.
 //
 // Modes
 //   bool only   stop at the first crossing (any-hit, Section 3.2)
-//   first hit   keep the crossing with the smallest (t, id) and prune boxes
-//               that start beyond it
+//   first hit   keep the crossing with the smallest (t, id); boxes that start
+//               beyond it are pruned
 //   all hits    count every crossing, keep the first K found in slots; the
 //               epilogue re-solves them in FP64, orders them by (t, id), and
 //               appends segments with more than K crossings to an overflow
@@ -40,7 +49,7 @@ struct QArgs {
     int32_t entry;
     const float *S;
     const float *E;
-    int64_t n_r;
+    int64_t n_items;     // work items: segments, or overflow entries in the spill pass
     QueryOut o;
     // overflow list (all-hits)
     int32_t *ovf_seg;
@@ -48,13 +57,14 @@ struct QArgs {
     int64_t *ovf_off;
     int64_t ovf_cap;
     int32_t *scalars;
-    // spill pass
     int32_t *pool_ids;
     float *pool_ts;
-    int64_t n_items;  // spill: number of overflow entries
     Counters *counters;
     int32_t depth;       // stack entries per lane (tree height + 1)
-    int32_t max_steps;   // node visits never exceed the node count
+    int32_t max_steps;   // node visits of one segment never exceed the node count
+    int32_t defer;       // test pending leaves once fewer lanes than this can step
+    int32_t refill;      // fetch new segments once this many lanes are idle
+    int32_t chunk;       // work items a wave claims per atomic on the global counter
 };
 
 __device__ inline void wave_add_u64(unsigned long long *dst, unsigned long long v)
@@ -63,22 +73,28 @@ __device__ inline void wave_add_u64(unsigned long long *dst, unsigned long long 
     if (__lane_id() == 0) atomicAdd(dst, v);
 }
 
-// Per-lane traversal state for one segment.
+__device__ inline uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Per-lane query state for the segment it currently owns.
 struct Lane {
     Seg seg;
-    float tlim;     // MT / box limit on t: 1, or slightly above the best t (first hit)
+    float tlim;        // limit on t for boxes and triangles: 1, or just above the best t
     float best_t;
     int32_t best_id;
     int32_t best_pos;
-    int32_t count;  // crossings found (all hits)
-    int32_t spill_cap;  // pool entries reserved for this segment (spill pass)
+    int32_t count;     // crossings found (all hits)
+    int32_t spill_cap; // pool entries reserved for this segment (spill pass)
+    int64_t seg_i;     // segment index
+    int64_t slot_base; // first slot of this segment (all hits) or pool offset (spill)
     bool found;
-    uint32_t visits, boxes, tests;
 };
 
-// Process the triangles of one leaf; returns true when the lane may stop.
+// Test the triangles of one leaf; returns true when the lane may stop.
 template <uint32_t MODE, bool SPILL, bool COUNT>
-__device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, int64_t seg_i, int64_t slot_base)
+__device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t &tests)
 {
     const int32_t first = leaf_first(ref);
     const int32_t cnt = leaf_count(ref);
@@ -87,7 +103,7 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, int64_t 
         float v[9];
         int32_t id;
         tri_load(a.tris, pos, v, id);
-        if (COUNT) ++L.tests;
+        if (COUNT) ++tests;
         const float lim = (MODE & M_ALL) ? 1.0f : L.tlim;
         const MTHit h = mt_test(L.seg, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], lim);
         if (!h.hit) continue;
@@ -107,61 +123,13 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, int64_t 
             if (SPILL) {
                 // the spill pass repeats the first pass's decisions; the
                 // bound only keeps a mismatch from writing past the segment
-                if (c < L.spill_cap) a.pool_ids[slot_base + c] = pos;
+                if (c < L.spill_cap) a.pool_ids[L.slot_base + c] = pos;
             } else if (c < a.o.cap) {
-                a.o.ids[slot_base + c] = pos;
+                a.o.ids[L.slot_base + c] = pos;
             }
         }
     }
     return false;
-}
-
-// Stack traversal of one segment.
-template <uint32_t MODE, bool SPILL, bool COUNT>
-__device__ inline void traverse(const QArgs &a, Lane &L, int32_t *stk, int stride, int64_t seg_i,
-                                int64_t slot_base)
-{
-    int32_t node = a.entry;
-    int sp = 0;
-    // A traversal visits each node at most once and the stack never holds
-    // more than the tree height; both bounds are checked so that a damaged
-    // tree can only produce wrong answers, never a hang or a stray access.
-    for (int32_t step = 0; step < a.max_steps; ++step) {
-        const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
-        const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-        const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
-        const float lim = (MODE & M_ALL) ? 1.0f : L.tlim;
-        float tl, tr;
-        const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
-        const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
-        if (COUNT) {
-            ++L.visits;
-            L.boxes += 2;
-        }
-        const int32_t cl = q3.x, cr = q3.y;
-        if (hl && cl < 0) {
-            if (visit_leaf<MODE, SPILL, COUNT>(a, L, cl, seg_i, slot_base)) return;
-        }
-        if (hr && cr < 0) {
-            if (visit_leaf<MODE, SPILL, COUNT>(a, L, cr, seg_i, slot_base)) return;
-        }
-        const bool gl = hl && cl >= 0;
-        const bool gr = hr && cr >= 0;
-        if (gl && gr && sp < a.depth) {
-            const bool left_first = tl <= tr;
-            stk[sp * stride] = left_first ? cr : cl;
-            ++sp;
-            node = left_first ? cl : cr;
-        } else if (gl) {
-            node = cl;
-        } else if (gr) {
-            node = cr;
-        } else {
-            if (sp == 0) return;
-            --sp;
-            node = stk[sp * stride];
-        }
-    }
 }
 
 // Orders entries [0, n) of a (t, id) list in place by (t, id); insertion sort
@@ -197,121 +165,227 @@ __device__ inline void refine_list(const QArgs &a, double sx, double sy, double 
     }
 }
 
-template <uint32_t MODE, bool COUNT>
-__global__ __launch_bounds__(1024) void k_query(QArgs a)
+// Write the results of a finished segment.
+template <uint32_t MODE, bool SPILL>
+__device__ inline void finish(const QArgs &a, const Lane &L)
 {
-    extern __shared__ int32_t lds_stack[];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    Lane L;
-    L.visits = L.boxes = L.tests = 0;
-    if (i < a.n_r) {
-        const float sx = a.S[3 * i], sy = a.S[3 * i + 1], sz = a.S[3 * i + 2];
-        const float ex = a.E[3 * i], ey = a.E[3 * i + 1], ez = a.E[3 * i + 2];
-        L.seg = make_seg(sx, sy, sz, ex, ey, ez);
-        L.tlim = 1.0f;
-        L.best_t = INFINITY;
-        L.best_id = 0x7FFFFFFF;
-        L.best_pos = -1;
-        L.count = 0;
-        L.spill_cap = 0;
-        L.found = false;
-        const int64_t slot_base = (MODE & M_ALL) ? i * (int64_t)a.o.cap : 0;
-        traverse<MODE, false, COUNT>(a, L, lds_stack + threadIdx.x, blockDim.x, i, slot_base);
-
-        if (MODE & M_BOOL) a.o.hit[i] = L.found ? 1 : 0;
-        if (MODE & M_FIRST) {
-            if (L.best_pos >= 0) {
-                float v[9];
-                int32_t id;
-                tri_load(a.tris, L.best_pos, v, id);
-                double t, u, w;
-                mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-                a.o.tri[i] = id;
-                a.o.t[i] = (float)t;
-                a.o.uv[2 * i] = (float)u;
-                a.o.uv[2 * i + 1] = (float)w;
-                a.o.point[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
-                a.o.point[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
-                a.o.point[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
-            } else {
-                a.o.tri[i] = -1;
-                a.o.t[i] = INFINITY;
-                a.o.uv[2 * i] = 0.0f;
-                a.o.uv[2 * i + 1] = 0.0f;
-                a.o.point[3 * i] = 0.0f;
-                a.o.point[3 * i + 1] = 0.0f;
-                a.o.point[3 * i + 2] = 0.0f;
-            }
+    const int64_t i = L.seg_i;
+    const float sx = a.S[3 * i], sy = a.S[3 * i + 1], sz = a.S[3 * i + 2];
+    const float ex = a.E[3 * i], ey = a.E[3 * i + 1], ez = a.E[3 * i + 2];
+    if (SPILL) {
+        const int n = L.count < L.spill_cap ? L.count : L.spill_cap;
+        int32_t *ids = a.pool_ids + L.slot_base;
+        float *ts = a.pool_ts + L.slot_base;
+        refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n);
+        sort_slots(ids, ts, n);
+        const int K = a.o.cap;
+        int32_t *sid = a.o.ids + i * (int64_t)K;
+        float *sts = a.o.ts + i * (int64_t)K;
+        for (int c = 0; c < K; ++c) {
+            sid[c] = c < n ? ids[c] : -1;
+            sts[c] = c < n ? ts[c] : INFINITY;
         }
-        if (MODE & M_ALL) {
-            const int K = a.o.cap;
-            a.o.count[i] = L.count;
-            int32_t *ids = a.o.ids + slot_base;
-            float *ts = a.o.ts + slot_base;
-            const int n_in = L.count < K ? L.count : K;
-            if (L.count <= K) {
-                refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n_in);
-                sort_slots(ids, ts, n_in);
-            }
-            for (int c = n_in; c < K; ++c) {
-                ids[c] = -1;
-                ts[c] = INFINITY;
-            }
-            if (L.count > K) {
-                const int32_t e = atomicAdd(&a.scalars[kOvfSegs], 1);
-                const unsigned long long off =
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&a.scalars[kOvfTotalLo]),
-                              (unsigned long long)L.count);
-                if (e < a.ovf_cap) {
-                    a.ovf_seg[e] = (int32_t)i;
-                    a.ovf_cnt[e] = L.count;
-                    a.ovf_off[e] = (int64_t)off;
-                }
-            }
+        return;
+    }
+    if (MODE & M_BOOL) a.o.hit[i] = L.found ? 1 : 0;
+    if (MODE & M_FIRST) {
+        if (L.best_pos >= 0) {
+            float v[9];
+            int32_t id;
+            tri_load(a.tris, L.best_pos, v, id);
+            double t, u, w;
+            mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
+            a.o.tri[i] = id;
+            a.o.t[i] = (float)t;
+            a.o.uv[2 * i] = (float)u;
+            a.o.uv[2 * i + 1] = (float)w;
+            a.o.point[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
+            a.o.point[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
+            a.o.point[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
+        } else {
+            a.o.tri[i] = -1;
+            a.o.t[i] = INFINITY;
+            a.o.uv[2 * i] = 0.0f;
+            a.o.uv[2 * i + 1] = 0.0f;
+            a.o.point[3 * i] = 0.0f;
+            a.o.point[3 * i + 1] = 0.0f;
+            a.o.point[3 * i + 2] = 0.0f;
         }
     }
-    if (COUNT) {
-        wave_add_u64(&a.counters->node_visits, L.visits);
-        wave_add_u64(&a.counters->box_tests, L.boxes);
-        wave_add_u64(&a.counters->tri_tests, L.tests);
-        wave_add_u64(&a.counters->segments, i < a.n_r ? 1ull : 0ull);
+    if (MODE & M_ALL) {
+        const int K = a.o.cap;
+        a.o.count[i] = L.count;
+        int32_t *ids = a.o.ids + L.slot_base;
+        float *ts = a.o.ts + L.slot_base;
+        const int n_in = L.count < K ? L.count : K;
+        if (L.count <= K) {
+            refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n_in);
+            sort_slots(ids, ts, n_in);
+        }
+        for (int c = n_in; c < K; ++c) {
+            ids[c] = -1;
+            ts[c] = INFINITY;
+        }
+        if (L.count > K) {
+            const int32_t e = atomicAdd(&a.scalars[kOvfSegs], 1);
+            const unsigned long long off = atomicAdd(
+                reinterpret_cast<unsigned long long *>(&a.scalars[kOvfTotalLo]), (unsigned long long)L.count);
+            if (e < a.ovf_cap) {
+                a.ovf_seg[e] = (int32_t)i;
+                a.ovf_cnt[e] = L.count;
+                a.ovf_off[e] = (int64_t)off;
+            }
+        }
     }
 }
 
-// Spill pass: one lane per overflowed segment traverses again and writes all
-// of its crossings to the pool, then orders them and refreshes its K slots.
-template <uint32_t MODE>
-__global__ __launch_bounds__(1024) void k_spill(QArgs a)
+template <uint32_t MODE, bool SPILL, bool COUNT>
+__global__ __launch_bounds__(256) void k_query(QArgs a)
 {
     extern __shared__ int32_t lds_stack[];
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.n_items) return;
-    const int64_t i = a.ovf_seg[e];
-    const int64_t off = a.ovf_off[e];
-    const float sx = a.S[3 * i], sy = a.S[3 * i + 1], sz = a.S[3 * i + 2];
-    const float ex = a.E[3 * i], ey = a.E[3 * i + 1], ez = a.E[3 * i + 2];
+    int32_t *const stk = lds_stack + threadIdx.x;
+    const int stride = blockDim.x;
+    int32_t *const work = &a.scalars[kWorkNext];
+
     Lane L;
-    L.seg = make_seg(sx, sy, sz, ex, ey, ez);
-    L.tlim = 1.0f;
-    L.best_t = INFINITY;
-    L.best_id = 0x7FFFFFFF;
-    L.best_pos = -1;
-    L.count = 0;
-    L.spill_cap = a.ovf_cnt[e];
-    L.found = false;
-    L.visits = L.boxes = L.tests = 0;
-    traverse<M_ALL, true, false>(a, L, lds_stack + threadIdx.x, blockDim.x, i, off);
-    const int n = L.count < L.spill_cap ? L.count : L.spill_cap;
-    int32_t *ids = a.pool_ids + off;
-    float *ts = a.pool_ts + off;
-    refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n);
-    sort_slots(ids, ts, n);
-    const int K = a.o.cap;
-    int32_t *sid = a.o.ids + i * (int64_t)K;
-    float *sts = a.o.ts + i * (int64_t)K;
-    for (int c = 0; c < K; ++c) {
-        sid[c] = ids[c];
-        sts[c] = ts[c];
+    int64_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
+    int32_t node = -1;   // next node to visit; < 0: none
+    int32_t sp = 0;
+    int32_t leaf0 = 0, leaf1 = 0;  // pending leaf references (leaf refs are negative; 0 = none)
+    int32_t steps = 0;
+    uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
+    int64_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
+    bool exhausted = false;                 // the global counter has passed the last item
+
+    for (;;) {
+        // ---- lanes whose walk is over write their results and take a new
+        // work item, batched: only once `refill` lanes are waiting (or no
+        // lane can make progress), so the epilogue and the segment set-up run
+        // with many lanes at once.  Items come from the wave's chunk; a new
+        // chunk is claimed from the global counter with one atomic.
+        const bool done = item >= 0 && node < 0 && leaf0 == 0;
+        const uint64_t waiting = __ballot(done || item == -1);
+        if (waiting != 0 &&
+            ((int)__popcll(waiting) >= a.refill || __ballot(item >= 0 && !done) == 0)) {
+            if (done) {
+                finish<MODE, SPILL>(a, L);
+                item = -1;
+            }
+            const uint64_t idle = __ballot(item == -1);
+            const int64_t n_idle = (int64_t)__popcll(idle);
+            const int64_t rank = (int64_t)lanes_below(idle);
+            int64_t k = -1;
+            const int64_t avail = chunk_end - chunk_next;
+            const int64_t used = avail < n_idle ? avail : n_idle;
+            if (rank < used) k = chunk_next + rank;
+            chunk_next += used;
+            if (used < n_idle && !exhausted) {
+                const int leader = __builtin_ctzll(idle);
+                int32_t base = 0;
+                if ((int)__lane_id() == leader) base = atomicAdd(work, a.chunk);
+                base = __shfl(base, leader, 64);
+                if (base >= a.n_items) {
+                    exhausted = true;
+                } else {
+                    chunk_next = base;
+                    chunk_end = base + a.chunk < a.n_items ? base + a.chunk : a.n_items;
+                    const int64_t room = chunk_end - chunk_next;
+                    const int64_t more = n_idle - used < room ? n_idle - used : room;
+                    if (rank >= used && rank - used < more) k = chunk_next + (rank - used);
+                    chunk_next += more;
+                }
+            }
+            if (item == -1) {
+                if (k >= 0) {
+                    item = k;
+                    int64_t i = k;
+                    L.slot_base = (MODE & M_ALL) ? k * (int64_t)a.o.cap : 0;
+                    L.spill_cap = 0;
+                    if (SPILL) {
+                        i = a.ovf_seg[k];
+                        L.slot_base = a.ovf_off[k];
+                        L.spill_cap = a.ovf_cnt[k];
+                    }
+                    L.seg_i = i;
+                    L.seg = make_seg(a.S[3 * i], a.S[3 * i + 1], a.S[3 * i + 2], a.E[3 * i], a.E[3 * i + 1],
+                                     a.E[3 * i + 2]);
+                    L.tlim = 1.0f;
+                    L.best_t = INFINITY;
+                    L.best_id = 0x7FFFFFFF;
+                    L.best_pos = -1;
+                    L.count = 0;
+                    L.found = false;
+                    node = a.entry;
+                    sp = 0;
+                    steps = 0;
+                    if (COUNT) ++segs;
+                } else if (exhausted) {
+                    item = -2;
+                }
+            }
+        }
+        if (__ballot(item >= 0) == 0) break;
+
+        // ---- one node step for every lane that has a node and no pending leaf
+        const bool want = node >= 0 && leaf0 == 0;
+        const uint64_t w = __ballot(want);
+        if (want) {
+            const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
+            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+            const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
+            const float lim = (MODE & M_ALL) ? 1.0f : L.tlim;
+            float tl, tr;
+            const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
+            const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
+            if (COUNT) {
+                ++visits;
+                boxes += 2;
+            }
+            const int32_t cl = q3.x, cr = q3.y;
+            if (hl && cl < 0) leaf0 = cl;
+            if (hr && cr < 0) {
+                if (leaf0 == 0) leaf0 = cr;
+                else leaf1 = cr;
+            }
+            const bool gl = hl && cl >= 0;
+            const bool gr = hr && cr >= 0;
+            if (gl && gr && sp < a.depth) {
+                const bool left_first = tl <= tr;
+                stk[sp * stride] = left_first ? cr : cl;
+                ++sp;
+                node = left_first ? cl : cr;
+            } else if (gl) {
+                node = cl;
+            } else if (gr) {
+                node = cr;
+            } else if (sp > 0) {
+                --sp;
+                node = stk[sp * stride];
+            } else {
+                node = -1;
+            }
+            // bound on the walk: a damaged tree can give wrong answers, never a hang
+            if (++steps >= a.max_steps) node = -1;
+        }
+
+        // ---- test pending leaves once few lanes can still step
+        const uint64_t pend = __ballot(leaf0 != 0);
+        if (pend != 0 && (int)__popcll(w) < a.defer) {
+            if (leaf0 != 0) {
+                bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
+                if (!stop && leaf1 != 0) stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf1, tests);
+                if (stop) node = -1;
+                leaf0 = 0;
+                leaf1 = 0;
+            }
+        }
+
+    }
+    if (COUNT) {
+        wave_add_u64(&a.counters->node_visits, visits);
+        wave_add_u64(&a.counters->box_tests, boxes);
+        wave_add_u64(&a.counters->tri_tests, tests);
+        wave_add_u64(&a.counters->segments, segs);
     }
 }
 
@@ -335,23 +409,45 @@ __global__ void k_fill_miss(int64_t n_r, uint32_t mode, QueryOut o)
     }
 }
 
-__global__ void k_reset_ovf(int32_t *scalars)
+// Reset the work counter (and the overflow totals for a first all-hits pass)
+// with a kernel rather than a memset, so the sequence can be captured.
+__global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
 {
-    scalars[kOvfSegs] = 0;
-    scalars[kOvfTotalLo] = 0;
-    scalars[kOvfTotalHi] = 0;
+    scalars[kWorkNext] = 0;
+    if (reset_ovf) {
+        scalars[kOvfSegs] = 0;
+        scalars[kOvfTotalLo] = 0;
+        scalars[kOvfTotalHi] = 0;
+    }
+    if (c) c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
 }
 
-__global__ void k_zero_counters(Counters *c)
+template <uint32_t MODE, bool SPILL, bool COUNT>
+hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
-}
-
-template <uint32_t MODE, bool COUNT>
-void launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
-{
-    const unsigned grid = (unsigned)((a.n_r + block - 1) / block);
-    hipLaunchKernelGGL((k_query<MODE, COUNT>), dim3(grid), dim3(block), lds, s, a);
+    auto kern = k_query<MODE, SPILL, COUNT>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, n_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)per_cu * n_cu;
+    const int64_t need = (a.n_items + block - 1) / block;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    QArgs b = a;
+    if (b.chunk <= 0) {
+        // about eight chunks per resident wave keeps the tail short while the
+        // global counter sees one atomic per chunk
+        const int64_t waves = grid * (block / 64);
+        int64_t c = (a.n_items + 8 * waves - 1) / (8 * waves);
+        c = (c + 63) / 64 * 64;
+        b.chunk = (int32_t)(c < 64 ? 64 : (c > 4096 ? 4096 : c));
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, s, b);
+    return hipGetLastError();
 }
 
 template <bool COUNT>
@@ -359,27 +455,27 @@ hipError_t dispatch(uint32_t mode, const QArgs &a, int block, size_t lds, hipStr
 {
     // RSI_BOOL is derived for free whenever a full pass runs
     switch (mode) {
-    case M_BOOL: launch_mode<M_BOOL, COUNT>(a, block, lds, s); break;
-    case M_FIRST: launch_mode<M_FIRST, COUNT>(a, block, lds, s); break;
-    case M_FIRST | M_BOOL: launch_mode<M_FIRST | M_BOOL, COUNT>(a, block, lds, s); break;
-    case M_ALL: launch_mode<M_ALL, COUNT>(a, block, lds, s); break;
-    case M_ALL | M_BOOL: launch_mode<M_ALL | M_BOOL, COUNT>(a, block, lds, s); break;
-    case M_ALL | M_FIRST: launch_mode<M_ALL | M_FIRST, COUNT>(a, block, lds, s); break;
-    case M_ALL | M_FIRST | M_BOOL: launch_mode<M_ALL | M_FIRST | M_BOOL, COUNT>(a, block, lds, s); break;
+    case M_BOOL: return launch_mode<M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_FIRST: return launch_mode<M_FIRST, false, COUNT>(a, block, lds, s);
+    case M_FIRST | M_BOOL: return launch_mode<M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_ALL: return launch_mode<M_ALL, false, COUNT>(a, block, lds, s);
+    case M_ALL | M_BOOL: return launch_mode<M_ALL | M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_ALL | M_FIRST: return launch_mode<M_ALL | M_FIRST, false, COUNT>(a, block, lds, s);
+    case M_ALL | M_FIRST | M_BOOL: return launch_mode<M_ALL | M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-// Largest multiple of 64 not above `want` whose stack fits in 64 KiB of LDS.
+// Largest multiple of 64 not above `want` (and at most 256, the kernels'
+// launch bound) whose stack fits in 64 KiB of LDS.
 int fit_block(int want, int depth)
 {
-    int b = want;
+    int b = want < 256 ? want : 256;
     while (b > 64 && (size_t)b * depth * sizeof(int32_t) > 65536) b -= 64;
     return b;
 }
 
-QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_r, const QueryOut &o)
+QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, const QueryOut &o)
 {
     QArgs a;
     a.nodes = h->nodes;
@@ -387,7 +483,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_r, const Q
     a.entry = h->entry;
     a.S = S;
     a.E = E;
-    a.n_r = n_r;
+    a.n_items = n_items;
     a.o = o;
     a.ovf_seg = h->ovf_seg;
     a.ovf_cnt = h->ovf_cnt;
@@ -396,10 +492,12 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_r, const Q
     a.scalars = h->scalars;
     a.pool_ids = h->pool_ids;
     a.pool_ts = h->pool_ts;
-    a.n_items = 0;
     a.counters = h->counters;
     a.depth = h->height + 1;
     a.max_steps = (int32_t)(h->n_t + 1);
+    a.defer = h->defer_lanes;
+    a.refill = h->refill_lanes;
+    a.chunk = h->chunk;
     return a;
 }
 
@@ -413,11 +511,9 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
     const int block = fit_block(h->block_size, depth);
     const size_t lds = (size_t)block * depth * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n_r, o);
-    if (mode & M_ALL) hipLaunchKernelGGL(k_reset_ovf, dim3(1), dim3(1), 0, s, h->scalars);
-    if (h->counting) {
-        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, h->counters);
-        return dispatch<true>(mode, a, block, lds, s);
-    }
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, (mode & M_ALL) ? 1 : 0,
+                       h->counting ? h->counters : nullptr);
+    if (h->counting) return dispatch<true>(mode, a, block, lds, s);
     return dispatch<false>(mode, a, block, lds, s);
 }
 
@@ -430,11 +526,9 @@ hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mod
     const int depth = h->height + 1;
     const int block = fit_block(h->block_size, depth);
     const size_t lds = (size_t)block * depth * sizeof(int32_t);
-    QArgs a = make_args(h, S, E, 0, o);
-    a.n_items = n;
-    const unsigned grid = (unsigned)((n + block - 1) / block);
-    hipLaunchKernelGGL(k_spill<M_ALL>, dim3(grid), dim3(block), lds, s, a);
-    return hipGetLastError();
+    QArgs a = make_args(h, S, E, n, o);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
+    return launch_mode<M_ALL, true, false>(a, block, lds, s);
 }
 
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s)

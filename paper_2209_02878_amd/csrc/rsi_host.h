@@ -21,6 +21,7 @@ enum Scalar {
     kOvfSegs = 9,      // overflowed segments of the last all-hits pass
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments (lo, hi words)
     kOvfTotalHi = 11,
+    kWorkNext = 12,    // next unclaimed work item of the running query kernel
     kNumScalars = 16
 };
 
@@ -44,6 +45,9 @@ struct rsi_bvh {
     int64_t n_v = 0, n_t = 0;
     int32_t leaf_size = 1;
     int32_t block_size = 256;
+    int32_t defer_lanes = 32;
+    int32_t refill_lanes = 32;
+    int32_t chunk = 0;  // 0: sized per launch
     int32_t height = 0;
     int32_t root_ref = 0;
     int32_t entry = 0;

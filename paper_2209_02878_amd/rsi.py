@@ -37,7 +37,8 @@ class RsiError(RuntimeError):
 
 class rsi_opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("defer_lanes", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class rsi_outputs(ctypes.Structure):
@@ -127,11 +128,11 @@ def _dev_i32(x, name):
 
 # ------------------------------------------------------------ C functions --
 
-def rsi_build(V, T, leaf_size=0, block_size=0, stream=None):
+def rsi_build(V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0):
     V = _dev_f32(V, "V")
     T = _dev_i32(T, "T")
     h = ctypes.c_void_p()
-    o = rsi_opts(leaf_size, block_size, 0, 0)
+    o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk)
     _check(lib().rsi_build(_ptr(V), V.shape[0], _ptr(T), T.shape[0], ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))
     return h
@@ -219,11 +220,12 @@ def parse_mode(mode) -> int:
 class Mesh:
     """A BVH over a triangle mesh on the current HIP device."""
 
-    def __init__(self, V, T, leaf_size=0, block_size=0, stream=None):
+    def __init__(self, V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0,
+                 chunk=0):
         self.V = V
         self.T = T
         self.n_t = T.shape[0]
-        self.handle = rsi_build(V, T, leaf_size, block_size, stream)
+        self.handle = rsi_build(V, T, leaf_size, block_size, stream, defer_lanes, refill_lanes, chunk)
 
     def rebuild(self, V, T, stream=None):
         rsi_rebuild(self.handle, V, T, stream)

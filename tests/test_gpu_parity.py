@@ -208,6 +208,8 @@ def test_invalid_arguments():
         rsi.Mesh(V, _t(np.array([[0, 1, 3]], np.int32), torch.int32))
     with pytest.raises(rsi.RsiError):
         rsi.Mesh(V, _t(np.array([[0, 1, 2]], np.int32), torch.int32), leaf_size=17)
+    with pytest.raises(rsi.RsiError):
+        rsi.Mesh(V, _t(np.array([[0, 1, 2]], np.int32), torch.int32), block_size=512)
     m = rsi.Mesh(V, _t(np.array([[0, 1, 2]], np.int32), torch.int32))
     S = torch.zeros(4, 3, device=DEV)
     with pytest.raises(rsi.RsiError):
@@ -224,8 +226,10 @@ def test_ragged_sizes_and_options():
     rng = np.random.default_rng(8)
     S, E = wl.segments_in_box(rng, V.min(0), V.max(0), 12_347, scale=1.5)
     base = None
-    for leaf, block in [(1, 256), (2, 64), (8, 256), (16, 512), (3, 192)]:
-        mesh = _mesh(V, T, leaf_size=leaf, block_size=block)
+    for leaf, block, defer, refill, chunk in [(1, 256, 1, 1, 64), (2, 64, 8, 64, 100), (8, 256, 32, 16, 4096),
+                                              (16, 128, 64, 32, 256), (3, 192, 16, 8, 1 << 20)]:
+        mesh = _mesh(V, T, leaf_size=leaf, block_size=block, defer_lanes=defer, refill_lanes=refill,
+                     chunk=chunk)
         out = _run(mesh, S, E, "bool|first|all", cap=2)
         res = {k: v.cpu() for k, v in out.items() if k != "spill"}
         if base is None:
