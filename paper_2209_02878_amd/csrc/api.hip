@@ -44,7 +44,7 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_handle_memory(rsi_bvh *h)
 {
-    void *ptrs[] = {h->T, h->cent, h->keys, h->order, h->nodes, h->tris, h->arrive, h->heights,
+    void *ptrs[] = {h->T, h->cent, h->keys, h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb,
                     h->scalars, h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->pool_ids, h->pool_ts};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -137,6 +137,7 @@ rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
     if (e == hipSuccess) e = dalloc(&h->tris, n);
     if (e == hipSuccess) e = dalloc(&h->arrive, n);
     if (e == hipSuccess) e = dalloc(&h->heights, 2 * n);
+    if (e == hipSuccess) e = dalloc(&h->climb, 11 * n);
     if (e == hipSuccess) e = dalloc(&h->scalars, rsi::kNumScalars);
     if (e == hipSuccess) e = dalloc(&h->counters, 1);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);

@@ -8,14 +8,18 @@
 //   k_morton     quantise c_j to 2^21 levels per axis inside that interval
 //                and interleave the three 21-bit integers into a 63-bit key
 //   (sort.hip)   stable radix sort of (key, triangle id)
-//   k_lbvh       agglomerative single-pass construction over the sorted
+//   k_lbvh_*     agglomerative single-pass construction over the sorted
 //                keys (Apetrei's scheme, as the paper follows): every leaf
 //                climbs; at each step the node joins the neighbour across the
 //                split whose key distance is smaller, writes its box and
 //                reference into its parent, and the parent's arrival counter
 //                lets only the second child continue -- so the parent's box
 //                is formed exactly once, from both children.  Ranges with at
-//                most `leaf_size` triangles become leaves.
+//                most `leaf_size` triangles become leaves.  The climb runs in
+//                two passes: subtrees inside a block of 256 sorted leaves
+//                finish in LDS (k_lbvh_local), the few that cross block
+//                boundaries finish with device-scope counters
+//                (k_lbvh_global), so only those pay for cross-XCD ordering.
 //
 // The entry node is record n_t - 1 (unused by the n_t - 1 internal nodes
 // 0 .. n_t - 2): its left child is the root and its right child an empty far
@@ -140,93 +144,222 @@ __device__ inline void write_child(Node *__restrict__ p, int side, const float b
     p->ref[side] = ref;
 }
 
-__global__ __launch_bounds__(256) void k_lbvh(int32_t n, const uint64_t *__restrict__ keys,
-                                              const uint32_t *__restrict__ order, const float *__restrict__ V,
-                                              int64_t n_v, const int32_t *__restrict__ T, Node *__restrict__ nodes,
-                                              Tri *__restrict__ tris, int32_t *__restrict__ arrive,
-                                              int32_t *__restrict__ heights, int32_t leaf_size,
-                                              int32_t *__restrict__ scalars)
+// State of one climbing node: its box, leaf range [l, r], reference and
+// height (internal levels below it).
+struct Climb {
+    float box[6];
+    int32_t l, r, ref, h;
+};
+
+// The neighbour to join: across the split with the smaller key distance.
+// Returns the parent index (= that split position) and our side in it
+// (0: left child, 1: right child).
+__device__ inline int32_t choose_parent(const uint64_t *__restrict__ keys, int32_t n, int32_t l, int32_t r,
+                                        int &side)
 {
-    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
-
-    // leaf i: pack the triangle in sorted order and form its box
-    int32_t id = (int32_t)order[i];
-    if (id < 0 || id >= n) {  // cannot happen after a correct sort; never read outside T
-        atomicOr(&scalars[kBadIndex], 2);
-        id = 0;
+    if (l == 0 || (r != n - 1 && dist_less(keys, r, l - 1))) {
+        side = 0;
+        return r;
     }
-    int32_t a = T[3 * id], b = T[3 * id + 1], c = T[3 * id + 2];
-    // an out-of-range index is reported by k_centroids; read vertex 0 instead
-    // so that no access leaves the vertex array
-    if (a < 0 || a >= n_v) a = 0;
-    if (b < 0 || b >= n_v) b = 0;
-    if (c < 0 || c >= n_v) c = 0;
-    const float v0x = V[3 * a], v0y = V[3 * a + 1], v0z = V[3 * a + 2];
-    const float v1x = V[3 * b], v1y = V[3 * b + 1], v1z = V[3 * b + 2];
-    const float v2x = V[3 * c], v2y = V[3 * c + 1], v2z = V[3 * c + 2];
-    Tri tr;
-    tr.a = make_float4(v0x, v0y, v0z, v1x);
-    tr.b = make_float4(v1y, v1z, v2x, v2y);
-    tr.c = make_float4(v2z, __int_as_float(id), 0.0f, 0.0f);
-    tris[i] = tr;
+    side = 1;
+    return l - 1;
+}
 
-    float box[6] = {fminf(v0x, fminf(v1x, v2x)), fminf(v0y, fminf(v1y, v2y)), fminf(v0z, fminf(v1z, v2z)),
-                    fmaxf(v0x, fmaxf(v1x, v2x)), fmaxf(v0y, fmaxf(v1y, v2y)), fmaxf(v0z, fmaxf(v1z, v2z))};
-    int32_t l = i, r = i;
-    int32_t ref = leaf_ref(i, 1);
-    int32_t h = 0;
-
-    // every step strictly widens [l, r], so at most n - 1 steps are needed
-    for (int32_t step = 0; !(l == 0 && r == n - 1); ++step) {
-        if (step >= n || l < 0 || r > n - 1 || l > r) {  // inconsistent state: report, do not wander
-            atomicOr(&scalars[kBadIndex], 2);
-            return;
-        }
-        int32_t parent;
-        int side;  // 0: this node is the parent's left child, 1: right child
-        if (l == 0 || (r != n - 1 && dist_less(keys, r, l - 1))) {
-            parent = r;
-            side = 0;
-        } else {
-            parent = l - 1;
-            side = 1;
-        }
-        Node *p = nodes + parent;
-        write_child(p, side, box, ref);
-        p->aux[side] = side ? r : l;
-        heights[2 * parent + side] = h;
-        // release our writes / acquire the sibling's, at device scope: the
-        // eight XCDs have separate L2s, so both halves are needed
-        const int32_t prev =
-            __hip_atomic_fetch_add(&arrive[parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 0) return;  // the sibling finishes this parent
-        const int other = 1 - side;
-        if (side == 0) r = p->aux[1];
-        else l = p->aux[0];
-        const float *g = p->f + 6 * other;
+__device__ inline void merge(Climb &c, const float *g, int32_t other_bound, int32_t other_h, int side,
+                             int32_t parent, int32_t leaf_size)
+{
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            box[k] = fminf(box[k], g[k]);
-            box[3 + k] = fmaxf(box[3 + k], g[3 + k]);
-        }
-        const int32_t ho = heights[2 * parent + other];
-        h = 1 + (h > ho ? h : ho);
-        ref = (r - l + 1 <= leaf_size) ? leaf_ref(l, r - l + 1) : parent;
-        if (ref < 0) h = 0;  // a collapsed range is a leaf
+    for (int k = 0; k < 3; ++k) {
+        c.box[k] = fminf(c.box[k], g[k]);
+        c.box[3 + k] = fmaxf(c.box[3 + k], g[3 + k]);
     }
-    // only the thread that completed the root gets here (or the single leaf)
+    if (side == 0) c.r = other_bound;
+    else c.l = other_bound;
+    c.h = 1 + (c.h > other_h ? c.h : other_h);
+    c.ref = (c.r - c.l + 1 <= leaf_size) ? leaf_ref(c.l, c.r - c.l + 1) : parent;
+    if (c.ref < 0) c.h = 0;  // a collapsed range is a leaf
+}
+
+// Entry node n-1: the root as its left child (the paper keeps the root as the
+// left child of its last internal node record), an empty far box on the right.
+__device__ inline void write_entry(Node *__restrict__ nodes, int32_t n, const Climb &c, int32_t *scalars)
+{
     Node *e = nodes + (n - 1);
-    write_child(e, 0, box, ref);
+    write_child(e, 0, c.box, c.ref);
     const float far[6] = {FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX};
     write_child(e, 1, far, leaf_ref(0, 1));
     e->aux[0] = 0;
     e->aux[1] = n - 1;
-    scalars[kHeight] = h;
-    scalars[kRootRef] = ref;
+    scalars[kHeight] = c.h;
+    scalars[kRootRef] = c.ref;
+}
+
+constexpr int kLocal = 256;   // leaves per workgroup in the local pass
+constexpr int kClimbWords = 11;
+
+// Local pass: each workgroup owns kLocal consecutive sorted leaves.  A node
+// whose leaf range lies inside that block has its whole subtree inside it,
+// so these subtrees are completed here with the arrival counters and child
+// records in LDS.  A climb that reaches a split outside the block (its parent
+// range crosses the block boundary) is saved for the global pass.
+__global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ order,
+                                                       const float *__restrict__ V, int64_t n_v,
+                                                       const int32_t *__restrict__ T, Node *__restrict__ nodes,
+                                                       Tri *__restrict__ tris, int32_t *__restrict__ arrive,
+                                                       int32_t *__restrict__ heights, int32_t leaf_size,
+                                                       int32_t *__restrict__ scalars, int32_t *__restrict__ climb)
+{
+    __shared__ int32_t lflag[kLocal];
+    __shared__ float lbox[kLocal][12];
+    __shared__ int32_t lref[kLocal][2];
+    __shared__ int32_t lbound[kLocal][2];
+    __shared__ int32_t lh[kLocal][2];
+    const int tid = threadIdx.x;
+    const int32_t B0 = (int32_t)blockIdx.x * kLocal;
+    const int32_t B1 = (B0 + kLocal < n ? B0 + kLocal : n) - 1;  // last leaf of this block
+    lflag[tid] = 0;
+    __syncthreads();
+
+    const int32_t i = B0 + tid;
+    bool active = i < n;
+    Climb c;
+    if (active) {
+        // leaf i: pack the triangle in sorted order and form its box
+        int32_t id = (int32_t)order[i];
+        if (id < 0 || id >= n) {  // cannot happen after a correct sort; never read outside T
+            atomicOr(&scalars[kBadIndex], 2);
+            id = 0;
+        }
+        int32_t a = T[3 * id], b = T[3 * id + 1], d = T[3 * id + 2];
+        // an out-of-range index is reported by k_centroids; read vertex 0
+        // instead so that no access leaves the vertex array
+        if (a < 0 || a >= n_v) a = 0;
+        if (b < 0 || b >= n_v) b = 0;
+        if (d < 0 || d >= n_v) d = 0;
+        const float v0x = V[3 * a], v0y = V[3 * a + 1], v0z = V[3 * a + 2];
+        const float v1x = V[3 * b], v1y = V[3 * b + 1], v1z = V[3 * b + 2];
+        const float v2x = V[3 * d], v2y = V[3 * d + 1], v2z = V[3 * d + 2];
+        Tri tr;
+        tr.a = make_float4(v0x, v0y, v0z, v1x);
+        tr.b = make_float4(v1y, v1z, v2x, v2y);
+        tr.c = make_float4(v2z, __int_as_float(id), 0.0f, 0.0f);
+        tris[i] = tr;
+        c.box[0] = fminf(v0x, fminf(v1x, v2x));
+        c.box[1] = fminf(v0y, fminf(v1y, v2y));
+        c.box[2] = fminf(v0z, fminf(v1z, v2z));
+        c.box[3] = fmaxf(v0x, fmaxf(v1x, v2x));
+        c.box[4] = fmaxf(v0y, fmaxf(v1y, v2y));
+        c.box[5] = fmaxf(v0z, fmaxf(v1z, v2z));
+        c.l = c.r = i;
+        c.ref = leaf_ref(i, 1);
+        c.h = 0;
+        climb[kClimbWords * (int64_t)i] = 0;  // no saved climb for this leaf unless set below
+    }
+    // a climb inside the block takes fewer than kLocal steps
+    for (int step = 0; active; ++step) {
+        if (c.l == 0 && c.r == n - 1) {  // the whole tree fits in this block
+            write_entry(nodes, n, c, scalars);
+            break;
+        }
+        int side;
+        const int32_t parent = choose_parent(keys, n, c.l, c.r, side);
+        if (parent < B0 || parent >= B1 || step >= kLocal) {
+            // the parent's range crosses the block boundary: hand over
+            int32_t *st = climb + kClimbWords * (int64_t)i;
+            st[0] = 1;
+            st[1] = c.l;
+            st[2] = c.r;
+            st[3] = c.ref;
+            st[4] = c.h;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) st[5 + k] = __float_as_int(c.box[k]);
+            break;
+        }
+        const int slot = parent - B0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) lbox[slot][6 * side + k] = c.box[k];
+        lref[slot][side] = c.ref;
+        lbound[slot][side] = side ? c.r : c.l;
+        lh[slot][side] = c.h;
+        const int32_t prev =
+            __hip_atomic_fetch_add(&lflag[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (prev == 0) break;  // the sibling finishes this parent
+        const int other = 1 - side;
+        merge(c, &lbox[slot][6 * other], lbound[slot][other], lh[slot][other], side, parent, leaf_size);
+    }
+    __syncthreads();
+    // publish the block's internal node records (splits B0 .. B1-1)
+    if (tid < B1 - B0 && lflag[tid] > 0) {
+        const int32_t p = B0 + tid;
+        Node *q = nodes + p;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) q->f[k] = lbox[tid][k];
+        q->ref[0] = lref[tid][0];
+        q->ref[1] = lref[tid][1];
+        q->aux[0] = lbound[tid][0];
+        q->aux[1] = lbound[tid][1];
+        heights[2 * p] = lh[tid][0];
+        heights[2 * p + 1] = lh[tid][1];
+        arrive[p] = lflag[tid];
+    }
+}
+
+// Global pass: continue the climbs saved by the local pass.  Their parents
+// are shared between workgroups, so the arrival counter works at device
+// scope (the XCDs have separate L2 caches: release our writes, acquire the
+// sibling's).  Only the few subtrees that cross block boundaries remain.
+__global__ __launch_bounds__(256) void k_lbvh_global(int32_t n, const uint64_t *__restrict__ keys,
+                                                     Node *__restrict__ nodes, int32_t *__restrict__ arrive,
+                                                     int32_t *__restrict__ heights, int32_t leaf_size,
+                                                     int32_t *__restrict__ scalars,
+                                                     const int32_t *__restrict__ climb)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int32_t *st = climb + kClimbWords * (int64_t)i;
+    if (st[0] == 0) return;
+    Climb c;
+    c.l = st[1];
+    c.r = st[2];
+    c.ref = st[3];
+    c.h = st[4];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c.box[k] = __int_as_float(st[5 + k]);
+    // every step strictly widens [l, r], so at most n - 1 steps are needed
+    for (int32_t step = 0; !(c.l == 0 && c.r == n - 1); ++step) {
+        if (step >= n || c.l < 0 || c.r > n - 1 || c.l > c.r) {  // inconsistent: report, do not wander
+            atomicOr(&scalars[kBadIndex], 2);
+            return;
+        }
+        int side;
+        const int32_t parent = choose_parent(keys, n, c.l, c.r, side);
+        Node *p = nodes + parent;
+        write_child(p, side, c.box, c.ref);
+        p->aux[side] = side ? c.r : c.l;
+        heights[2 * parent + side] = c.h;
+        const int32_t prev =
+            __hip_atomic_fetch_add(&arrive[parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 0) return;  // the sibling finishes this parent
+        const int other = 1 - side;
+        merge(c, p->f + 6 * other, p->aux[other], heights[2 * parent + other], side, parent, leaf_size);
+    }
+    write_entry(nodes, n, c, scalars);
 }
 
 }  // namespace
+
+static hipError_t run_hierarchy(rsi_bvh *h, const float *V, hipStream_t s)
+{
+    const int32_t n = (int32_t)h->n_t;
+    const unsigned nb = (unsigned)((n + kLocal - 1) / kLocal);
+    hipLaunchKernelGGL(k_lbvh_local, dim3(nb), dim3(kLocal), 0, s, n, h->keys, h->order, V, h->n_v, h->T,
+                       h->nodes, h->tris, h->arrive, h->heights, h->leaf_size, h->scalars, h->climb);
+    if (nb > 1)
+        hipLaunchKernelGGL(k_lbvh_global, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, h->keys,
+                           h->nodes, h->arrive, h->heights, h->leaf_size, h->scalars, h->climb);
+    return hipGetLastError();
+}
 
 static hipError_t run_lbvh(rsi_bvh *h, const float *V, hipStream_t s)
 {
@@ -234,9 +367,7 @@ static hipError_t run_lbvh(rsi_bvh *h, const float *V, hipStream_t s)
     const int blk = 256;
     hipLaunchKernelGGL(k_init, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, s, h->scalars, h->arrive,
                        (int64_t)n);
-    hipLaunchKernelGGL(k_lbvh, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, s, n, h->keys, h->order, V,
-                       h->n_v, h->T, h->nodes, h->tris, h->arrive, h->heights, h->leaf_size, h->scalars);
-    return hipGetLastError();
+    return run_hierarchy(h, V, s);
 }
 
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
@@ -252,9 +383,7 @@ hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
     if (e != hipSuccess) return e;
     e = radix_sort_pairs(h->keys, h->order, n, 63, h->sort, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lbvh, dim3(grid), dim3(blk), 0, s, (int32_t)n, h->keys, h->order, V, h->n_v, h->T, h->nodes,
-                       h->tris, h->arrive, h->heights, h->leaf_size, h->scalars);
-    return hipGetLastError();
+    return run_hierarchy(h, V, s);
 }
 
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)

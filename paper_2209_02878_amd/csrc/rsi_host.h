@@ -62,6 +62,7 @@ struct rsi_bvh {
     rsi::Tri *tris = nullptr;      // [n_t] in sorted order
     int32_t *arrive = nullptr;     // arrival counters [n_t]
     int32_t *heights = nullptr;    // child heights [2*n_t]
+    int32_t *climb = nullptr;      // climbs handed from the local to the global build pass [11*n_t]
     int32_t *scalars = nullptr;    // rsi::Scalar
     rsi::Counters *counters = nullptr;
     rsi::SortScratch sort;

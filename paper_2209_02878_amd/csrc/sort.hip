@@ -6,7 +6,9 @@
 //   k_hist     per-tile digit histogram in LDS -> hist[digit][tile]
 //   k_scan     one workgroup turns hist into exclusive global offsets
 //              (digit-major, so the offset of (digit, tile) is the count of
-//              all smaller digits plus this digit in earlier tiles)
+//              all smaller digits plus this digit in earlier tiles); with at
+//              most 64 tiles every scatter workgroup derives its own offsets
+//              from the histograms instead and this launch is skipped
 //   k_scatter  per tile: stable rank of every element among equal digits
 //              via wave64 ballots, reorder the tile in LDS by digit, then
 //              write each digit run to its global offset (contiguous runs)
@@ -25,6 +27,7 @@ constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kFusedTiles = 64;  // up to this many tiles each workgroup scans the histograms itself
 
 __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                                                    uint32_t *__restrict__ hist, int ntiles)
@@ -78,6 +81,31 @@ __device__ inline uint64_t lanemask_lt()
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// Exclusive scan of 256 per-digit values held one per thread, done by the
+// first wave (four digits per lane).
+__device__ inline void scan256(const uint32_t *in, uint32_t *out)
+{
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        uint32_t c0 = in[4 * tid], c1 = in[4 * tid + 1], c2 = in[4 * tid + 2], c3 = in[4 * tid + 3];
+        uint32_t s4 = c0 + c1 + c2 + c3;
+        uint32_t incl = s4;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t v = __shfl_up(incl, off, 64);
+            if ((int)__lane_id() >= off) incl += v;
+        }
+        uint32_t ex = incl - s4;
+        out[4 * tid] = ex;
+        out[4 * tid + 1] = ex + c0;
+        out[4 * tid + 2] = ex + c0 + c1;
+        out[4 * tid + 3] = ex + c0 + c1 + c2;
+    }
+}
+
+// FUSED: `offs` holds the raw per-tile histograms and each workgroup forms
+// its own global digit offsets (used when there are few tiles, which saves
+// the separate scan launch); otherwise `offs` is the scanned table.
+template <bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -97,7 +125,22 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     run[tid] = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-    gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    if (FUSED) {
+        // digit tid: elements in earlier tiles and in all tiles
+        uint32_t before = 0, total = 0;
+        for (int b = 0; b < ntiles; ++b) {
+            const uint32_t c = offs[(int64_t)tid * ntiles + b];
+            before += b < (int)blockIdx.x ? c : 0u;
+            total += c;
+        }
+        start[tid] = total;
+        __syncthreads();
+        scan256(start, gbase);
+        __syncthreads();
+        gbase[tid] += before;
+    } else {
+        gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    }
     __syncthreads();
 
     uint64_t key[kItems];
@@ -140,20 +183,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     }
 
     // exclusive scan of the tile's per-digit counts (run[]) into start[]
-    if (tid < 64) {
-        uint32_t c0 = run[4 * tid], c1 = run[4 * tid + 1], c2 = run[4 * tid + 2], c3 = run[4 * tid + 3];
-        uint32_t s4 = c0 + c1 + c2 + c3;
-        uint32_t incl = s4;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t v = __shfl_up(incl, off, 64);
-            if ((int)__lane_id() >= off) incl += v;
-        }
-        uint32_t ex = incl - s4;
-        start[4 * tid] = ex;
-        start[4 * tid + 1] = ex + c0;
-        start[4 * tid + 2] = ex + c0 + c1;
-        start[4 * tid + 3] = ex + c0 + c1 + c2;
-    }
+    scan256(run, start);
     __syncthreads();
 
 #pragma unroll
@@ -236,9 +266,14 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, n, shift, sc.hist, ntiles);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, (int64_t)ntiles * kRadix);
-        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift, sc.hist,
-                           ntiles);
+        if (ntiles <= kFusedTiles) {
+            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift,
+                               sc.hist, ntiles);
+        } else {
+            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, (int64_t)ntiles * kRadix);
+            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift,
+                               sc.hist, ntiles);
+        }
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
