@@ -128,6 +128,29 @@ rsi_status rsi_refit(rsi_handle h, const float *V, void *stream);
 rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
                      uint32_t mode, const rsi_outputs *out, void *stream);
 
+/* Gradient of the first hit (t, u, v, P of RSI_FIRST_HIT) with respect to
+ * the vertices and both segment ends, by the adjoint of the crossing system
+ * S + t (E - S) = v0 + u (v1 - v0) + v (v2 - v0): the differentiable form of
+ * the paper's `barycentric` output (Section 2.4).
+ *   V        device float32 [n_v*3]: the vertices the handle was built or
+ *            refit with (read-only)
+ *   S, E     device float32 [n_r*3]: the segments of the forward query
+ *   tri      device int32 [n_r]: first-hit triangle ids from the forward
+ *            query (-1 = miss, contributes nothing)
+ *   g_t      device float32 [n_r]   upstream dL/dt      (NULL = zero)
+ *   g_uv     device float32 [n_r*2] upstream dL/d(u, v) (NULL = zero)
+ *   g_point  device float32 [n_r*3] upstream dL/dP      (NULL = zero)
+ *   dV       device float32 [n_v*3]: ACCUMULATED with atomic adds (the
+ *            caller zeroes it); summation order is not fixed, so the last
+ *            bits vary between runs
+ *   dS, dE   device float32 [n_r*3]: written (zero for misses); NULL skips
+ * (t, u, v) and the 3x3 transposed solve are evaluated in FP64 per segment.
+ * Asynchronous on `stream`.  Errors: RSI_E_INVALID (NULL pointers, n_r out
+ * of range), RSI_E_HIP. */
+rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,
+                                  const int32_t *tri, const float *g_t, const float *g_uv, const float *g_point,
+                                  float *dV, float *dS, float *dE, void *stream);
+
 /* After an RSI_ALL_HITS query: number of overflowed segments and total
  * crossings held in the spill pool (host out-parameters). */
 rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossings);

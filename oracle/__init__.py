@@ -11,7 +11,8 @@ Functions
   degenerate(V, T, S, E, delta, threads=0) -> uint8 flags per segment
       bit 1 edge within delta, bit 2 endpoint within delta of a triangle,
       bit 4 two crossings within delta of each other along the segment
-  first_hit_grad(V, T, S, E, tri, tuv, g_t, g_uv, g_p) -> dV, dS, dE (FP64)
+  first_hit_grad(V, T, S, E, tri, tuv, g_t, g_uv, g_p, with_abs) -> dV, dS, dE
+      (FP64; with_abs also returns the per-element sum of |contributions|)
   seg_seg_dist, pt_tri_dist: the distance routines the classifier uses
 """
 from __future__ import annotations
@@ -52,7 +53,7 @@ def _load():
     lib.rsi_oracle_query.restype = ctypes.c_int
     lib.rsi_oracle_degenerate.argtypes = [P, i64, P, i64, P, P, i64, ctypes.c_double, P, i32]
     lib.rsi_oracle_degenerate.restype = ctypes.c_int
-    lib.rsi_oracle_first_hit_grad.argtypes = [P, i64, P, i64, P, P, i64, P, P, P, P, P, P, P, P]
+    lib.rsi_oracle_first_hit_grad.argtypes = [P, i64, P, i64, P, P, i64, P, P, P, P, P, P, P, P, P]
     lib.rsi_oracle_first_hit_grad.restype = ctypes.c_int
     lib.rsi_oracle_seg_seg_dist.argtypes = [P, P, P, P]
     lib.rsi_oracle_seg_seg_dist.restype = ctypes.c_double
@@ -115,7 +116,7 @@ def degenerate(V, T, S, E, delta: float, threads: int = 0) -> np.ndarray:
     return flags
 
 
-def first_hit_grad(V, T, S, E, tri, tuv, g_t=None, g_uv=None, g_p=None):
+def first_hit_grad(V, T, S, E, tri, tuv, g_t=None, g_uv=None, g_p=None, with_abs=False):
     lib = _load()
     V, T, S, E = _mesh_args(V, T, S, E)
     nr = S.shape[0]
@@ -127,11 +128,14 @@ def first_hit_grad(V, T, S, E, tri, tuv, g_t=None, g_uv=None, g_p=None):
     dV = np.zeros((V.shape[0], 3), np.float64)
     dS = np.zeros((nr, 3), np.float64)
     dE = np.zeros((nr, 3), np.float64)
+    dV_abs = np.zeros((V.shape[0], 3), np.float64) if with_abs else None
     rc = lib.rsi_oracle_first_hit_grad(_p(V), V.shape[0], _p(T), T.shape[0], _p(S), _p(E), nr,
                                        _p(tri), _p(tuv), _p(g_t), _p(g_uv), _p(g_p),
-                                       _p(dV), _p(dS), _p(dE))
+                                       _p(dV), _p(dS), _p(dE), _p(dV_abs))
     if rc != 0:
         raise ValueError("triangle index out of range")
+    if with_abs:
+        return dV, dS, dE, dV_abs
     return dV, dS, dE
 
 

@@ -415,7 +415,8 @@ static int solve3_transpose(dv3 c0, dv3 c1, dv3 c2, dv3 g, dv3 *y)
  * First-hit adjoint.  For each segment i with first hit on triangle
  * tri[i] (-1: miss, contributes nothing), given upstream gradients
  *   g_t [nr], g_uv [nr*2], g_p [nr*3]  (each nullable = zero),
- * accumulates dL/dV into dV [nv*3] and writes dL/dS, dL/dE [nr*3].
+ * accumulates dL/dV into dV [nv*3] and writes dL/dS, dL/dE [nr*3]; dV_abs
+ * (nullable) accumulates the absolute value of every contribution.
  * The hit solves M x = S - v0, M = [-d | e1 | e2], x = (t, u, v),
  * d = E - S, e1 = v1 - v0, e2 = v2 - v0, and P = S + t d.
  * With tbar the gradient on t after folding P in (tbar += Pbar.d) and
@@ -429,7 +430,7 @@ int rsi_oracle_first_hit_grad(const double *V, int64_t nv, const int32_t *T, int
                               const double *S, const double *E, int64_t nr,
                               const int32_t *tri, const double *tuv,
                               const double *g_t, const double *g_uv, const double *g_p,
-                              double *dV, double *dS, double *dE)
+                              double *dV, double *dS, double *dE, double *dV_abs)
 {
     if (check_indices(T, nt, nv)) return -1;
     for (int64_t i = 0; i < nr; ++i) {
@@ -467,6 +468,11 @@ int rsi_oracle_first_hit_grad(const double *V, int64_t nv, const int32_t *T, int
                 dV[3 * a] += v0bar.x; dV[3 * a + 1] += v0bar.y; dV[3 * a + 2] += v0bar.z;
                 dV[3 * b] += v1bar.x; dV[3 * b + 1] += v1bar.y; dV[3 * b + 2] += v1bar.z;
                 dV[3 * c] += v2bar.x; dV[3 * c + 1] += v2bar.y; dV[3 * c + 2] += v2bar.z;
+                if (dV_abs) {  /* sum of |contribution| per element: the scale of its rounding */
+                    dV_abs[3 * a] += fabs(v0bar.x); dV_abs[3 * a + 1] += fabs(v0bar.y); dV_abs[3 * a + 2] += fabs(v0bar.z);
+                    dV_abs[3 * b] += fabs(v1bar.x); dV_abs[3 * b + 1] += fabs(v1bar.y); dV_abs[3 * b + 2] += fabs(v1bar.z);
+                    dV_abs[3 * c] += fabs(v2bar.x); dV_abs[3 * c + 1] += fabs(v2bar.y); dV_abs[3 * c + 2] += fabs(v2bar.z);
+                }
             }
             /* d = E - S */
             ge = dbar;

@@ -265,6 +265,22 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
     return RSI_OK;
 }
 
+rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,
+                                  const int32_t *tri, const float *g_t, const float *g_uv, const float *g_point,
+                                  float *dV, float *dS, float *dE, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_first_hit_backward: NULL handle");
+    if (n_r < 0 || n_r >= (int64_t(1) << 30)) return invalid("rsi_first_hit_backward: n_r must be in [0, 2^30)");
+    if (n_r == 0) return RSI_OK;
+    if (!S || !E || !tri) return invalid("rsi_first_hit_backward: NULL S, E or tri");
+    if (h->n_t > 0 && (!V || !dV)) return invalid("rsi_first_hit_backward: NULL V or dV");
+    hipError_t e = rsi::launch_first_hit_adjoint(h, V, S, E, n_r, tri, g_t, g_uv, g_point, dV, dS, dE,
+                                                 (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rsi_first_hit_backward");
+    return RSI_OK;
+}
+
 rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossings)
 {
     set_error("");

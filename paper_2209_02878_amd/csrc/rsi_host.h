@@ -112,4 +112,9 @@ hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mod
                         hipStream_t s);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);
 
+// adjoint.hip
+hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, const float *E, int64_t n_r,
+                                    const int32_t *tri, const float *g_t, const float *g_uv, const float *g_p,
+                                    float *dV, float *dS, float *dE, hipStream_t s);
+
 }  // namespace rsi

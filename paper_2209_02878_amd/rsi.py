@@ -23,7 +23,8 @@ RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS = 1, 2, 4
 MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS}
 
 EXPORTED = [
-    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_spill_info", "rsi_spill_read",
+    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_first_hit_backward",
+    "rsi_spill_info", "rsi_spill_read",
     "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_export_tree",
     "rsi_destroy", "rsi_status_str", "rsi_last_error",
 ]
@@ -76,6 +77,7 @@ def lib():
     L.rsi_rebuild.argtypes = [H, P, i64, P, P]
     L.rsi_refit.argtypes = [H, P, P]
     L.rsi_query.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
+    L.rsi_first_hit_backward.argtypes = [H, P, P, P, i64, P, P, P, P, P, P, P, P]
     L.rsi_spill_info.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.rsi_spill_read.argtypes = [H, P, P, P, P, P, P]
     L.rsi_set_counting.argtypes = [H, ctypes.c_int]
@@ -155,6 +157,29 @@ def rsi_query(h, S, E, mode, out: rsi_outputs, stream=None):
     if S.shape != E.shape:
         raise ValueError("S and E must have the same shape")
     _check(lib().rsi_query(h, _ptr(S), _ptr(E), S.shape[0], mode, ctypes.byref(out), _stream(stream)))
+
+
+def rsi_first_hit_backward(h, V, S, E, tri, g_t=None, g_uv=None, g_point=None, dV=None, dS=None, dE=None,
+                           stream=None):
+    """dV is accumulated (pass zeros); dS / dE are written.  Returns (dV, dS, dE)."""
+    V = _dev_f32(V, "V")
+    S = _dev_f32(S, "S")
+    E = _dev_f32(E, "E")
+    n = S.shape[0]
+    if tri.dtype != torch.int32 or not tri.is_contiguous() or tri.numel() != n:
+        raise TypeError("tri must be a contiguous int32 [n] tensor")
+    for name, g, c in (("g_t", g_t, 1), ("g_uv", g_uv, 2), ("g_point", g_point, 3)):
+        if g is not None and (g.dtype != torch.float32 or not g.is_contiguous() or g.numel() != c * n):
+            raise TypeError(f"{name} must be a contiguous float32 tensor with {c} values per segment")
+    if dV is None:
+        dV = torch.zeros_like(V)
+    if dS is None:
+        dS = torch.empty_like(S)
+    if dE is None:
+        dE = torch.empty_like(E)
+    _check(lib().rsi_first_hit_backward(h, _ptr(V), _ptr(S), _ptr(E), n, _ptr(tri), _ptr(g_t), _ptr(g_uv),
+                                        _ptr(g_point), _ptr(dV), _ptr(dS), _ptr(dE), _stream(stream)))
+    return dV, dS, dE
 
 
 def rsi_spill_info(h):
@@ -277,6 +302,9 @@ class Mesh:
                 out["spill"] = sp
         return out
 
+    def first_hit_backward(self, V, S, E, tri, g_t=None, g_uv=None, g_point=None, stream=None):
+        return rsi_first_hit_backward(self.handle, V, S, E, tri, g_t, g_uv, g_point, stream=stream)
+
     def set_counting(self, enable=True):
         rsi_set_counting(self.handle, enable)
 
@@ -299,3 +327,38 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+
+class FirstHit(torch.autograd.Function):
+    """Differentiable first hit of segments (S, E) against a mesh with
+    learnable vertices V (the topology T is fixed by `mesh`).
+
+    forward(V, S, E, mesh) -> (t [n], uv [n, 2], point [n, 3], tri [n])
+    The forward refits `mesh` to V (bounds only, same tree topology) and runs
+    the first-hit query; the backward runs the library's adjoint kernel and
+    returns dL/dV, dL/dS, dL/dE (tri is not differentiable).
+    """
+
+    @staticmethod
+    def forward(ctx, V, S, E, mesh):
+        V = V.detach().contiguous()
+        S = S.detach().contiguous()
+        E = E.detach().contiguous()
+        mesh.refit(V)
+        out = mesh.query(S, E, "first")
+        ctx.mesh = mesh
+        ctx.save_for_backward(V, S, E, out["tri"])
+        ctx.mark_non_differentiable(out["tri"])
+        return out["t"], out["uv"], out["point"], out["tri"]
+
+    @staticmethod
+    def backward(ctx, g_t, g_uv, g_point, g_tri):
+        V, S, E, tri = ctx.saved_tensors
+        f = lambda g: None if g is None else g.contiguous().to(torch.float32)
+        dV, dS, dE = rsi_first_hit_backward(ctx.mesh.handle, V, S, E, tri, f(g_t), f(g_uv), f(g_point))
+        return dV, dS, dE, None
+
+
+def first_hit(V, S, E, mesh):
+    """Convenience wrapper of FirstHit.apply."""
+    return FirstHit.apply(V, S, E, mesh)

@@ -1,0 +1,193 @@
+"""GPU adjoint of the first hit (differentiable form of the paper's
+`barycentric` output, Section 2.4) against the FP64 oracle gradient and
+FP64 central finite differences.
+
+Tolerances: dS and dE per segment within 1e-5 relative (plus a 1e-7 floor of
+the largest magnitude); dV per element within 1e-5 of the sum of absolute
+contributions to that element (FP32 atomic accumulation cancels across
+segments), and within 1e-5 relative in 2-norm over the whole vector.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2209_02878_amd import rsi
+from paper_2209_02878_amd import workloads as wl
+import oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+def _check_dv(dv_gpu, dv_ref, dv_abs, rel=1e-5):
+    err = np.abs(dv_gpu - dv_ref)
+    bad = err > rel * dv_abs + 1e-30
+    assert not bad.any(), f"{bad.sum()} dV elements off; worst ratio {np.max(err / (dv_abs + 1e-30)):.3g}"
+    norm = np.linalg.norm(dv_gpu - dv_ref) / np.linalg.norm(dv_ref)
+    assert norm <= rel, norm
+
+
+def _check_seg(g_gpu, g_ref, rel=1e-5):
+    floor = 1e-7 * np.abs(g_ref).max()
+    bad = np.abs(g_gpu - g_ref) > rel * np.abs(g_ref) + floor
+    assert not bad.any(), f"{bad.sum()} per-segment gradient values off"
+
+
+def test_adjoint_matches_oracle_random_upstream():
+    V, T = wl.noise_heightfield(60, 17, 0.2)
+    rng = np.random.default_rng(3)
+    S1, E1 = wl.segments_near_vertical(rng, 30_000)
+    S2, E2 = wl.segments_random_dir(rng, V.min(0), V.max(0), 30_000)
+    S = np.concatenate([S1, S2])
+    E = np.concatenate([E1, E2])
+    mesh = rsi.Mesh(_t(V), _t(T, torch.int32))
+    out = mesh.query(_t(S), _t(E), "first")
+    ref = parity.oracle_reference(V, T, S, E)
+    tri = out["tri"].cpu().numpy()
+    ok = (ref["degenerate"] == 0) & (tri == ref["first_tri"]) & (tri >= 0)
+    assert ok.sum() > 30_000
+    n = S.shape[0]
+    g_t = (rng.standard_normal(n) * ok).astype(np.float32)
+    g_uv = (rng.standard_normal((n, 2)) * ok[:, None]).astype(np.float32)
+    g_p = (rng.standard_normal((n, 3)) * ok[:, None]).astype(np.float32)
+    tri_in = np.where(ok, tri, -1).astype(np.int32)
+    dV, dS, dE = mesh.first_hit_backward(_t(V), _t(S), _t(E), _t(tri_in, torch.int32), _t(g_t), _t(g_uv),
+                                         _t(g_p))
+    torch.cuda.synchronize()
+    rV, rS, rE, rabs = oracle.first_hit_grad(V, T, S, E, tri_in, ref["first_tuv"], g_t, g_uv, g_p,
+                                             with_abs=True)
+    _check_dv(dV.cpu().numpy().astype(np.float64), rV, rabs)
+    _check_seg(dS.cpu().numpy()[ok].astype(np.float64), rS[ok])
+    _check_seg(dE.cpu().numpy()[ok].astype(np.float64), rE[ok])
+    assert not dS.cpu().numpy()[~ok].any() and not dE.cpu().numpy()[~ok].any()
+
+
+def test_autograd_function_matches_direct_call():
+    V, T = wl.noise_heightfield(40, 5, 0.2)
+    rng = np.random.default_rng(9)
+    S, E = wl.segments_near_vertical(rng, 20_000)
+    Vt = _t(V).requires_grad_(True)
+    St = _t(S).requires_grad_(True)
+    Et = _t(E).requires_grad_(True)
+    mesh = rsi.Mesh(_t(V), _t(T, torch.int32))
+    t, uv, P, tri = rsi.FirstHit.apply(Vt, St, Et, mesh)
+    loss = (P[:, 2] ** 2).sum() + t.sum() + uv.sum()
+    loss.backward()
+    g_p = torch.zeros_like(P)
+    g_p[:, 2] = 2 * P[:, 2].detach()
+    dV, dS, dE = mesh.first_hit_backward(_t(V), _t(S), _t(E), tri, torch.ones_like(t), torch.ones_like(uv), g_p)
+    scale = dV.abs().max()
+    assert torch.allclose(Vt.grad, dV, atol=1e-6 * float(scale), rtol=1e-5)
+    assert torch.allclose(St.grad, dS) and torch.allclose(Et.grad, dE)
+
+
+def test_c4_fwd_bwd_against_oracle_and_finite_differences():
+    """Differentiable first hit on the 317 x 317 heightfield (199,712
+    triangles) with 4M near-vertical segments and loss
+    L = sum (P_z - g(x_S, y_S))^2 for a second seeded surface g.  The check
+    set is a seeded 100k sample plus every segment that can hit a triangle
+    around one of 64 sampled interior vertices; the loss is masked to it."""
+    n = 317
+    w = wl.config4()
+    Vg, _ = wl.config4_target(n)
+    V, T, S, E = w.V, w.T, w.S, w.E
+    gz = Vg[:, 2].astype(np.float64)
+
+    # g(x, y): bilinear interpolation of the target grid's vertex heights
+    def target_at(x, y):
+        X = np.clip(x * (n - 1), 0, n - 1 - 1e-9)
+        Y = np.clip(y * (n - 1), 0, n - 1 - 1e-9)
+        i = X.astype(np.int64)
+        j = Y.astype(np.int64)
+        a, b = X - i, Y - j
+        k = j * n + i
+        return (gz[k] * (1 - a) * (1 - b) + gz[k + 1] * a * (1 - b) + gz[k + n] * (1 - a) * b
+                + gz[k + n + 1] * a * b)
+    target = target_at(S[:, 0].astype(np.float64), S[:, 1].astype(np.float64)).astype(np.float32)
+
+    rng = np.random.default_rng(wl.seed_for(4, 3))
+    # 64 interior vertices and the segments whose xy box meets their 1-ring box
+    vi = rng.integers(2, n - 2, size=(64, 2))
+    fd_vertices = vi[:, 1] * n + vi[:, 0]
+    ring_lo = np.stack([(vi[:, 0] - 1) / (n - 1), (vi[:, 1] - 1) / (n - 1)], 1)
+    ring_hi = np.stack([(vi[:, 0] + 1) / (n - 1), (vi[:, 1] + 1) / (n - 1)], 1)
+    seg_lo = np.minimum(S[:, :2], E[:, :2])
+    seg_hi = np.maximum(S[:, :2], E[:, :2])
+    near = np.zeros(S.shape[0], bool)
+    for k in range(64):
+        near |= np.all((seg_hi >= ring_lo[k]) & (seg_lo <= ring_hi[k]), axis=1)
+    chk = np.union1d(wl.subset(S.shape[0], 100_000, wl.seed_for(4, 3)), np.nonzero(near)[0])
+
+    # GPU forward + backward with the loss masked to the check set
+    mesh = rsi.Mesh(_t(V), _t(T, torch.int32))
+    Vt = _t(V)
+    St, Et = _t(S), _t(E)
+    t, uv, P, tri = rsi.FirstHit.apply(Vt, St, Et, mesh)
+    mask = torch.zeros(S.shape[0], dtype=torch.float32, device=DEV)
+    mask[_t(chk, torch.int64)] = 1.0
+    resid = P[:, 2] - _t(target)
+    g_p = torch.zeros_like(P)
+    g_p[:, 2] = 2 * resid * mask
+    dV, dS, dE = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_p.contiguous())
+    torch.cuda.synchronize()
+
+    # oracle on the check set
+    Sc, Ec = S[chk], E[chk]
+    ref = parity.oracle_reference(V, T, Sc, Ec)
+    tri_c = tri.cpu().numpy()[chk]
+    ok = (ref["degenerate"] == 0) & (ref["first_tri"] == tri_c)
+    assert ok.mean() > 0.999 and np.all(ref["count"][ok] == 1)
+    gp_ref = np.zeros((chk.size, 3))
+    gp_ref[:, 2] = 2 * (ref["first_p"][:, 2] - target[chk])
+    gp_ref[~ok] = 0.0
+    rV, rS, rE, rabs = oracle.first_hit_grad(V, T, Sc, Ec, np.where(ok, tri_c, -1), ref["first_tuv"],
+                                             g_p=gp_ref, with_abs=True)
+    # the GPU's masked loss must skip the same (degenerate) segments
+    drop = chk[~ok]
+    if drop.size:
+        g_p2 = g_p.clone()
+        g_p2[_t(drop, torch.int64)] = 0
+        dV, dS, dE = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_p2.contiguous())
+    dVn = dV.cpu().numpy().astype(np.float64)
+    _check_dv(dVn, rV, rabs)
+    _check_seg(dS.cpu().numpy()[chk][ok].astype(np.float64), rS[ok])
+    _check_seg(dE.cpu().numpy()[chk][ok].astype(np.float64), rE[ok])
+
+    # central differences (FP64, h = 1e-4) of the masked loss in each sampled
+    # vertex's z, over the check segments that stay clear of every edge
+    u, v = ref["first_tuv"][:, 1], ref["first_tuv"][:, 2]
+    clear = ok & (np.minimum(np.minimum(u, v), 1 - u - v) > 1e-3)
+    V64 = V.astype(np.float64)
+    h = 1e-4
+    n_checked = 0
+    for k in fd_vertices:
+        inc = np.any(T[np.where(clear, tri_c, 0)] == k, axis=1) & clear
+        if not inc.any():
+            continue
+        # the GPU gradient of the loss restricted to `clear` segments
+        sel = chk[inc]
+        g_k = torch.zeros_like(P)
+        g_k[_t(sel, torch.int64), 2] = 2 * resid[_t(sel, torch.int64)]
+        dVk, _, _ = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_k.contiguous())
+        gpu = float(dVk[int(k), 2])
+        losses = []
+        for sgn in (1, -1):
+            Vp = V64.copy()
+            Vp[k, 2] += sgn * h
+            r = oracle.query(Vp, T, Sc[inc], Ec[inc])
+            assert np.array_equal(r["first_tri"], tri_c[inc])
+            losses.append(np.sum((r["first_p"][:, 2] - target[sel].astype(np.float64)) ** 2))
+        fd = (losses[0] - losses[1]) / (2 * h)
+        gp_k = np.zeros((chk.size, 3))
+        gp_k[inc, 2] = 2 * (ref["first_p"][inc, 2] - target[sel])
+        _, _, _, abs_k = oracle.first_hit_grad(V, T, Sc, Ec, np.where(inc, tri_c, -1), ref["first_tuv"],
+                                               g_p=gp_k, with_abs=True)
+        assert abs(gpu - fd) <= 1e-5 * abs_k[k, 2] + 1e-9, (int(k), gpu, fd, abs_k[k, 2])
+        n_checked += 1
+    assert n_checked >= 60

@@ -27,7 +27,8 @@ def test_vertical_hit_height_gradient_is_barycentric():
     assert np.all(r["count"] == 1)
     g_p = np.zeros((m, 3))
     g_p[:, 2] = 1.0
-    dV, dS, dE = oracle.first_hit_grad(V, T, S, E, r["first_tri"], r["first_tuv"], g_p=g_p)
+    dV, dS, dE, dV_abs = oracle.first_hit_grad(V, T, S, E, r["first_tri"], r["first_tuv"], g_p=g_p,
+                                               with_abs=True)
     # expected: scatter the barycentric weights (1-u-v, u, v) into z
     t, u, v = r["first_tuv"].T
     want = np.zeros(V.shape[0])
@@ -36,6 +37,8 @@ def test_vertical_hit_height_gradient_is_barycentric():
     np.add.at(want, tri[:, 1], u)
     np.add.at(want, tri[:, 2], v)
     np.testing.assert_allclose(dV[:, 2], want, atol=1e-12)
+    # every contribution to a z component is a nonnegative weight here
+    np.testing.assert_allclose(dV_abs[:, 2], want, atol=1e-12)
     np.testing.assert_allclose(dS[:, 2], 0.0, atol=1e-12)
     np.testing.assert_allclose(dE[:, 2], 0.0, atol=1e-12)
 
