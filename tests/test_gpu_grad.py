@@ -141,23 +141,37 @@ def test_c4_fwd_bwd_against_oracle_and_finite_differences():
     Sc, Ec = S[chk], E[chk]
     ref = parity.oracle_reference(V, T, Sc, Ec)
     tri_c = tri.cpu().numpy()[chk]
-    ok = (ref["degenerate"] == 0) & (ref["first_tri"] == tri_c)
-    assert ok.mean() > 0.999 and np.all(ref["count"][ok] == 1)
-    gp_ref = np.zeros((chk.size, 3))
-    gp_ref[:, 2] = 2 * (ref["first_p"][:, 2] - target[chk])
-    gp_ref[~ok] = 0.0
-    rV, rS, rE, rabs = oracle.first_hit_grad(V, T, Sc, Ec, np.where(ok, tri_c, -1), ref["first_tuv"],
-                                             g_p=gp_ref, with_abs=True)
+    clean = ref["degenerate"] == 0
+    # on the regular grid about 3 edge lines per cell width lie within the
+    # 1e-6 * L band, so a few tenths of a percent are near-degenerate
+    assert clean.mean() > 0.99
+    assert int((clean & (ref["first_tri"] != tri_c)).sum()) == 0
+    ok = clean
+    assert np.all(ref["count"][ok] == 1)
     # the GPU's masked loss must skip the same (degenerate) segments
     drop = chk[~ok]
     if drop.size:
-        g_p2 = g_p.clone()
-        g_p2[_t(drop, torch.int64)] = 0
-        dV, dS, dE = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_p2.contiguous())
+        g_p[_t(drop, torch.int64)] = 0
+        dV, dS, dE = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_p.contiguous())
     dVn = dV.cpu().numpy().astype(np.float64)
-    _check_dv(dVn, rV, rabs)
-    _check_seg(dS.cpu().numpy()[chk][ok].astype(np.float64), rS[ok])
-    _check_seg(dE.cpu().numpy()[chk][ok].astype(np.float64), rE[ok])
+    tri_ok = np.where(ok, tri_c, -1)
+    # (a) the adjoint alone: the oracle differentiates with the same upstream
+    # gradient the GPU used (formed from the GPU's FP32 hit points)
+    gp_gpu = g_p.cpu().numpy()[chk].astype(np.float64)
+    aV, aS, aE, aabs = oracle.first_hit_grad(V, T, Sc, Ec, tri_ok, ref["first_tuv"], g_p=gp_gpu, with_abs=True)
+    _check_dv(dVn, aV, aabs)
+    _check_seg(dS.cpu().numpy()[chk][ok].astype(np.float64), aS[ok])
+    _check_seg(dE.cpu().numpy()[chk][ok].astype(np.float64), aE[ok])
+    # (b) end to end: the oracle's own FP64 hit points form its loss gradient
+    gp_ref = np.zeros((chk.size, 3))
+    gp_ref[:, 2] = 2 * (ref["first_p"][:, 2] - target[chk])
+    gp_ref[~ok] = 0.0
+    rV, rS, rE = oracle.first_hit_grad(V, T, Sc, Ec, tri_ok, ref["first_tuv"], g_p=gp_ref)
+    rel = np.linalg.norm(dVn - rV) / np.linalg.norm(rV)
+    print(f"end-to-end dL/dV relative error (2-norm): {rel:.3g}")
+    assert rel <= 1e-5
+    dSc = dS.cpu().numpy()[chk].astype(np.float64)
+    assert np.linalg.norm(dSc - rS) / np.linalg.norm(rS) <= 1e-5
 
     # central differences (FP64, h = 1e-4) of the masked loss in each sampled
     # vertex's z, over the check segments that stay clear of every edge
@@ -172,8 +186,9 @@ def test_c4_fwd_bwd_against_oracle_and_finite_differences():
             continue
         # the GPU gradient of the loss restricted to `clear` segments
         sel = chk[inc]
+        # upstream from the oracle's FP64 residuals, as in the differenced loss
         g_k = torch.zeros_like(P)
-        g_k[_t(sel, torch.int64), 2] = 2 * resid[_t(sel, torch.int64)]
+        g_k[_t(sel, torch.int64), 2] = _t(2 * (ref["first_p"][inc, 2] - target[sel].astype(np.float64)))
         dVk, _, _ = mesh.first_hit_backward(Vt, St, Et, tri, None, None, g_k.contiguous())
         gpu = float(dVk[int(k), 2])
         losses = []
