@@ -66,7 +66,11 @@ typedef struct {
                              of its lanes are done, 1..64 (default 32) */
     int32_t chunk;        /* segments a wave claims per global atomic, 64..2^20
                              (default: about eight chunks per resident wave, 64..4096) */
-    int32_t reserved[3];
+    int32_t stack_depth;  /* traversal-stack entries kept in LDS per lane; deeper entries go to
+                             device memory.  The whole stack (tree height + 1) stays in LDS by
+                             default and for any value at or above it; a smaller value raises
+                             occupancy. 1..255 */
+    int32_t reserved[2];
 } rsi_opts;
 
 /* Output buffers of rsi_query (host struct of device pointers, each [n_r...]).
@@ -183,14 +187,19 @@ rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);
  *   whose left child is the root, as in the paper's Section 2), height: levels
  *   of internal nodes below the entry node, leaf_size: as built. */
 typedef struct {
-    int64_t n_t;
-    int64_t n_nodes;
-    int32_t height;
+    int64_t n_t;       /* triangles over all meshes */
+    int64_t n_nodes;   /* node records (= n_t) */
+    int32_t height;    /* largest tree height over the meshes */
     int32_t leaf_size;
-    int32_t entry;
-    int32_t reserved;
+    int32_t entry;     /* entry node of the first mesh */
+    int32_t n_meshes;
 } rsi_tree_info;
 rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out);
+
+/* Per-mesh layout of a handle: mesh `mesh` owns triangles, sorted leaves and
+ * node records [tri_offset, tri_offset + n_t); its entry node is the last of
+ * them.  Any out-pointer may be NULL. */
+rsi_status rsi_get_mesh_info(rsi_handle h, int32_t mesh, int64_t *tri_offset, int64_t *n_t, int32_t *height);
 
 /* Copy the tree to host buffers (blocking):
  *   boxes  float  [n_nodes*12] per node: left child lo xyz, hi xyz, right child lo xyz, hi xyz
@@ -201,6 +210,78 @@ rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out);
  *   keys   uint64 [n_t]        sorted Morton codes
  * Any pointer may be NULL to skip it. */
 rsi_status rsi_export_tree(rsi_handle h, float *boxes, int32_t *refs, int32_t *order, uint64_t *keys);
+
+/* ------------------------------------------------------------- batches --
+ * Many meshes in one handle, built by the same launches (one launch per
+ * build stage covers every mesh) and queried by ONE persistent launch over
+ * all (mesh, segment) work items; the build + query sequence can be captured
+ * once into a HIP graph and replayed with a single launch.  This extends the
+ * paper's single-surface program (Section 2.3) to batches; callers are those
+ * with many small meshes whose separate launches would be latency bound.
+ *
+ * rsi_batch_create: n_meshes in 1..65535; V, T host arrays of n_meshes
+ * device pointers (vertex and triangle arrays as for rsi_build), n_v, n_t
+ * host arrays of sizes.  The device pointers are kept: rsi_batch_rebuild and
+ * captured rebuilds re-read the same buffers.  Triangle ids in outputs are
+ * per mesh.  Blocks until built.  Errors as for rsi_build. */
+rsi_status rsi_batch_create(int32_t n_meshes, const float *const *V, const int64_t *n_v, const int32_t *const *T,
+                            const int64_t *n_t, const rsi_opts *opts, void *stream, rsi_handle *out);
+
+/* Rebuild every mesh of a batch from its (possibly updated) vertex and
+ * triangle buffers; blocks until done. */
+rsi_status rsi_batch_rebuild(rsi_handle h, void *stream);
+
+/* Query every mesh with its own segments in one launch.  S, E: host arrays of
+ * n_meshes device pointers; n_r: host array of counts; outs: host array of
+ * n_meshes rsi_outputs (hit / tri / t / uv / point as for rsi_query).  mode:
+ * RSI_BOOL and/or RSI_FIRST_HIT.  Copies the tables (waits for that copy),
+ * then runs asynchronously on `stream`. */
+rsi_status rsi_batch_query(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
+                           uint32_t mode, const rsi_outputs *outs, void *stream);
+
+/* Capture [rebuild of every mesh if `rebuild`] + the batched query with
+ * these tables into a HIP graph held by the handle (replacing any previous
+ * one).  All buffers named here must stay valid while the graph is used. */
+rsi_status rsi_batch_capture(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
+                             uint32_t mode, const rsi_outputs *outs, int rebuild, void *stream);
+
+/* Launch the captured graph on `stream`. */
+rsi_status rsi_batch_replay(rsi_handle h, void *stream);
+
+/* Change the options of a handle (all rsi_opts fields; zero keeps the
+ * current value).  Query options apply to the next query; a new leaf_size
+ * takes effect at the next rsi_rebuild / rsi_batch_rebuild.  A captured
+ * graph of the handle is released (after waiting for the device); capture
+ * again to replay with the new options.  rsi_tune does the same. */
+rsi_status rsi_set_opts(rsi_handle h, const rsi_opts *opts);
+rsi_status rsi_get_opts(rsi_handle h, rsi_opts *out);
+
+/* Autotuner: time candidate option sets on a real query and keep the fastest.
+ * For a single-mesh handle set V, n_v, T (used to rebuild when a candidate's
+ * leaf size differs), S, E, n_r and out; for a batch handle set bS, bE, b_nr
+ * and b_outs (per-mesh host arrays as for rsi_batch_query).  Each candidate
+ * is applied, warmed up once, then timed `reps` times with HIP events on
+ * `stream` (median written to ms[i]); the fastest is applied to the handle
+ * (rebuilding if its leaf size differs) and its index written to *best.
+ * The block size, leaf size, LDS stack depth, defer / refill lanes and chunk
+ * are tunable.  Blocks until done. */
+typedef struct {
+    const float *V;
+    int64_t n_v;
+    const int32_t *T;
+    const float *S;
+    const float *E;
+    int64_t n_r;
+    const rsi_outputs *out;
+    const float *const *bS;
+    const float *const *bE;
+    const int64_t *b_nr;
+    const rsi_outputs *b_outs;
+    uint32_t mode;
+    int32_t reserved;
+} rsi_tune_job;
+rsi_status rsi_tune(rsi_handle h, const rsi_tune_job *job, const rsi_opts *candidates, int32_t n_candidates,
+                    int32_t reps, float *ms, int32_t *best, void *stream);
 
 /* Release the handle and its device memory (waits for its pending work). */
 void rsi_destroy(rsi_handle h);

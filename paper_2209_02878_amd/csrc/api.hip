@@ -1,11 +1,12 @@
 // api.hip -- the extern "C" boundary declared in include/rsi.h: argument
-// validation, handle lifetime, device memory, and the launch sequence.
+// validation, handle lifetime, device memory, and the launch sequences.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/rsi.h"
 #include "rsi_host.h"
@@ -44,33 +45,251 @@ hipError_t dalloc(T **p, int64_t n)
 
 void free_handle_memory(rsi_bvh *h)
 {
-    void *ptrs[] = {h->T, h->cent, h->keys, h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb,
-                    h->scalars, h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->pool_ids, h->pool_ts};
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    void *ptrs[] = {h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
+                    h->arrive, h->heights, h->climb, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
+                    h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off, h->vert_off, h->mesh_bounds,
+                    h->mesh_height, h->mesh_root, h->mesh_entry, h->bt.seg_off, h->bt.S, h->bt.E, h->bt.hit,
+                    h->bt.tri, h->bt.t, h->bt.uv, h->bt.point, h->bt_graph.seg_off, h->bt_graph.S,
+                    h->bt_graph.E, h->bt_graph.hit, h->bt_graph.tri, h->bt_graph.t, h->bt_graph.uv,
+                    h->bt_graph.point};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     rsi::free_sort_scratch(h->sort);
     if (h->h_scalars) (void)hipHostFree(h->h_scalars);
 }
 
-// Copy the indices, run the build kernels, then wait once to read back the
-// index check and the tree height (which sizes the traversal stack).
-rsi_status build_into(rsi_bvh *h, const float *V, int64_t n_v, const int32_t *T, hipStream_t s)
+void destroy_handle(rsi_bvh *h)
 {
-    const int64_t n = h->n_t;
-    h->n_v = n_v;
-    hipError_t e = hipSuccess;
-    if (n > 0) e = hipMemcpyAsync(h->T, T, sizeof(int32_t) * 3 * n, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = rsi::launch_build(h, V, s);
-    if (e == hipSuccess && n > 0)
-        e = hipMemcpyAsync(h->h_scalars, h->scalars, sizeof(int32_t) * rsi::kNumScalars, hipMemcpyDeviceToHost,
-                           s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "rsi_build");
-    if (n > 0) {
-        if (h->h_scalars[rsi::kBadIndex]) return invalid("rsi_build: triangle index outside [0, n_v)");
-        h->height = h->h_scalars[rsi::kHeight];
-        h->root_ref = h->h_scalars[rsi::kRootRef];
+    free_handle_memory(h);
+    delete h;
+}
+
+// Apply the nonzero fields of `opts` on top of the handle's current values.
+rsi_status read_opts(const rsi_opts *opts, rsi_bvh *h)
+{
+    int leaf = h->leaf_size, block = h->block_size, defer = h->defer_lanes, refill = h->refill_lanes;
+    int chunk = h->chunk, stack = h->stack_cap;
+    if (opts) {
+        if (opts->leaf_size) leaf = opts->leaf_size;
+        if (opts->block_size) block = opts->block_size;
+        if (opts->defer_lanes) defer = opts->defer_lanes;
+        if (opts->refill_lanes) refill = opts->refill_lanes;
+        if (opts->chunk) chunk = opts->chunk;
+        if (opts->stack_depth) stack = opts->stack_depth;
     }
+    if (stack < 0 || stack > 255) return invalid("stack_depth must be in 1..255");
+    if (leaf < 1 || leaf > rsi::kMaxLeafSize) return invalid("leaf_size must be in 1..16");
+    if (block < 64 || block > 256 || block % 64) return invalid("block_size must be 64, 128, 192 or 256");
+    if (defer < 1 || defer > 64) return invalid("defer_lanes must be in 1..64");
+    if (refill < 1 || refill > 64) return invalid("refill_lanes must be in 1..64");
+    if (chunk != 0 && (chunk < 64 || chunk > (1 << 20))) return invalid("chunk must be 0 or 64..2^20");
+    h->leaf_size = leaf;
+    h->block_size = block;
+    h->defer_lanes = defer;
+    h->refill_lanes = refill;
+    h->chunk = chunk;
+    h->stack_cap = stack;
+    return RSI_OK;
+}
+
+hipError_t alloc_tables(rsi::BatchTables &t, int32_t M)
+{
+    hipError_t e = dalloc(&t.seg_off, M + 1);
+    if (e == hipSuccess) e = dalloc(&t.S, M);
+    if (e == hipSuccess) e = dalloc(&t.E, M);
+    if (e == hipSuccess) e = dalloc(&t.hit, M);
+    if (e == hipSuccess) e = dalloc(&t.tri, M);
+    if (e == hipSuccess) e = dalloc(&t.t, M);
+    if (e == hipSuccess) e = dalloc(&t.uv, M);
+    if (e == hipSuccess) e = dalloc(&t.point, M);
+    return e;
+}
+
+// Allocate a handle for M meshes with the given vertex and triangle counts.
+rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const rsi_opts *opts, bool batch,
+                        rsi_bvh **out)
+{
+    rsi_bvh *h = new (std::nothrow) rsi_bvh();
+    if (!h) return invalid("host allocation failed");
+    rsi_status st = read_opts(opts, h);
+    if (st != RSI_OK) {
+        delete h;
+        return st;
+    }
+    h->M = M;
+    h->h_tri_off.assign(M + 1, 0);
+    h->h_vert_off.assign(M + 1, 0);
+    for (int32_t m = 0; m < M; ++m) {
+        h->h_tri_off[m + 1] = h->h_tri_off[m] + n_t[m];
+        h->h_vert_off[m + 1] = h->h_vert_off[m] + n_v[m];
+    }
+    h->n_t = h->h_tri_off[M];
+    h->n_v = h->h_vert_off[M];
+    h->h_height.assign(M, 0);
+    h->h_root.assign(M, 0);
+    if (h->n_t >= (int64_t(1) << rsi::kLeafFirstBits)) {
+        delete h;
+        return invalid("total triangle count must be below 2^27");
+    }
+    std::vector<int32_t> entry(M);
+    for (int32_t m = 0; m < M; ++m) entry[m] = n_t[m] > 0 ? (int32_t)(h->h_tri_off[m + 1] - 1) : -1;
+
+    const int64_t n = h->n_t;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess) e = dalloc(&h->T, 3 * n);
+    if (e == hipSuccess && batch) e = dalloc(&h->V_all, 3 * h->n_v);
+    if (e == hipSuccess && batch) e = dalloc(&h->src_V, M);
+    if (e == hipSuccess && batch) e = dalloc(&h->src_T, M);
+    if (e == hipSuccess) e = dalloc(&h->cent, 3 * n);
+    if (e == hipSuccess) e = dalloc(&h->keys, n);
+    if (e == hipSuccess) e = dalloc(&h->order, n);
+    if (e == hipSuccess) e = dalloc(&h->nodes, n);
+    if (e == hipSuccess) e = dalloc(&h->tris, n);
+    if (e == hipSuccess) e = dalloc(&h->arrive, n);
+    if (e == hipSuccess) e = dalloc(&h->heights, 2 * n);
+    if (e == hipSuccess) e = dalloc(&h->climb, 11 * n);
+    if (e == hipSuccess) e = dalloc(&h->scalars, rsi::kNumScalars);
+    if (e == hipSuccess) e = dalloc(&h->counters, 1);
+    if (e == hipSuccess) e = dalloc(&h->tri_off, M + 1);
+    if (e == hipSuccess) e = dalloc(&h->vert_off, M + 1);
+    if (e == hipSuccess) e = dalloc(&h->mesh_bounds, 6 * M);
+    if (e == hipSuccess) e = dalloc(&h->mesh_height, M);
+    if (e == hipSuccess) e = dalloc(&h->mesh_root, M);
+    if (e == hipSuccess) e = dalloc(&h->mesh_entry, M);
+    if (e == hipSuccess && batch) e = alloc_tables(h->bt, M);
+    if (e == hipSuccess && batch) e = alloc_tables(h->bt_graph, M);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);
+    if (e == hipSuccess && n > 0) e = rsi::ensure_sort_scratch(h->sort, n);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->tri_off, h->h_tri_off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->vert_off, h->h_vert_off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->mesh_entry, entry.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "handle allocation");
+        destroy_handle(h);
+        return st;
+    }
+    *out = h;
+    return RSI_OK;
+}
+
+// Wait for the build on `s`, then read back the index check and the tree
+// heights (which size the traversal stack).
+rsi_status finish_build(rsi_bvh *h, hipStream_t s, const char *who)
+{
+    hipError_t e = hipSuccess;
+    if (h->n_t > 0) {
+        e = hipMemcpyAsync(h->h_scalars, h->scalars, sizeof(int32_t) * rsi::kNumScalars, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->h_height.data(), h->mesh_height, sizeof(int32_t) * h->M, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->h_root.data(), h->mesh_root, sizeof(int32_t) * h->M, hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (h->n_t > 0) {
+        if ((h->h_scalars[rsi::kBadIndex] & 1) || (h->src_V && h->h_scalars[rsi::kBadGather]))
+            return invalid("triangle index outside [0, n_v)");
+        if (h->h_scalars[rsi::kBadIndex]) return invalid("inconsistent build state (report this)");
+        int32_t mx = 0;
+        for (int32_t v : h->h_height) mx = v > mx ? v : mx;
+        h->height = mx;
+    }
+    return RSI_OK;
+}
+
+// Single mesh: copy the indices and run the build kernels.
+hipError_t enqueue_build_single(rsi_bvh *h, const float *V, const int32_t *T, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (h->n_t > 0) e = hipMemcpyAsync(h->T, T, sizeof(int32_t) * 3 * h->n_t, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = rsi::launch_build(h, V, s);
+    return e;
+}
+
+// Batch: gather the meshes into the concatenated arrays and build.
+hipError_t enqueue_build_batch(rsi_bvh *h, hipStream_t s)
+{
+    hipError_t e = rsi::launch_gather(h, s);
+    if (e == hipSuccess) e = rsi::launch_build(h, h->V_all, s);
+    return e;
+}
+
+bool valid_mode(uint32_t mode) { return mode != 0 && !(mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS)); }
+
+hipError_t ensure_ovf(rsi_bvh *h, int64_t n_r)
+{
+    if (h->ovf_cap >= n_r) return hipSuccess;
+    if (h->ovf_seg) (void)hipFree(h->ovf_seg);
+    if (h->ovf_cnt) (void)hipFree(h->ovf_cnt);
+    if (h->ovf_off) (void)hipFree(h->ovf_off);
+    h->ovf_seg = nullptr;
+    h->ovf_cnt = nullptr;
+    h->ovf_off = nullptr;
+    h->ovf_cap = 0;
+    hipError_t e = dalloc(&h->ovf_seg, n_r);
+    if (e == hipSuccess) e = dalloc(&h->ovf_cnt, n_r);
+    if (e == hipSuccess) e = dalloc(&h->ovf_off, n_r);
+    if (e == hipSuccess) h->ovf_cap = n_r;
+    return e;
+}
+
+hipError_t ensure_pool(rsi_bvh *h, int64_t n)
+{
+    if (h->pool_cap >= n) return hipSuccess;
+    if (h->pool_ids) (void)hipFree(h->pool_ids);
+    if (h->pool_ts) (void)hipFree(h->pool_ts);
+    h->pool_ids = nullptr;
+    h->pool_ts = nullptr;
+    h->pool_cap = 0;
+    const int64_t want = n + n / 4;
+    hipError_t e = dalloc(&h->pool_ids, want);
+    if (e == hipSuccess) e = dalloc(&h->pool_ts, want);
+    if (e == hipSuccess) h->pool_cap = want;
+    return e;
+}
+
+// Validate a batch query and write its tables; returns the total segment count.
+rsi_status set_batch_tables(rsi_bvh *h, rsi::BatchTables &bt, const float *const *S, const float *const *E,
+                            const int64_t *n_r, uint32_t mode, const rsi_outputs *outs, hipStream_t s,
+                            int64_t *total)
+{
+    const int32_t M = h->M;
+    if (!S || !E || !n_r || !outs) return invalid("rsi_batch_query: NULL table");
+    if (mode == 0 || (mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT)))
+        return invalid("rsi_batch_query: mode must be a nonzero mask of RSI_BOOL and RSI_FIRST_HIT");
+    std::vector<int64_t> off(M + 1, 0);
+    std::vector<const void *> tab(7 * (size_t)M, nullptr);
+    for (int32_t m = 0; m < M; ++m) {
+        if (n_r[m] < 0) return invalid("rsi_batch_query: negative segment count");
+        off[m + 1] = off[m] + n_r[m];
+        if (n_r[m] > 0) {
+            if (!S[m] || !E[m]) return invalid("rsi_batch_query: NULL segment pointer");
+            if ((mode & RSI_BOOL) && !outs[m].hit) return invalid("rsi_batch_query: RSI_BOOL needs hit");
+            if ((mode & RSI_FIRST_HIT) && (!outs[m].tri || !outs[m].t || !outs[m].uv || !outs[m].point))
+                return invalid("rsi_batch_query: RSI_FIRST_HIT needs tri, t, uv, point");
+        }
+        tab[0 * M + m] = S[m];
+        tab[1 * M + m] = E[m];
+        tab[2 * M + m] = outs[m].hit;
+        tab[3 * M + m] = outs[m].tri;
+        tab[4 * M + m] = outs[m].t;
+        tab[5 * M + m] = outs[m].uv;
+        tab[6 * M + m] = outs[m].point;
+    }
+    if (off[M] >= (int64_t(1) << 30)) return invalid("rsi_batch_query: total segments must be below 2^30");
+    void *dst[7] = {bt.S, bt.E, bt.hit, bt.tri, bt.t, bt.uv, bt.point};
+    hipError_t e = hipMemcpyAsync(bt.seg_off, off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice, s);
+    for (int k = 0; k < 7 && e == hipSuccess; ++k)
+        e = hipMemcpyAsync(dst[k], tab.data() + (size_t)k * M, sizeof(void *) * M, hipMemcpyHostToDevice, s);
+    // the host vectors go out of scope on return: wait for the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_query: tables");
+    *total = off[M];
     return RSI_OK;
 }
 
@@ -102,56 +321,14 @@ rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
     if (n_t >= (int64_t(1) << rsi::kLeafFirstBits)) return invalid("rsi_build: n_t must be below 2^27");
     if (n_t > 0 && n_v == 0) return invalid("rsi_build: triangles given without vertices");
     if ((n_v > 0 && !V) || (n_t > 0 && !T)) return invalid("rsi_build: NULL pointer with nonzero size");
-    int leaf = 1, block = 128, defer = 32, refill = 32, chunk = 0;
-    if (opts) {
-        if (opts->leaf_size) leaf = opts->leaf_size;
-        if (opts->block_size) block = opts->block_size;
-        if (opts->defer_lanes) defer = opts->defer_lanes;
-        if (opts->refill_lanes) refill = opts->refill_lanes;
-        if (opts->chunk) chunk = opts->chunk;
-    }
-    if (chunk != 0 && (chunk < 64 || chunk > (1 << 20))) return invalid("rsi_build: chunk must be 0 or 64..2^20");
-    if (defer < 1 || defer > 64) return invalid("rsi_build: defer_lanes must be in 1..64");
-    if (refill < 1 || refill > 64) return invalid("rsi_build: refill_lanes must be in 1..64");
-    if (leaf < 1 || leaf > rsi::kMaxLeafSize) return invalid("rsi_build: leaf_size must be in 1..16");
-    if (block < 64 || block > 256 || block % 64) return invalid("rsi_build: block_size must be 64, 128, 192 or 256");
-
-    rsi_bvh *h = new (std::nothrow) rsi_bvh();
-    if (!h) return invalid("rsi_build: host allocation failed");
+    rsi_bvh *h = nullptr;
+    rsi_status st = alloc_handle(1, &n_v, &n_t, opts, false, &h);
+    if (st != RSI_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    h->n_v = n_v;
-    h->n_t = n_t;
-    h->leaf_size = leaf;
-    h->block_size = block;
-    h->defer_lanes = defer;
-    h->refill_lanes = refill;
-    h->chunk = chunk;
-    h->entry = n_t > 0 ? (int32_t)(n_t - 1) : 0;
-    hipError_t e = hipGetDevice(&h->device);
-    const int64_t n = n_t;
-    if (e == hipSuccess) e = dalloc(&h->T, 3 * n);
-    if (e == hipSuccess) e = dalloc(&h->cent, 3 * n);
-    if (e == hipSuccess) e = dalloc(&h->keys, n);
-    if (e == hipSuccess) e = dalloc(&h->order, n);
-    if (e == hipSuccess) e = dalloc(&h->nodes, n);
-    if (e == hipSuccess) e = dalloc(&h->tris, n);
-    if (e == hipSuccess) e = dalloc(&h->arrive, n);
-    if (e == hipSuccess) e = dalloc(&h->heights, 2 * n);
-    if (e == hipSuccess) e = dalloc(&h->climb, 11 * n);
-    if (e == hipSuccess) e = dalloc(&h->scalars, rsi::kNumScalars);
-    if (e == hipSuccess) e = dalloc(&h->counters, 1);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);
-    if (e == hipSuccess && n > 0) e = rsi::ensure_sort_scratch(h->sort, n);
-    if (e != hipSuccess) {
-        rsi_status st = hip_fail(e, "rsi_build");
-        free_handle_memory(h);
-        delete h;
-        return st;
-    }
-    rsi_status st = build_into(h, V, n_v, T, s);
+    hipError_t e = enqueue_build_single(h, V, T, s);
+    st = e == hipSuccess ? finish_build(h, s, "rsi_build") : hip_fail(e, "rsi_build");
     if (st != RSI_OK) {
-        free_handle_memory(h);
-        delete h;
+        destroy_handle(h);
         return st;
     }
     *out = h;
@@ -162,52 +339,26 @@ rsi_status rsi_rebuild(rsi_handle h, const float *V, int64_t n_v, const int32_t 
 {
     set_error("");
     if (!h) return invalid("rsi_rebuild: NULL handle");
+    if (h->M != 1) return invalid("rsi_rebuild: batch handle (use rsi_batch_rebuild)");
     if (n_v < 0) return invalid("rsi_rebuild: negative n_v");
     if (h->n_t > 0 && n_v == 0) return invalid("rsi_rebuild: triangles given without vertices");
     if (h->n_t > 0 && (!V || !T)) return invalid("rsi_rebuild: NULL pointer with nonzero size");
-    return build_into(h, V, n_v, T, (hipStream_t)stream);
+    h->n_v = n_v;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = enqueue_build_single(h, V, T, s);
+    if (e != hipSuccess) return hip_fail(e, "rsi_rebuild");
+    return finish_build(h, s, "rsi_rebuild");
 }
 
 rsi_status rsi_refit(rsi_handle h, const float *V, void *stream)
 {
     set_error("");
     if (!h) return invalid("rsi_refit: NULL handle");
+    if (h->M != 1) return invalid("rsi_refit: batch handle");
     if (h->n_t > 0 && !V) return invalid("rsi_refit: NULL vertices");
     hipError_t e = rsi::launch_refit(h, V, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rsi_refit");
     return RSI_OK;
-}
-
-static hipError_t ensure_ovf(rsi_bvh *h, int64_t n_r)
-{
-    if (h->ovf_cap >= n_r) return hipSuccess;
-    if (h->ovf_seg) (void)hipFree(h->ovf_seg);
-    if (h->ovf_cnt) (void)hipFree(h->ovf_cnt);
-    if (h->ovf_off) (void)hipFree(h->ovf_off);
-    h->ovf_seg = nullptr;
-    h->ovf_cnt = nullptr;
-    h->ovf_off = nullptr;
-    h->ovf_cap = 0;
-    hipError_t e = dalloc(&h->ovf_seg, n_r);
-    if (e == hipSuccess) e = dalloc(&h->ovf_cnt, n_r);
-    if (e == hipSuccess) e = dalloc(&h->ovf_off, n_r);
-    if (e == hipSuccess) h->ovf_cap = n_r;
-    return e;
-}
-
-static hipError_t ensure_pool(rsi_bvh *h, int64_t n)
-{
-    if (h->pool_cap >= n) return hipSuccess;
-    if (h->pool_ids) (void)hipFree(h->pool_ids);
-    if (h->pool_ts) (void)hipFree(h->pool_ts);
-    h->pool_ids = nullptr;
-    h->pool_ts = nullptr;
-    h->pool_cap = 0;
-    const int64_t want = n + n / 4;
-    hipError_t e = dalloc(&h->pool_ids, want);
-    if (e == hipSuccess) e = dalloc(&h->pool_ts, want);
-    if (e == hipSuccess) h->pool_cap = want;
-    return e;
 }
 
 rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, uint32_t mode,
@@ -215,9 +366,10 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
 {
     set_error("");
     if (!h) return invalid("rsi_query: NULL handle");
+    if (h->M != 1) return invalid("rsi_query: batch handle (use rsi_batch_query)");
     if (!out) return invalid("rsi_query: NULL outputs");
     if (n_r < 0) return invalid("rsi_query: negative n_r");
-    if (mode == 0 || (mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS)))
+    if (!valid_mode(mode))
         return invalid("rsi_query: mode must be a nonzero mask of RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS");
     if (n_r == 0) return RSI_OK;  // nothing to read or write; output pointers may be NULL
     if (!S || !E) return invalid("rsi_query: NULL segment pointer");
@@ -243,6 +395,8 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
         e = ensure_ovf(h, n_r);
         if (e != hipSuccess) return hip_fail(e, "rsi_query: overflow list");
     }
+    e = rsi::ensure_gstack(h);
+    if (e != hipSuccess) return hip_fail(e, "rsi_query: stack");
     e = rsi::launch_query(h, S, E, n_r, mode, o, s);
     if (e != hipSuccess) return hip_fail(e, "rsi_query");
     if (mode & RSI_ALL_HITS) {
@@ -252,7 +406,8 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "rsi_query: overflow read-back");
         const int64_t nseg = h->h_scalars[rsi::kOvfSegs];
-        uint64_t tot = (uint32_t)h->h_scalars[rsi::kOvfTotalLo] | ((uint64_t)(uint32_t)h->h_scalars[rsi::kOvfTotalHi] << 32);
+        const uint64_t tot = (uint32_t)h->h_scalars[rsi::kOvfTotalLo] |
+                             ((uint64_t)(uint32_t)h->h_scalars[rsi::kOvfTotalHi] << 32);
         h->last_ovf_segs = nseg;
         h->last_ovf_total = (int64_t)tot;
         if (nseg > 0) {
@@ -271,6 +426,7 @@ rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, 
 {
     set_error("");
     if (!h) return invalid("rsi_first_hit_backward: NULL handle");
+    if (h->M != 1) return invalid("rsi_first_hit_backward: batch handle");
     if (n_r < 0 || n_r >= (int64_t(1) << 30)) return invalid("rsi_first_hit_backward: n_r must be in [0, 2^30)");
     if (n_r == 0) return RSI_OK;
     if (!S || !E || !tri) return invalid("rsi_first_hit_backward: NULL S, E or tri");
@@ -308,6 +464,245 @@ rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *
     return RSI_OK;
 }
 
+// ------------------------------------------------------------- batches ---
+
+rsi_status rsi_batch_create(int32_t n_meshes, const float *const *V, const int64_t *n_v, const int32_t *const *T,
+                            const int64_t *n_t, const rsi_opts *opts, void *stream, rsi_handle *out)
+{
+    set_error("");
+    if (!out) return invalid("rsi_batch_create: out is NULL");
+    *out = nullptr;
+    if (n_meshes < 1 || n_meshes > 65535) return invalid("rsi_batch_create: n_meshes must be in 1..65535");
+    if (!V || !n_v || !T || !n_t) return invalid("rsi_batch_create: NULL table");
+    for (int32_t m = 0; m < n_meshes; ++m) {
+        if (n_v[m] < 0 || n_t[m] < 0) return invalid("rsi_batch_create: negative size");
+        if (n_t[m] > 0 && n_v[m] == 0) return invalid("rsi_batch_create: triangles given without vertices");
+        if ((n_v[m] > 0 && !V[m]) || (n_t[m] > 0 && !T[m])) return invalid("rsi_batch_create: NULL pointer");
+    }
+    rsi_bvh *h = nullptr;
+    rsi_status st = alloc_handle(n_meshes, n_v, n_t, opts, true, &h);
+    if (st != RSI_OK) return st;
+    hipError_t e = hipMemcpy(h->src_V, V, sizeof(float *) * n_meshes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->src_T, T, sizeof(int32_t *) * n_meshes, hipMemcpyHostToDevice);
+    hipStream_t s = (hipStream_t)stream;
+    if (e == hipSuccess) e = enqueue_build_batch(h, s);
+    st = e == hipSuccess ? finish_build(h, s, "rsi_batch_create") : hip_fail(e, "rsi_batch_create");
+    if (st != RSI_OK) {
+        destroy_handle(h);
+        return st;
+    }
+    *out = h;
+    return RSI_OK;
+}
+
+rsi_status rsi_batch_rebuild(rsi_handle h, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_batch_rebuild: NULL handle");
+    if (!h->src_V) return invalid("rsi_batch_rebuild: not a batch handle");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t before = h->height;
+    hipError_t e = enqueue_build_batch(h, s);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_rebuild");
+    rsi_status st = finish_build(h, s, "rsi_batch_rebuild");
+    if (st == RSI_OK && h->height > before && h->graph) {
+        // the captured launch sized its stack for the old trees
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    return st;
+}
+
+rsi_status rsi_batch_query(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
+                           uint32_t mode, const rsi_outputs *outs, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_batch_query: NULL handle");
+    if (!h->src_V) return invalid("rsi_batch_query: not a batch handle");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t total = 0;
+    rsi_status st = set_batch_tables(h, h->bt, S, E, n_r, mode, outs, s, &total);
+    if (st != RSI_OK) return st;
+    hipError_t e = rsi::ensure_gstack(h);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_query: stack");
+    e = rsi::launch_batch_query(h, h->bt, total, mode, s);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_query");
+    return RSI_OK;
+}
+
+rsi_status rsi_batch_capture(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
+                             uint32_t mode, const rsi_outputs *outs, int rebuild, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_batch_capture: NULL handle");
+    if (!h->src_V) return invalid("rsi_batch_capture: not a batch handle");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t total = 0;
+    if (h->graph) {
+        // the old graph reads bt_graph, which is about to be rewritten
+        hipError_t w = hipDeviceSynchronize();
+        if (w != hipSuccess) return hip_fail(w, "rsi_batch_capture: wait for replays");
+        (void)hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    rsi_status st = set_batch_tables(h, h->bt_graph, S, E, n_r, mode, outs, s, &total);
+    if (st != RSI_OK) return st;
+    hipError_t e = rsi::ensure_gstack(h);  // no allocation may happen inside the capture
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: stack");
+    if (!h->capture_stream) e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: stream");
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: begin");
+    hipError_t ek = hipSuccess;
+    if (rebuild) ek = enqueue_build_batch(h, h->capture_stream);
+    if (ek == hipSuccess) ek = rsi::launch_batch_query(h, h->bt_graph, total, mode, h->capture_stream);
+    e = hipStreamEndCapture(h->capture_stream, &g);
+    if (ek != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(ek, "rsi_batch_capture: enqueue");
+    }
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: end");
+    e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph = nullptr;
+        return hip_fail(e, "rsi_batch_capture: instantiate");
+    }
+    return RSI_OK;
+}
+
+rsi_status rsi_batch_replay(rsi_handle h, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_batch_replay: NULL handle");
+    if (!h->graph) return invalid("rsi_batch_replay: nothing captured");
+    hipError_t e = hipGraphLaunch(h->graph, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rsi_batch_replay");
+    return RSI_OK;
+}
+
+// --------------------------------------------------------------- tuning ---
+
+// A captured graph froze the launch shape of the old options: drop it.
+static rsi_status drop_graph(rsi_bvh *h)
+{
+    if (!h->graph) return RSI_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "waiting for graph replays");
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    return RSI_OK;
+}
+
+rsi_status rsi_set_opts(rsi_handle h, const rsi_opts *opts)
+{
+    set_error("");
+    if (!h) return invalid("rsi_set_opts: NULL handle");
+    rsi_status st = drop_graph(h);
+    if (st != RSI_OK) return st;
+    return read_opts(opts, h);
+}
+
+rsi_status rsi_get_opts(rsi_handle h, rsi_opts *out)
+{
+    set_error("");
+    if (!h || !out) return invalid("rsi_get_opts: NULL argument");
+    memset(out, 0, sizeof(*out));
+    out->leaf_size = h->leaf_size;
+    out->block_size = h->block_size;
+    out->defer_lanes = h->defer_lanes;
+    out->refill_lanes = h->refill_lanes;
+    out->chunk = h->chunk;
+    out->stack_depth = h->stack_cap;
+    return RSI_OK;
+}
+
+static rsi_status tune_rebuild(rsi_bvh *h, const rsi_tune_job *job, hipStream_t s)
+{
+    if (h->src_V) return rsi_batch_rebuild(h, s);
+    if (h->n_t > 0 && (!job->V || !job->T)) return invalid("rsi_tune: V and T are needed to try leaf sizes");
+    return rsi_rebuild(h, job->V, job->n_v, job->T, s);
+}
+
+static rsi_status tune_run(rsi_bvh *h, const rsi_tune_job *job, hipStream_t s)
+{
+    if (h->src_V) return rsi_batch_query(h, job->bS, job->bE, job->b_nr, job->mode, job->b_outs, s);
+    return rsi_query(h, job->S, job->E, job->n_r, job->mode, job->out, s);
+}
+
+rsi_status rsi_tune(rsi_handle h, const rsi_tune_job *job, const rsi_opts *cand, int32_t n_cand, int32_t reps,
+                    float *ms, int32_t *best, void *stream)
+{
+    set_error("");
+    if (!h || !job || !cand || n_cand < 1 || reps < 1 || !best) return invalid("rsi_tune: bad argument");
+    {
+        rsi_status dg = drop_graph(h);
+        if (dg != RSI_OK) return dg;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "rsi_tune: events");
+    // options before tuning (set directly: a zero field in rsi_opts means "keep")
+    const int32_t o_leaf = h->leaf_size, o_block = h->block_size, o_defer = h->defer_lanes;
+    const int32_t o_refill = h->refill_lanes, o_chunk = h->chunk, o_stack = h->stack_cap;
+    auto restore = [&]() {
+        h->leaf_size = o_leaf;
+        h->block_size = o_block;
+        h->defer_lanes = o_defer;
+        h->refill_lanes = o_refill;
+        h->chunk = o_chunk;
+        h->stack_cap = o_stack;
+    };
+    rsi_status st = RSI_OK;
+    float best_ms = 0.0f;
+    int32_t best_i = -1;
+    std::vector<float> t((size_t)reps);
+    for (int32_t c = 0; c < n_cand && st == RSI_OK; ++c) {
+        const int32_t old_leaf = h->leaf_size;
+        restore();  // each candidate starts from the original options
+        st = read_opts(&cand[c], h);
+        if (st == RSI_OK && h->leaf_size != old_leaf) st = tune_rebuild(h, job, s);
+        if (st == RSI_OK) st = tune_run(h, job, s);  // warm-up
+        for (int32_t r = 0; r < reps && st == RSI_OK; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) st = tune_run(h, job, s);
+            if (st == RSI_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+            if (st == RSI_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            if (st == RSI_OK && e == hipSuccess) e = hipEventElapsedTime(&t[(size_t)r], e0, e1);
+            if (e != hipSuccess) st = hip_fail(e, "rsi_tune: timing");
+        }
+        if (st != RSI_OK) break;
+        std::vector<float> sorted = t;
+        for (size_t x = 1; x < sorted.size(); ++x)
+            for (size_t y = x; y > 0 && sorted[y] < sorted[y - 1]; --y) std::swap(sorted[y], sorted[y - 1]);
+        const float med = sorted[sorted.size() / 2];
+        if (ms) ms[c] = med;
+        if (best_i < 0 || med < best_ms) {
+            best_ms = med;
+            best_i = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RSI_OK) {
+        const int32_t cur_leaf = h->leaf_size;
+        restore();
+        if (h->leaf_size != cur_leaf) (void)tune_rebuild(h, job, s);
+        return st;
+    }
+    const int32_t old_leaf = h->leaf_size;
+    restore();
+    st = read_opts(&cand[best_i], h);
+    if (st == RSI_OK && h->leaf_size != old_leaf) st = tune_rebuild(h, job, s);
+    *best = best_i;
+    return st;
+}
+
+// --------------------------------------------------------------- status ---
+
 rsi_status rsi_set_counting(rsi_handle h, int enable)
 {
     set_error("");
@@ -339,7 +734,19 @@ rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out)
     out->n_nodes = h->n_t;
     out->height = h->height;
     out->leaf_size = h->leaf_size;
-    out->entry = h->entry;
+    out->entry = h->n_t > 0 ? (int32_t)(h->h_tri_off[1] - 1) : 0;
+    out->n_meshes = h->M;
+    return RSI_OK;
+}
+
+rsi_status rsi_get_mesh_info(rsi_handle h, int32_t mesh, int64_t *tri_offset, int64_t *n_t, int32_t *height)
+{
+    set_error("");
+    if (!h) return invalid("rsi_get_mesh_info: NULL handle");
+    if (mesh < 0 || mesh >= h->M) return invalid("rsi_get_mesh_info: mesh out of range");
+    if (tri_offset) *tri_offset = h->h_tri_off[mesh];
+    if (n_t) *n_t = h->h_tri_off[mesh + 1] - h->h_tri_off[mesh];
+    if (height) *height = h->h_height[mesh];
     return RSI_OK;
 }
 
@@ -350,9 +757,8 @@ rsi_status rsi_export_tree(rsi_handle h, float *boxes, int32_t *refs, int32_t *o
     const int64_t n = h->n_t;
     if (n == 0) return RSI_OK;
     hipError_t e = hipDeviceSynchronize();
-    rsi::Node *tmp = nullptr;
     if (e == hipSuccess && (boxes || refs)) {
-        tmp = new (std::nothrow) rsi::Node[(size_t)n];
+        rsi::Node *tmp = new (std::nothrow) rsi::Node[(size_t)n];
         if (!tmp) return invalid("rsi_export_tree: host allocation failed");
         e = hipMemcpy(tmp, h->nodes, sizeof(rsi::Node) * (size_t)n, hipMemcpyDeviceToHost);
         if (e == hipSuccess) {
@@ -376,8 +782,7 @@ void rsi_destroy(rsi_handle h)
 {
     if (!h) return;
     (void)hipDeviceSynchronize();
-    free_handle_memory(h);
-    delete h;
+    destroy_handle(h);
 }
 
 }  // extern "C"

@@ -1,13 +1,23 @@
 // build.hip -- linear BVH construction on the GPU (paper Section 2 and
-// Section 3.1; the steps are those timed in the paper's Table 2).
+// Section 3.1; the steps are those timed in the paper's Table 2), for one
+// mesh or for a batch of meshes in the same launches.
 //
-//   k_init       reset the build scalars and the per-node arrival counters
+// All meshes of a handle share concatenated arrays: mesh m owns triangles,
+// sorted leaves and node records [off[m], off[m+1]).  A single mesh is the
+// case M = 1.
+//
+//   k_gather     (batches) copy every mesh's vertices and triangles into the
+//                concatenated arrays, offsetting the vertex indices
+//   k_init       reset per-mesh bounds, heights, roots and arrival counters
 //   k_centroids  c_j = (v_a + v_b + v_c) / 3 per triangle, index validation,
-//                and the support interval of the centroids (block min/max
-//                in LDS, then one ordered-int atomic per block and axis)
-//   k_morton     quantise c_j to 2^21 levels per axis inside that interval
-//                and interleave the three 21-bit integers into a 63-bit key
-//   (sort.hip)   stable radix sort of (key, triangle id)
+//                and the support interval of each mesh's centroids (block
+//                min/max in LDS, then one ordered-int atomic per block, mesh
+//                and axis)
+//   k_morton     quantise c_j to 2^21 levels per axis inside its mesh's
+//                interval and interleave the three 21-bit integers into a
+//                63-bit key
+//   (sort.hip)   stable radix sort of (key, triangle id); with M > 1 a final
+//                stable pass on the mesh id groups each mesh's leaves again
 //   k_lbvh_*     agglomerative single-pass construction over the sorted
 //                keys (Apetrei's scheme, as the paper follows): every leaf
 //                climbs; at each step the node joins the neighbour across the
@@ -21,10 +31,10 @@
 //                boundaries finish with device-scope counters
 //                (k_lbvh_global), so only those pay for cross-XCD ordering.
 //
-// The entry node is record n_t - 1 (unused by the n_t - 1 internal nodes
-// 0 .. n_t - 2): its left child is the root and its right child an empty far
-// box, which mirrors the paper's convention of keeping the root as the left
-// child of internalNodes[N_t - 1] and also covers n_t == 1.
+// The entry node of mesh m is its last record off[m+1] - 1 (unused by its
+// n - 1 internal nodes): its left child is the root and its right child an
+// empty far box, which mirrors the paper's convention of keeping the root as
+// the left child of internalNodes[N_t - 1] and also covers n = 1.
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <stdint.h>
@@ -34,57 +44,125 @@
 namespace rsi {
 namespace {
 
-__global__ void k_init(int32_t *__restrict__ scalars, int32_t *__restrict__ arrive, int64_t n_arrive)
+struct BuildArgs {
+    int32_t M;
+    const int64_t *off;    // [M+1] triangle offsets
+    const float *V;        // vertices, global indexing
+    int64_t n_v;
+    const int32_t *T;      // triangles with global vertex indices
+    int64_t n_t;
+    float *cent;
+    uint64_t *keys;
+    uint32_t *order;
+    Node *nodes;
+    Tri *tris;
+    int32_t *arrive;
+    int32_t *heights;
+    int32_t *climb;
+    int32_t *bounds;       // [6M] ordered-int centroid bounds per mesh
+    int32_t *mesh_height;  // [M]
+    int32_t *mesh_root;    // [M]
+    int32_t *scalars;
+    int32_t leaf_size;
+};
+
+__global__ void k_gather(int32_t M, const float *const *__restrict__ Vp, const int32_t *const *__restrict__ Tp,
+                         const int64_t *__restrict__ voff, const int64_t *__restrict__ toff, float *__restrict__ V,
+                         int32_t *__restrict__ T, int32_t *__restrict__ scalars)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        for (int k = 0; k < 3; ++k) {
-            scalars[kBoundLo + k] = float_to_ordered(FLT_MAX);
-            scalars[kBoundHi + k] = float_to_ordered(-FLT_MAX);
+    const int64_t nv = voff[M], nt = toff[M];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nv + nt; k += stride) {
+        if (k < nv) {
+            const int32_t m = mesh_of(voff, M, k);
+            const int64_t loc = k - voff[m];
+            V[3 * k] = Vp[m][3 * loc];
+            V[3 * k + 1] = Vp[m][3 * loc + 1];
+            V[3 * k + 2] = Vp[m][3 * loc + 2];
+        } else {
+            const int64_t j = k - nv;
+            const int32_t m = mesh_of(toff, M, j);
+            const int64_t loc = j - toff[m];
+            const int64_t nvm = voff[m + 1] - voff[m];
+            for (int c = 0; c < 3; ++c) {
+                int32_t x = Tp[m][3 * loc + c];
+                if (x < 0 || x >= nvm) {  // reported; a valid index keeps later reads inside V
+                    atomicOr(&scalars[kBadGather], 1);
+                    x = 0;
+                }
+                T[3 * j + c] = (int32_t)(x + voff[m]);
+            }
         }
-        scalars[kBadIndex] = 0;
-        scalars[kHeight] = 0;
-        scalars[kRootRef] = 0;
     }
-    if (i < n_arrive) arrive[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_centroids(const float *__restrict__ V, int64_t n_v,
-                                                   const int32_t *__restrict__ T, int64_t n_t,
-                                                   float *__restrict__ cent, int32_t *__restrict__ scalars)
+__global__ void k_clear_gather_flag(int32_t *scalars) { scalars[kBadGather] = 0; }
+
+__global__ void k_init(BuildArgs a)
 {
-    __shared__ int32_t lo[3], hi[3];
-    const int tid = threadIdx.x;
-    if (tid < 3) {
-        lo[tid] = float_to_ordered(FLT_MAX);
-        hi[tid] = float_to_ordered(-FLT_MAX);
-    }
-    __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + tid;
-    if (j < n_t) {
-        int32_t a = T[3 * j], b = T[3 * j + 1], c = T[3 * j + 2];
-        bool ok = a >= 0 && a < n_v && b >= 0 && b < n_v && c >= 0 && c < n_v;
-        if (!ok) {
-            atomicOr(&scalars[kBadIndex], 1);
-            a = b = c = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < a.M) {
+        for (int k = 0; k < 3; ++k) {
+            a.bounds[6 * i + k] = float_to_ordered(FLT_MAX);
+            a.bounds[6 * i + 3 + k] = float_to_ordered(-FLT_MAX);
         }
-        float cx = (V[3 * a] + V[3 * b] + V[3 * c]) * (1.0f / 3.0f);
-        float cy = (V[3 * a + 1] + V[3 * b + 1] + V[3 * c + 1]) * (1.0f / 3.0f);
-        float cz = (V[3 * a + 2] + V[3 * b + 2] + V[3 * c + 2]) * (1.0f / 3.0f);
-        cent[j] = cx;
-        cent[n_t + j] = cy;
-        cent[2 * n_t + j] = cz;
-        atomicMin(&lo[0], float_to_ordered(cx));
-        atomicMin(&lo[1], float_to_ordered(cy));
-        atomicMin(&lo[2], float_to_ordered(cz));
-        atomicMax(&hi[0], float_to_ordered(cx));
-        atomicMax(&hi[1], float_to_ordered(cy));
-        atomicMax(&hi[2], float_to_ordered(cz));
+        a.mesh_height[i] = 0;
+        a.mesh_root[i] = 0;
+    }
+    if (i == 0) a.scalars[kBadIndex] = 0;
+    if (i < a.n_t) a.arrive[i] = 0;
+}
+
+constexpr int kCentBlock = 256;
+constexpr int kCentMeshes = 4;  // meshes per block reduced in LDS; the rest go straight to global
+
+__global__ __launch_bounds__(kCentBlock) void k_centroids(BuildArgs a)
+{
+    __shared__ int32_t lb[kCentMeshes][6];
+    const int tid = threadIdx.x;
+    if (tid < kCentMeshes * 6) {
+        lb[tid / 6][tid % 6] = float_to_ordered((tid % 6) < 3 ? FLT_MAX : -FLT_MAX);
+    }
+    const int64_t j0 = (int64_t)blockIdx.x * kCentBlock;
+    const int32_t m0 = mesh_of(a.off, a.M, j0 < a.n_t ? j0 : a.n_t - 1);
+    __syncthreads();
+    const int64_t j = j0 + tid;
+    if (j < a.n_t) {
+        int32_t va = a.T[3 * j], vb = a.T[3 * j + 1], vc = a.T[3 * j + 2];
+        const bool ok = va >= 0 && va < a.n_v && vb >= 0 && vb < a.n_v && vc >= 0 && vc < a.n_v;
+        if (!ok) {
+            atomicOr(&a.scalars[kBadIndex], 1);
+            va = vb = vc = 0;
+        }
+        const float cx = (a.V[3 * va] + a.V[3 * vb] + a.V[3 * vc]) * (1.0f / 3.0f);
+        const float cy = (a.V[3 * va + 1] + a.V[3 * vb + 1] + a.V[3 * vc + 1]) * (1.0f / 3.0f);
+        const float cz = (a.V[3 * va + 2] + a.V[3 * vb + 2] + a.V[3 * vc + 2]) * (1.0f / 3.0f);
+        a.cent[j] = cx;
+        a.cent[a.n_t + j] = cy;
+        a.cent[2 * a.n_t + j] = cz;
+        const int32_t m = mesh_of(a.off, a.M, j);
+        const int32_t q[3] = {float_to_ordered(cx), float_to_ordered(cy), float_to_ordered(cz)};
+        if (m - m0 < kCentMeshes) {
+            int32_t *l = lb[m - m0];
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&l[k], q[k]);
+                atomicMax(&l[3 + k], q[k]);
+            }
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&a.bounds[6 * m + k], q[k]);
+                atomicMax(&a.bounds[6 * m + 3 + k], q[k]);
+            }
+        }
     }
     __syncthreads();
-    if (tid < 3) {
-        atomicMin(&scalars[kBoundLo + tid], lo[tid]);
-        atomicMax(&scalars[kBoundHi + tid], hi[tid]);
+    if (tid < kCentMeshes * 6) {
+        const int32_t m = m0 + tid / 6, k = tid % 6;
+        const int32_t v = lb[tid / 6][k];
+        if (m < a.M && v != float_to_ordered(k < 3 ? FLT_MAX : -FLT_MAX)) {
+            if (k < 3) atomicMin(&a.bounds[6 * m + k], v);
+            else atomicMax(&a.bounds[6 * m + k], v);
+        }
     }
 }
 
@@ -109,20 +187,18 @@ __device__ inline uint32_t quantise21(float c, float lo, float ext)
     return (uint32_t)q;
 }
 
-__global__ void k_morton(const float *__restrict__ cent, int64_t n_t, const int32_t *__restrict__ scalars,
-                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids)
+__global__ void k_morton(BuildArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_t) return;
-    const float lx = ordered_to_float(scalars[kBoundLo]), ly = ordered_to_float(scalars[kBoundLo + 1]),
-                lz = ordered_to_float(scalars[kBoundLo + 2]);
-    const float hx = ordered_to_float(scalars[kBoundHi]), hy = ordered_to_float(scalars[kBoundHi + 1]),
-                hz = ordered_to_float(scalars[kBoundHi + 2]);
-    const uint32_t qx = quantise21(cent[j], lx, hx - lx);
-    const uint32_t qy = quantise21(cent[n_t + j], ly, hy - ly);
-    const uint32_t qz = quantise21(cent[2 * n_t + j], lz, hz - lz);
-    keys[j] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-    ids[j] = (uint32_t)j;
+    if (j >= a.n_t) return;
+    const int32_t *b = a.bounds + 6 * mesh_of(a.off, a.M, j);
+    const float lx = ordered_to_float(b[0]), ly = ordered_to_float(b[1]), lz = ordered_to_float(b[2]);
+    const float hx = ordered_to_float(b[3]), hy = ordered_to_float(b[4]), hz = ordered_to_float(b[5]);
+    const uint32_t qx = quantise21(a.cent[j], lx, hx - lx);
+    const uint32_t qy = quantise21(a.cent[a.n_t + j], ly, hy - ly);
+    const uint32_t qz = quantise21(a.cent[2 * a.n_t + j], lz, hz - lz);
+    a.keys[j] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    a.order[j] = (uint32_t)j;
 }
 
 // Key distance between sorted neighbours k and k+1, compared
@@ -151,13 +227,13 @@ struct Climb {
     int32_t l, r, ref, h;
 };
 
-// The neighbour to join: across the split with the smaller key distance.
-// Returns the parent index (= that split position) and our side in it
-// (0: left child, 1: right child).
-__device__ inline int32_t choose_parent(const uint64_t *__restrict__ keys, int32_t n, int32_t l, int32_t r,
-                                        int &side)
+// The neighbour to join, within the mesh's leaf range [lo, hi]: across the
+// split with the smaller key distance.  Returns the parent index (= that
+// split position) and our side in it (0: left child, 1: right child).
+__device__ inline int32_t choose_parent(const uint64_t *__restrict__ keys, int32_t lo, int32_t hi, int32_t l,
+                                        int32_t r, int &side)
 {
-    if (l == 0 || (r != n - 1 && dist_less(keys, r, l - 1))) {
+    if (l == lo || (r != hi && dist_less(keys, r, l - 1))) {
         side = 0;
         return r;
     }
@@ -180,18 +256,19 @@ __device__ inline void merge(Climb &c, const float *g, int32_t other_bound, int3
     if (c.ref < 0) c.h = 0;  // a collapsed range is a leaf
 }
 
-// Entry node n-1: the root as its left child (the paper keeps the root as the
-// left child of its last internal node record), an empty far box on the right.
-__device__ inline void write_entry(Node *__restrict__ nodes, int32_t n, const Climb &c, int32_t *scalars)
+// Entry node `hi` (the mesh's last record): the root as its left child (the
+// paper keeps the root as the left child of its last internal node record),
+// an empty far box on the right.
+__device__ inline void write_entry(const BuildArgs &a, int32_t m, int32_t lo, int32_t hi, const Climb &c)
 {
-    Node *e = nodes + (n - 1);
+    Node *e = a.nodes + hi;
     write_child(e, 0, c.box, c.ref);
     const float far[6] = {FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX, FLT_MAX};
-    write_child(e, 1, far, leaf_ref(0, 1));
-    e->aux[0] = 0;
-    e->aux[1] = n - 1;
-    scalars[kHeight] = c.h;
-    scalars[kRootRef] = c.ref;
+    write_child(e, 1, far, leaf_ref(lo, 1));
+    e->aux[0] = lo;
+    e->aux[1] = hi;
+    a.mesh_height[m] = c.h;
+    a.mesh_root[m] = c.ref;
 }
 
 constexpr int kLocal = 256;   // leaves per workgroup in the local pass
@@ -202,13 +279,7 @@ constexpr int kClimbWords = 11;
 // so these subtrees are completed here with the arrival counters and child
 // records in LDS.  A climb that reaches a split outside the block (its parent
 // range crosses the block boundary) is saved for the global pass.
-__global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t *__restrict__ keys,
-                                                       const uint32_t *__restrict__ order,
-                                                       const float *__restrict__ V, int64_t n_v,
-                                                       const int32_t *__restrict__ T, Node *__restrict__ nodes,
-                                                       Tri *__restrict__ tris, int32_t *__restrict__ arrive,
-                                                       int32_t *__restrict__ heights, int32_t leaf_size,
-                                                       int32_t *__restrict__ scalars, int32_t *__restrict__ climb)
+__global__ __launch_bounds__(kLocal) void k_lbvh_local(BuildArgs a)
 {
     __shared__ int32_t lflag[kLocal];
     __shared__ float lbox[kLocal][12];
@@ -216,6 +287,7 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t
     __shared__ int32_t lbound[kLocal][2];
     __shared__ int32_t lh[kLocal][2];
     const int tid = threadIdx.x;
+    const int32_t n = (int32_t)a.n_t;
     const int32_t B0 = (int32_t)blockIdx.x * kLocal;
     const int32_t B1 = (B0 + kLocal < n ? B0 + kLocal : n) - 1;  // last leaf of this block
     lflag[tid] = 0;
@@ -224,27 +296,31 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t
     const int32_t i = B0 + tid;
     bool active = i < n;
     Climb c;
+    int32_t m = 0, lo = 0, hi = 0;
     if (active) {
+        m = mesh_of(a.off, a.M, i);
+        lo = (int32_t)a.off[m];
+        hi = (int32_t)a.off[m + 1] - 1;
         // leaf i: pack the triangle in sorted order and form its box
-        int32_t id = (int32_t)order[i];
-        if (id < 0 || id >= n) {  // cannot happen after a correct sort; never read outside T
-            atomicOr(&scalars[kBadIndex], 2);
-            id = 0;
+        int32_t id = (int32_t)a.order[i];
+        if (id < lo || id > hi) {  // cannot happen after a correct sort; never read outside T
+            atomicOr(&a.scalars[kBadIndex], 2);
+            id = lo;
         }
-        int32_t a = T[3 * id], b = T[3 * id + 1], d = T[3 * id + 2];
+        int32_t va = a.T[3 * id], vb = a.T[3 * id + 1], vd = a.T[3 * id + 2];
         // an out-of-range index is reported by k_centroids; read vertex 0
         // instead so that no access leaves the vertex array
-        if (a < 0 || a >= n_v) a = 0;
-        if (b < 0 || b >= n_v) b = 0;
-        if (d < 0 || d >= n_v) d = 0;
-        const float v0x = V[3 * a], v0y = V[3 * a + 1], v0z = V[3 * a + 2];
-        const float v1x = V[3 * b], v1y = V[3 * b + 1], v1z = V[3 * b + 2];
-        const float v2x = V[3 * d], v2y = V[3 * d + 1], v2z = V[3 * d + 2];
+        if (va < 0 || va >= a.n_v) va = 0;
+        if (vb < 0 || vb >= a.n_v) vb = 0;
+        if (vd < 0 || vd >= a.n_v) vd = 0;
+        const float v0x = a.V[3 * va], v0y = a.V[3 * va + 1], v0z = a.V[3 * va + 2];
+        const float v1x = a.V[3 * vb], v1y = a.V[3 * vb + 1], v1z = a.V[3 * vb + 2];
+        const float v2x = a.V[3 * vd], v2y = a.V[3 * vd + 1], v2z = a.V[3 * vd + 2];
         Tri tr;
         tr.a = make_float4(v0x, v0y, v0z, v1x);
         tr.b = make_float4(v1y, v1z, v2x, v2y);
-        tr.c = make_float4(v2z, __int_as_float(id), 0.0f, 0.0f);
-        tris[i] = tr;
+        tr.c = make_float4(v2z, __int_as_float(id - lo), 0.0f, 0.0f);  // id within its mesh
+        a.tris[i] = tr;
         c.box[0] = fminf(v0x, fminf(v1x, v2x));
         c.box[1] = fminf(v0y, fminf(v1y, v2y));
         c.box[2] = fminf(v0z, fminf(v1z, v2z));
@@ -254,19 +330,19 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t
         c.l = c.r = i;
         c.ref = leaf_ref(i, 1);
         c.h = 0;
-        climb[kClimbWords * (int64_t)i] = 0;  // no saved climb for this leaf unless set below
+        a.climb[kClimbWords * (int64_t)i] = 0;  // no saved climb for this leaf unless set below
     }
     // a climb inside the block takes fewer than kLocal steps
     for (int step = 0; active; ++step) {
-        if (c.l == 0 && c.r == n - 1) {  // the whole tree fits in this block
-            write_entry(nodes, n, c, scalars);
+        if (c.l == lo && c.r == hi) {  // the whole mesh fits in this block
+            write_entry(a, m, lo, hi, c);
             break;
         }
         int side;
-        const int32_t parent = choose_parent(keys, n, c.l, c.r, side);
+        const int32_t parent = choose_parent(a.keys, lo, hi, c.l, c.r, side);
         if (parent < B0 || parent >= B1 || step >= kLocal) {
             // the parent's range crosses the block boundary: hand over
-            int32_t *st = climb + kClimbWords * (int64_t)i;
+            int32_t *st = a.climb + kClimbWords * (int64_t)i;
             st[0] = 1;
             st[1] = c.l;
             st[2] = c.r;
@@ -286,22 +362,22 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t
             __hip_atomic_fetch_add(&lflag[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (prev == 0) break;  // the sibling finishes this parent
         const int other = 1 - side;
-        merge(c, &lbox[slot][6 * other], lbound[slot][other], lh[slot][other], side, parent, leaf_size);
+        merge(c, &lbox[slot][6 * other], lbound[slot][other], lh[slot][other], side, parent, a.leaf_size);
     }
     __syncthreads();
     // publish the block's internal node records (splits B0 .. B1-1)
     if (tid < B1 - B0 && lflag[tid] > 0) {
         const int32_t p = B0 + tid;
-        Node *q = nodes + p;
+        Node *q = a.nodes + p;
 #pragma unroll
         for (int k = 0; k < 12; ++k) q->f[k] = lbox[tid][k];
         q->ref[0] = lref[tid][0];
         q->ref[1] = lref[tid][1];
         q->aux[0] = lbound[tid][0];
         q->aux[1] = lbound[tid][1];
-        heights[2 * p] = lh[tid][0];
-        heights[2 * p + 1] = lh[tid][1];
-        arrive[p] = lflag[tid];
+        a.heights[2 * p] = lh[tid][0];
+        a.heights[2 * p + 1] = lh[tid][1];
+        a.arrive[p] = lflag[tid];
     }
 }
 
@@ -309,16 +385,15 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(int32_t n, const uint64_t
 // are shared between workgroups, so the arrival counter works at device
 // scope (the XCDs have separate L2 caches: release our writes, acquire the
 // sibling's).  Only the few subtrees that cross block boundaries remain.
-__global__ __launch_bounds__(256) void k_lbvh_global(int32_t n, const uint64_t *__restrict__ keys,
-                                                     Node *__restrict__ nodes, int32_t *__restrict__ arrive,
-                                                     int32_t *__restrict__ heights, int32_t leaf_size,
-                                                     int32_t *__restrict__ scalars,
-                                                     const int32_t *__restrict__ climb)
+__global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
 {
+    const int32_t n = (int32_t)a.n_t;
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= n) return;
-    const int32_t *st = climb + kClimbWords * (int64_t)i;
+    const int32_t *st = a.climb + kClimbWords * (int64_t)i;
     if (st[0] == 0) return;
+    const int32_t m = mesh_of(a.off, a.M, i);
+    const int32_t lo = (int32_t)a.off[m], hi = (int32_t)a.off[m + 1] - 1;
     Climb c;
     c.l = st[1];
     c.r = st[2];
@@ -327,69 +402,102 @@ __global__ __launch_bounds__(256) void k_lbvh_global(int32_t n, const uint64_t *
 #pragma unroll
     for (int k = 0; k < 6; ++k) c.box[k] = __int_as_float(st[5 + k]);
     // every step strictly widens [l, r], so at most n - 1 steps are needed
-    for (int32_t step = 0; !(c.l == 0 && c.r == n - 1); ++step) {
-        if (step >= n || c.l < 0 || c.r > n - 1 || c.l > c.r) {  // inconsistent: report, do not wander
-            atomicOr(&scalars[kBadIndex], 2);
+    for (int32_t step = 0; !(c.l == lo && c.r == hi); ++step) {
+        if (step >= n || c.l < lo || c.r > hi || c.l > c.r) {  // inconsistent: report, do not wander
+            atomicOr(&a.scalars[kBadIndex], 2);
             return;
         }
         int side;
-        const int32_t parent = choose_parent(keys, n, c.l, c.r, side);
-        Node *p = nodes + parent;
+        const int32_t parent = choose_parent(a.keys, lo, hi, c.l, c.r, side);
+        Node *p = a.nodes + parent;
         write_child(p, side, c.box, c.ref);
         p->aux[side] = side ? c.r : c.l;
-        heights[2 * parent + side] = c.h;
+        a.heights[2 * parent + side] = c.h;
         const int32_t prev =
-            __hip_atomic_fetch_add(&arrive[parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&a.arrive[parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == 0) return;  // the sibling finishes this parent
         const int other = 1 - side;
-        merge(c, p->f + 6 * other, p->aux[other], heights[2 * parent + other], side, parent, leaf_size);
+        merge(c, p->f + 6 * other, p->aux[other], a.heights[2 * parent + other], side, parent, a.leaf_size);
     }
-    write_entry(nodes, n, c, scalars);
+    write_entry(a, m, lo, hi, c);
+}
+
+BuildArgs make_build_args(rsi_bvh *h, const float *V)
+{
+    BuildArgs a;
+    a.M = h->M;
+    a.off = h->tri_off;
+    a.V = V;
+    a.n_v = h->n_v;
+    a.T = h->T;
+    a.n_t = h->n_t;
+    a.cent = h->cent;
+    a.keys = h->keys;
+    a.order = h->order;
+    a.nodes = h->nodes;
+    a.tris = h->tris;
+    a.arrive = h->arrive;
+    a.heights = h->heights;
+    a.climb = h->climb;
+    a.bounds = h->mesh_bounds;
+    a.mesh_height = h->mesh_height;
+    a.mesh_root = h->mesh_root;
+    a.scalars = h->scalars;
+    a.leaf_size = h->leaf_size;
+    return a;
+}
+
+hipError_t run_hierarchy(const BuildArgs &a, hipStream_t s)
+{
+    const int32_t n = (int32_t)a.n_t;
+    const unsigned nb = (unsigned)((n + kLocal - 1) / kLocal);
+    hipLaunchKernelGGL(k_lbvh_local, dim3(nb), dim3(kLocal), 0, s, a);
+    if (nb > 1) hipLaunchKernelGGL(k_lbvh_global, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+unsigned init_grid(const BuildArgs &a)
+{
+    const int64_t n = a.n_t > a.M ? a.n_t : a.M;
+    return (unsigned)((n + 255) / 256);
 }
 
 }  // namespace
 
-static hipError_t run_hierarchy(rsi_bvh *h, const float *V, hipStream_t s)
+hipError_t launch_gather(rsi_bvh *h, hipStream_t s)
 {
-    const int32_t n = (int32_t)h->n_t;
-    const unsigned nb = (unsigned)((n + kLocal - 1) / kLocal);
-    hipLaunchKernelGGL(k_lbvh_local, dim3(nb), dim3(kLocal), 0, s, n, h->keys, h->order, V, h->n_v, h->T,
-                       h->nodes, h->tris, h->arrive, h->heights, h->leaf_size, h->scalars, h->climb);
-    if (nb > 1)
-        hipLaunchKernelGGL(k_lbvh_global, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, h->keys,
-                           h->nodes, h->arrive, h->heights, h->leaf_size, h->scalars, h->climb);
+    const int64_t total = h->n_v + h->n_t;
+    if (total == 0) return hipSuccess;
+    int64_t grid = (total + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_clear_gather_flag, dim3(1), dim3(1), 0, s, h->scalars);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)grid), dim3(256), 0, s, h->M, h->src_V, h->src_T, h->vert_off,
+                       h->tri_off, h->V_all, h->T, h->scalars);
     return hipGetLastError();
-}
-
-static hipError_t run_lbvh(rsi_bvh *h, const float *V, hipStream_t s)
-{
-    const int32_t n = (int32_t)h->n_t;
-    const int blk = 256;
-    hipLaunchKernelGGL(k_init, dim3((unsigned)((n + blk - 1) / blk)), dim3(blk), 0, s, h->scalars, h->arrive,
-                       (int64_t)n);
-    return run_hierarchy(h, V, s);
 }
 
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
 {
     const int64_t n = h->n_t;
     if (n == 0) return hipSuccess;
-    const int blk = 256;
-    const unsigned grid = (unsigned)((n + blk - 1) / blk);
-    hipLaunchKernelGGL(k_init, dim3(grid), dim3(blk), 0, s, h->scalars, h->arrive, n);
-    hipLaunchKernelGGL(k_centroids, dim3(grid), dim3(blk), 0, s, V, h->n_v, h->T, n, h->cent, h->scalars);
-    hipLaunchKernelGGL(k_morton, dim3(grid), dim3(blk), 0, s, h->cent, n, h->scalars, h->keys, h->order);
+    const BuildArgs a = make_build_args(h, V);
+    hipLaunchKernelGGL(k_init, dim3(init_grid(a)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_centroids, dim3((unsigned)((n + kCentBlock - 1) / kCentBlock)), dim3(kCentBlock), 0, s,
+                       a);
+    hipLaunchKernelGGL(k_morton, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = radix_sort_pairs(h->keys, h->order, n, 63, h->sort, s);
+    e = radix_sort_pairs(h->keys, h->order, n, 63, h->sort, s, h->M > 1 ? h->tri_off : nullptr, h->M);
     if (e != hipSuccess) return e;
-    return run_hierarchy(h, V, s);
+    return run_hierarchy(a, s);
 }
 
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)
 {
     if (h->n_t == 0) return hipSuccess;
-    return run_lbvh(h, V, s);
+    const BuildArgs a = make_build_args(h, V);
+    hipLaunchKernelGGL(k_init, dim3(init_grid(a)), dim3(256), 0, s, a);
+    return run_hierarchy(a, s);
 }
 
 }  // namespace rsi

@@ -61,10 +61,17 @@ struct QArgs {
     float *pool_ts;
     Counters *counters;
     int32_t depth;       // stack entries per lane (tree height + 1)
+    int32_t lds_depth;   // of which the first lds_depth live in LDS, the rest in gstack
+    int32_t *gstack;     // [(depth - lds_depth) x resident threads], laid out [entry][thread]
+    int64_t gstack_cap;  // entries in gstack
     int32_t max_steps;   // node visits of one segment never exceed the node count
     int32_t defer;       // test pending leaves once fewer lanes than this can step
     int32_t refill;      // fetch new segments once this many lanes are idle
     int32_t chunk;       // work items a wave claims per atomic on the global counter
+    // batched queries: work item k belongs to mesh m with bt.seg_off[m] <= k < bt.seg_off[m+1]
+    int32_t M;
+    const int32_t *mesh_entry;
+    BatchTables bt;
 };
 
 __device__ inline void wave_add_u64(unsigned long long *dst, unsigned long long v)
@@ -87,8 +94,11 @@ struct Lane {
     int32_t best_pos;
     int32_t count;     // crossings found (all hits)
     int32_t spill_cap; // pool entries reserved for this segment (spill pass)
-    int64_t seg_i;     // segment index
+    int64_t seg_i;     // segment index (within its mesh for batched queries)
     int64_t slot_base; // first slot of this segment (all hits) or pool offset (spill)
+    const float *sp;   // this segment's start and end (3 floats each)
+    const float *ep;
+    int32_t mesh;      // batched queries: the segment's mesh
     bool found;
 };
 
@@ -166,12 +176,12 @@ __device__ inline void refine_list(const QArgs &a, double sx, double sy, double 
 }
 
 // Write the results of a finished segment.
-template <uint32_t MODE, bool SPILL>
+template <uint32_t MODE, bool SPILL, bool BATCH>
 __device__ inline void finish(const QArgs &a, const Lane &L)
 {
     const int64_t i = L.seg_i;
-    const float sx = a.S[3 * i], sy = a.S[3 * i + 1], sz = a.S[3 * i + 2];
-    const float ex = a.E[3 * i], ey = a.E[3 * i + 1], ez = a.E[3 * i + 2];
+    const float sx = L.sp[0], sy = L.sp[1], sz = L.sp[2];
+    const float ex = L.ep[0], ey = L.ep[1], ez = L.ep[2];
     if (SPILL) {
         const int n = L.count < L.spill_cap ? L.count : L.spill_cap;
         int32_t *ids = a.pool_ids + L.slot_base;
@@ -187,29 +197,36 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         }
         return;
     }
-    if (MODE & M_BOOL) a.o.hit[i] = L.found ? 1 : 0;
+    if (MODE & M_BOOL) {
+        uint8_t *hit = BATCH ? a.bt.hit[L.mesh] : a.o.hit;
+        hit[i] = L.found ? 1 : 0;
+    }
     if (MODE & M_FIRST) {
+        int32_t *tri = BATCH ? a.bt.tri[L.mesh] : a.o.tri;
+        float *tt = BATCH ? a.bt.t[L.mesh] : a.o.t;
+        float *uv = BATCH ? a.bt.uv[L.mesh] : a.o.uv;
+        float *pt = BATCH ? a.bt.point[L.mesh] : a.o.point;
         if (L.best_pos >= 0) {
             float v[9];
             int32_t id;
             tri_load(a.tris, L.best_pos, v, id);
             double t, u, w;
             mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-            a.o.tri[i] = id;
-            a.o.t[i] = (float)t;
-            a.o.uv[2 * i] = (float)u;
-            a.o.uv[2 * i + 1] = (float)w;
-            a.o.point[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
-            a.o.point[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
-            a.o.point[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
+            tri[i] = id;
+            tt[i] = (float)t;
+            uv[2 * i] = (float)u;
+            uv[2 * i + 1] = (float)w;
+            pt[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
+            pt[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
+            pt[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
         } else {
-            a.o.tri[i] = -1;
-            a.o.t[i] = INFINITY;
-            a.o.uv[2 * i] = 0.0f;
-            a.o.uv[2 * i + 1] = 0.0f;
-            a.o.point[3 * i] = 0.0f;
-            a.o.point[3 * i + 1] = 0.0f;
-            a.o.point[3 * i + 2] = 0.0f;
+            tri[i] = -1;
+            tt[i] = INFINITY;
+            uv[2 * i] = 0.0f;
+            uv[2 * i + 1] = 0.0f;
+            pt[3 * i] = 0.0f;
+            pt[3 * i + 1] = 0.0f;
+            pt[3 * i + 2] = 0.0f;
         }
     }
     if (MODE & M_ALL) {
@@ -239,13 +256,16 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
     }
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT>
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH>
 __global__ __launch_bounds__(256) void k_query(QArgs a)
 {
     extern __shared__ int32_t lds_stack[];
     int32_t *const stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
     int32_t *const work = &a.scalars[kWorkNext];
+    // stack entry k >= lds_depth lives at gstack[(k - lds_depth) * gstride + gtid]
+    const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
     Lane L;
     int64_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
@@ -268,7 +288,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         if (waiting != 0 &&
             ((int)__popcll(waiting) >= a.refill || __ballot(item >= 0 && !done) == 0)) {
             if (done) {
-                finish<MODE, SPILL>(a, L);
+                finish<MODE, SPILL, BATCH>(a, L);
                 item = -1;
             }
             const uint64_t idle = __ballot(item == -1);
@@ -299,6 +319,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 if (k >= 0) {
                     item = k;
                     int64_t i = k;
+                    int32_t entry = a.entry;
                     L.slot_base = (MODE & M_ALL) ? k * (int64_t)a.o.cap : 0;
                     L.spill_cap = 0;
                     if (SPILL) {
@@ -306,16 +327,27 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                         L.slot_base = a.ovf_off[k];
                         L.spill_cap = a.ovf_cnt[k];
                     }
+                    if (BATCH) {
+                        const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
+                        i = k - a.bt.seg_off[m];
+                        L.mesh = m;
+                        L.sp = a.bt.S[m] + 3 * i;
+                        L.ep = a.bt.E[m] + 3 * i;
+                        entry = a.mesh_entry[m];
+                    } else {
+                        L.mesh = 0;
+                        L.sp = a.S + 3 * i;
+                        L.ep = a.E + 3 * i;
+                    }
                     L.seg_i = i;
-                    L.seg = make_seg(a.S[3 * i], a.S[3 * i + 1], a.S[3 * i + 2], a.E[3 * i], a.E[3 * i + 1],
-                                     a.E[3 * i + 2]);
+                    L.seg = make_seg(L.sp[0], L.sp[1], L.sp[2], L.ep[0], L.ep[1], L.ep[2]);
                     L.tlim = 1.0f;
                     L.best_t = INFINITY;
                     L.best_id = 0x7FFFFFFF;
                     L.best_pos = -1;
                     L.count = 0;
                     L.found = false;
-                    node = a.entry;
+                    node = entry;  // < 0 for an empty mesh: the segment misses
                     sp = 0;
                     steps = 0;
                     if (COUNT) ++segs;
@@ -351,7 +383,9 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             const bool gr = hr && cr >= 0;
             if (gl && gr && sp < a.depth) {
                 const bool left_first = tl <= tr;
-                stk[sp * stride] = left_first ? cr : cl;
+                const int32_t far_child = left_first ? cr : cl;
+                if (sp < a.lds_depth) stk[sp * stride] = far_child;
+                else a.gstack[(int64_t)(sp - a.lds_depth) * gstride + gtid] = far_child;
                 ++sp;
                 node = left_first ? cl : cr;
             } else if (gl) {
@@ -360,7 +394,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 node = cr;
             } else if (sp > 0) {
                 --sp;
-                node = stk[sp * stride];
+                node = sp < a.lds_depth ? stk[sp * stride] : a.gstack[(int64_t)(sp - a.lds_depth) * gstride + gtid];
             } else {
                 node = -1;
             }
@@ -422,10 +456,10 @@ __global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
     if (c) c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT>
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH = false>
 hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    auto kern = k_query<MODE, SPILL, COUNT>;
+    auto kern = k_query<MODE, SPILL, COUNT, BATCH>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess) return e;
@@ -437,6 +471,10 @@ hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
     const int64_t need = (a.n_items + block - 1) / block;
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
+    // the global part of the stack must hold every resident thread's column
+    if (a.lds_depth < a.depth && (a.gstack == nullptr || grid * block * (int64_t)(a.depth - a.lds_depth) >
+                                                             a.gstack_cap))
+        return hipErrorInvalidValue;
     QArgs b = a;
     if (b.chunk <= 0) {
         // about eight chunks per resident wave keeps the tail short while the
@@ -467,7 +505,7 @@ hipError_t dispatch(uint32_t mode, const QArgs &a, int block, size_t lds, hipStr
 }
 
 // Largest multiple of 64 not above `want` (and at most 256, the kernels'
-// launch bound) whose stack fits in 64 KiB of LDS.
+// launch bound) whose LDS part of the stack fits in 64 KiB.
 int fit_block(int want, int depth)
 {
     int b = want < 256 ? want : 256;
@@ -475,12 +513,19 @@ int fit_block(int want, int depth)
     return b;
 }
 
+// LDS part of the stack: the whole stack unless a smaller cap is set.
+int lds_part(const rsi_bvh *h)
+{
+    const int depth = h->height + 1;
+    return (h->stack_cap > 0 && h->stack_cap < depth) ? h->stack_cap : depth;
+}
+
 QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, const QueryOut &o)
 {
     QArgs a;
     a.nodes = h->nodes;
     a.tris = h->tris;
-    a.entry = h->entry;
+    a.entry = h->n_t > 0 ? (int32_t)(h->h_tri_off[1] - 1) : -1;
     a.S = S;
     a.E = E;
     a.n_items = n_items;
@@ -494,10 +539,16 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.pool_ts = h->pool_ts;
     a.counters = h->counters;
     a.depth = h->height + 1;
+    a.lds_depth = lds_part(h);
+    a.gstack = h->gstack;
+    a.gstack_cap = h->gstack_cap;
     a.max_steps = (int32_t)(h->n_t + 1);
     a.defer = h->defer_lanes;
     a.refill = h->refill_lanes;
     a.chunk = h->chunk;
+    a.M = h->M;
+    a.mesh_entry = h->mesh_entry;
+    a.bt = h->bt;
     return a;
 }
 
@@ -507,9 +558,9 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
                         const QueryOut &o, hipStream_t s)
 {
     if (n_r == 0) return hipSuccess;
-    const int depth = h->height + 1;
-    const int block = fit_block(h->block_size, depth);
-    const size_t lds = (size_t)block * depth * sizeof(int32_t);
+    const int ld = lds_part(h);
+    const int block = fit_block(h->block_size, ld);
+    const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n_r, o);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, (mode & M_ALL) ? 1 : 0,
                        h->counting ? h->counters : nullptr);
@@ -523,12 +574,51 @@ hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mod
     (void)mode;
     const int64_t n = h->last_ovf_segs;
     if (n == 0) return hipSuccess;
-    const int depth = h->height + 1;
-    const int block = fit_block(h->block_size, depth);
-    const size_t lds = (size_t)block * depth * sizeof(int32_t);
+    const int ld = lds_part(h);
+    const int block = fit_block(h->block_size, ld);
+    const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n, o);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
     return launch_mode<M_ALL, true, false>(a, block, lds, s);
+}
+
+hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s)
+{
+    if (n_total == 0) return hipSuccess;
+    const int ld = lds_part(h);
+    const int block = fit_block(h->block_size, ld);
+    const size_t lds = (size_t)block * ld * sizeof(int32_t);
+    QueryOut o = {};
+    QArgs a = make_args(h, nullptr, nullptr, n_total, o);
+    a.bt = bt;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
+    switch (mode) {
+    case M_BOOL: return launch_mode<M_BOOL, false, false, true>(a, block, lds, s);
+    case M_FIRST: return launch_mode<M_FIRST, false, false, true>(a, block, lds, s);
+    case M_FIRST | M_BOOL: return launch_mode<M_FIRST | M_BOOL, false, false, true>(a, block, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t ensure_gstack(rsi_bvh *h)
+{
+    const int depth = h->height + 1;
+    const int ld = lds_part(h);
+    if (ld >= depth) return hipSuccess;
+    int dev = 0, n_cu = 0, max_threads = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_threads, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev);
+    if (e != hipSuccess) return e;
+    // every thread the GPU can hold at once, times the entries beyond the LDS part
+    const int64_t need = (int64_t)n_cu * max_threads * (depth - ld);
+    if (h->gstack_cap >= need) return hipSuccess;
+    if (h->gstack) (void)hipFree(h->gstack);
+    h->gstack = nullptr;
+    h->gstack_cap = 0;
+    e = hipMalloc(reinterpret_cast<void **>(&h->gstack), sizeof(int32_t) * (size_t)need);
+    if (e == hipSuccess) h->gstack_cap = need;
+    return e;
 }
 
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s)

@@ -177,6 +177,20 @@ __device__ inline void mt_refine64(double sx, double sy, double sz, double ex, d
     t = (e2x * qx + e2y * qy + e2z * qz) * inv;
 }
 
+// Index of the segment of a partition that holds item j: the largest m with
+// off[m] <= j, for a table of M + 1 nondecreasing offsets (meshes of a batch
+// over triangles, nodes or segments).
+__device__ inline int32_t mesh_of(const int64_t *__restrict__ off, int32_t M, int64_t j)
+{
+    int32_t lo = 0, hi = M - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Order-preserving int encoding of floats for atomic min / max.
 __device__ inline int32_t float_to_ordered(float f)
 {

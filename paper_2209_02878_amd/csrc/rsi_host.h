@@ -6,18 +6,16 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "rsi_device.h"
 
 namespace rsi {
 
-// Device scalars written by the build (one small array, read back once).
+// Device scalars of a handle (one small array, read back when needed).
 enum Scalar {
-    kBoundLo = 0,      // 3 ordered-int centroid minima
-    kBoundHi = 3,      // 3 ordered-int centroid maxima
-    kBadIndex = 6,     // nonzero if a triangle index was out of range
-    kHeight = 7,       // levels of internal nodes below the entry node
-    kRootRef = 8,      // reference of the root (internal index or leaf ref)
+    kBadIndex = 6,     // nonzero if a triangle index was out of range (1) or the build state was inconsistent (2)
+    kBadGather = 7,    // nonzero if a batch gather met a triangle index outside its mesh
     kOvfSegs = 9,      // overflowed segments of the last all-hits pass
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments (lo, hi words)
     kOvfTotalHi = 11,
@@ -38,27 +36,54 @@ struct SortScratch {
     int64_t hist_cap = 0;
 };
 
+// Per-mesh tables of a batched query (device arrays, one entry per mesh).
+struct BatchTables {
+    int64_t *seg_off = nullptr;        // [M+1] segment offsets of the work items
+    const float **S = nullptr;         // [M] segment starts of each mesh
+    const float **E = nullptr;
+    uint8_t **hit = nullptr;
+    int32_t **tri = nullptr;
+    float **t = nullptr;
+    float **uv = nullptr;
+    float **point = nullptr;
+};
+
 }  // namespace rsi
 
+// A handle owns the trees of M >= 1 meshes in concatenated arrays: mesh m
+// owns triangles, sorted leaves and node records [tri_off[m], tri_off[m+1]).
 struct rsi_bvh {
     int device = 0;
-    int64_t n_v = 0, n_t = 0;
+    int32_t M = 1;
+    int64_t n_v = 0, n_t = 0;      // totals over all meshes
     int32_t leaf_size = 1;
-    int32_t block_size = 256;
+    int32_t block_size = 128;
     int32_t defer_lanes = 32;
     int32_t refill_lanes = 32;
-    int32_t chunk = 0;  // 0: sized per launch
-    int32_t height = 0;
-    int32_t root_ref = 0;
-    int32_t entry = 0;
+    int32_t chunk = 0;             // 0: sized per launch
+    int32_t stack_cap = 0;         // LDS part of the traversal stack (0: the whole stack)
+    int32_t height = 0;            // largest tree height over the meshes
     bool counting = false;
+    std::vector<int64_t> h_tri_off, h_vert_off;  // host copies of the offsets
+    std::vector<int32_t> h_height, h_root;
+
+    // mesh tables (device)
+    int64_t *tri_off = nullptr;    // [M+1]
+    int64_t *vert_off = nullptr;   // [M+1]
+    int32_t *mesh_bounds = nullptr;  // [6M]
+    int32_t *mesh_height = nullptr;  // [M]
+    int32_t *mesh_root = nullptr;    // [M]
+    int32_t *mesh_entry = nullptr;   // [M] entry node per mesh, -1 for an empty mesh
 
     // geometry and tree (device)
-    int32_t *T = nullptr;          // copy of the index triplets [n_t*3]
+    int32_t *T = nullptr;          // index triplets with global vertex indices [n_t*3]
+    float *V_all = nullptr;        // concatenated vertices (batches only) [n_v*3]
+    const float **src_V = nullptr; // batches: the caller's per-mesh vertex pointers [M]
+    const int32_t **src_T = nullptr;
     float *cent = nullptr;         // centroids SoA [3*n_t]
     uint64_t *keys = nullptr;      // Morton codes, sorted in place [n_t]
-    uint32_t *order = nullptr;     // original id per sorted position [n_t]
-    rsi::Node *nodes = nullptr;    // [max(n_t, 1)]; node n_t-1 is the entry node
+    uint32_t *order = nullptr;     // original triangle per sorted position [n_t]
+    rsi::Node *nodes = nullptr;    // [max(n_t, 1)]; each mesh's last record is its entry node
     rsi::Tri *tris = nullptr;      // [n_t] in sorted order
     int32_t *arrive = nullptr;     // arrival counters [n_t]
     int32_t *heights = nullptr;    // child heights [2*n_t]
@@ -78,6 +103,18 @@ struct rsi_bvh {
     int64_t last_ovf_segs = 0;
     int64_t last_ovf_total = 0;
 
+    // batched queries (device tables, sized for M meshes): `bt` serves the
+    // eager calls, `bt_graph` belongs to the captured graph, so an eager call
+    // never rewrites what a replay reads
+    rsi::BatchTables bt;
+    rsi::BatchTables bt_graph;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t capture_stream = nullptr;
+
+    // global part of the traversal stack when stack_cap is below the height
+    int32_t *gstack = nullptr;
+    int64_t gstack_cap = 0;
+
     // pinned host mirror of `scalars`
     int32_t *h_scalars = nullptr;
 };
@@ -88,12 +125,15 @@ namespace rsi {
 void set_error(const std::string &msg);
 
 // build.hip
+hipError_t launch_gather(rsi_bvh *h, hipStream_t s);
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s);
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s);
 
-// sort.hip: stable LSD radix sort of 63-bit keys with 32-bit values, in place
-hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits,
-                            SortScratch &scratch, hipStream_t s);
+// sort.hip: stable LSD radix sort of 63-bit keys with 32-bit values, in
+// place; with mesh_off (M > 1) the mesh of each value is the most
+// significant digit
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &scratch,
+                            hipStream_t s, const int64_t *mesh_off = nullptr, int32_t M = 1);
 hipError_t ensure_sort_scratch(SortScratch &scratch, int64_t n);
 void free_sort_scratch(SortScratch &scratch);
 
@@ -111,6 +151,9 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
 hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mode, const QueryOut &o,
                         hipStream_t s);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);
+hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s);
+// size the global part of the traversal stack (call outside graph capture)
+hipError_t ensure_gstack(rsi_bvh *h);
 
 // adjoint.hip
 hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, const float *E, int64_t n_r,

@@ -29,7 +29,21 @@ constexpr int kRadix = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kFusedTiles = 64;  // up to this many tiles each workgroup scans the histograms itself
 
-__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+// Digit of an element for one pass: 8 bits of the key, or (for batches)
+// 8 bits of the mesh that the element's value (a triangle index) belongs to.
+struct Digit {
+    const int64_t *off;  // null: key digits
+    int32_t M;
+    int shift;
+    __device__ inline uint32_t operator()(uint64_t key, uint32_t val) const
+    {
+        if (off) return ((uint32_t)mesh_of(off, M, (int64_t)val) >> shift) & (kRadix - 1);
+        return (uint32_t)(key >> shift) & (kRadix - 1);
+    }
+};
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ vals, int64_t n, Digit dg,
                                                    uint32_t *__restrict__ hist, int ntiles)
 {
     __shared__ uint32_t h[kRadix];
@@ -40,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         int64_t i = base + r * kThreads + tid;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+        if (i < n) atomicAdd(&h[dg(keys[i], dg.off ? vals[i] : 0u)], 1u);
     }
     __syncthreads();
     hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
@@ -109,7 +123,7 @@ template <bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                      int64_t n, int shift, const uint32_t *__restrict__ offs,
+                                                      int64_t n, Digit dg, const uint32_t *__restrict__ offs,
                                                       int ntiles)
 {
     __shared__ uint32_t run[kRadix];          // elements of each digit ranked so far in this tile
@@ -155,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         const bool valid = i < n;
         key[r] = valid ? kin[i] : 0ull;
         val[r] = valid ? vin[i] : 0u;
-        const uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+        const uint32_t d = valid ? dg(key[r], val[r]) : 0u;
         dig[r] = d;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
@@ -201,10 +215,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     const int cnt = rem < kTile ? (int)rem : kTile;
     for (int p = tid; p < cnt; p += kThreads) {
         const uint64_t k = skey[p];
-        const uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+        const uint32_t v = sval[p];
+        const uint32_t d = dg(k, v);
         const int64_t dst = (int64_t)gbase[d] + (p - start[d]);
         kout[dst] = k;
-        vout[dst] = sval[p];
+        vout[dst] = v;
     }
 }
 
@@ -254,24 +269,32 @@ void free_sort_scratch(SortScratch &sc)
 }
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &sc,
-                            hipStream_t s)
+                            hipStream_t s, const int64_t *mesh_off, int32_t M)
 {
     if (n <= 1) return hipSuccess;
     hipError_t e = ensure_sort_scratch(sc, n);
     if (e != hipSuccess) return e;
     const int ntiles = (int)((n + kTile - 1) / kTile);
-    const int passes = (key_bits + 7) / 8;
+    // key digits first, then (batches) the mesh id as the most significant
+    // digits, so each mesh's elements end up contiguous in key order
+    Digit passes[16];
+    int np = 0;
+    for (int p = 0; p < (key_bits + 7) / 8; ++p) passes[np++] = Digit{nullptr, 0, 8 * p};
+    if (mesh_off && M > 1) {
+        passes[np++] = Digit{mesh_off, M, 0};
+        if (M > 256) passes[np++] = Digit{mesh_off, M, 8};
+    }
     uint64_t *ka = keys, *kb = sc.keys_alt;
     uint32_t *va = vals, *vb = sc.vals_alt;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, n, shift, sc.hist, ntiles);
+    for (int p = 0; p < np; ++p) {
+        const Digit dg = passes[p];
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles);
         if (ntiles <= kFusedTiles) {
-            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift,
+            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
                                sc.hist, ntiles);
         } else {
             hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, (int64_t)ntiles * kRadix);
-            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, shift,
+            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
                                sc.hist, ntiles);
         }
         uint64_t *tk = ka; ka = kb; kb = tk;

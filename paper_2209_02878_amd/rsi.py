@@ -25,7 +25,9 @@ MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS}
 EXPORTED = [
     "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_first_hit_backward",
     "rsi_spill_info", "rsi_spill_read",
-    "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_export_tree",
+    "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_get_mesh_info", "rsi_export_tree",
+    "rsi_batch_create", "rsi_batch_rebuild", "rsi_batch_query", "rsi_batch_capture", "rsi_batch_replay",
+    "rsi_set_opts", "rsi_get_opts", "rsi_tune",
     "rsi_destroy", "rsi_status_str", "rsi_last_error",
 ]
 
@@ -39,7 +41,14 @@ class RsiError(RuntimeError):
 class rsi_opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("defer_lanes", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("chunk", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+class rsi_tune_job(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_void_p), ("n_v", ctypes.c_int64), ("T", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("n_r", ctypes.c_int64), ("out", ctypes.c_void_p), ("bS", ctypes.c_void_p),
+                ("bE", ctypes.c_void_p), ("b_nr", ctypes.c_void_p), ("b_outs", ctypes.c_void_p),
+                ("mode", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
 class rsi_outputs(ctypes.Structure):
@@ -56,7 +65,7 @@ class rsi_counters(ctypes.Structure):
 
 class rsi_tree_info(ctypes.Structure):
     _fields_ = [("n_t", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("height", ctypes.c_int32),
-                ("leaf_size", ctypes.c_int32), ("entry", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("leaf_size", ctypes.c_int32), ("entry", ctypes.c_int32), ("n_meshes", ctypes.c_int32)]
 
 
 _lib = None
@@ -84,6 +93,15 @@ def lib():
     L.rsi_get_counters.argtypes = [H, ctypes.POINTER(rsi_counters)]
     L.rsi_get_tree_info.argtypes = [H, ctypes.POINTER(rsi_tree_info)]
     L.rsi_export_tree.argtypes = [H, P, P, P, P]
+    L.rsi_get_mesh_info.argtypes = [H, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.rsi_batch_create.argtypes = [i32, P, P, P, P, ctypes.POINTER(rsi_opts), P, ctypes.POINTER(H)]
+    L.rsi_batch_rebuild.argtypes = [H, P]
+    L.rsi_batch_query.argtypes = [H, P, P, P, u32, P, P]
+    L.rsi_batch_capture.argtypes = [H, P, P, P, u32, P, ctypes.c_int, P]
+    L.rsi_batch_replay.argtypes = [H, P]
+    L.rsi_set_opts.argtypes = [H, ctypes.POINTER(rsi_opts)]
+    L.rsi_get_opts.argtypes = [H, ctypes.POINTER(rsi_opts)]
+    L.rsi_tune.argtypes = [H, ctypes.POINTER(rsi_tune_job), P, i32, i32, P, ctypes.POINTER(i32), P]
     L.rsi_destroy.argtypes = [H]
     L.rsi_destroy.restype = None
     L.rsi_status_str.argtypes = [ctypes.c_int]
@@ -208,7 +226,13 @@ def rsi_get_tree_info(h):
     t = rsi_tree_info()
     _check(lib().rsi_get_tree_info(h, ctypes.byref(t)))
     return {"n_t": t.n_t, "n_nodes": t.n_nodes, "height": t.height, "leaf_size": t.leaf_size,
-            "entry": t.entry}
+            "entry": t.entry, "n_meshes": t.n_meshes}
+
+
+def rsi_get_mesh_info(h, mesh):
+    off, n, ht = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().rsi_get_mesh_info(h, mesh, ctypes.byref(off), ctypes.byref(n), ctypes.byref(ht)))
+    return {"tri_offset": off.value, "n_t": n.value, "height": ht.value}
 
 
 def rsi_export_tree(h):
@@ -224,6 +248,36 @@ def rsi_export_tree(h):
                                  order.ctypes.data_as(P), keys.ctypes.data_as(P)))
     return {"boxes": boxes[:n], "refs": refs[:n], "order": order[:info["n_t"]], "keys": keys[:info["n_t"]],
             **info}
+
+
+OPT_FIELDS = ("leaf_size", "block_size", "defer_lanes", "refill_lanes", "chunk", "stack_depth")
+
+
+def make_opts(d=None):
+    d = d or {}
+    return rsi_opts(*[int(d.get(k, 0)) for k in OPT_FIELDS])
+
+
+def rsi_set_opts(h, **opts):
+    o = make_opts(opts)
+    _check(lib().rsi_set_opts(h, ctypes.byref(o)))
+
+
+def rsi_get_opts(h):
+    o = rsi_opts()
+    _check(lib().rsi_get_opts(h, ctypes.byref(o)))
+    return {k: getattr(o, k) for k in OPT_FIELDS}
+
+
+def rsi_tune(h, job, candidates, reps=5, stream=None):
+    """Time each candidate (list of option dicts) on `job`, apply the fastest.
+    Returns (best index, list of median milliseconds)."""
+    cand = (rsi_opts * len(candidates))(*[make_opts(c) for c in candidates])
+    ms = (ctypes.c_float * len(candidates))()
+    best = ctypes.c_int32()
+    _check(lib().rsi_tune(h, ctypes.byref(job), ctypes.cast(cand, ctypes.c_void_p), len(candidates), reps,
+                          ctypes.cast(ms, ctypes.c_void_p), ctypes.byref(best), _stream(stream)))
+    return best.value, list(ms)
 
 
 def rsi_destroy(h):
@@ -308,6 +362,22 @@ class Mesh:
     def set_counting(self, enable=True):
         rsi_set_counting(self.handle, enable)
 
+    def set_opts(self, **opts):
+        rsi_set_opts(self.handle, **opts)
+
+    def opts(self):
+        return rsi_get_opts(self.handle)
+
+    def tune(self, S, E, mode, candidates, capacity=4, reps=5, stream=None):
+        """Autotune on a real query of (S, E); the fastest candidate stays applied."""
+        mode = parse_mode(mode)
+        out = self.alloc_outputs(S.shape[0], mode, capacity, S.device)
+        o = self.outputs_struct(out, capacity)
+        job = rsi_tune_job(_ptr(self.V), self.V.shape[0], _ptr(self.T), _ptr(_dev_f32(S, "S")),
+                           _ptr(_dev_f32(E, "E")), S.shape[0], ctypes.cast(ctypes.pointer(o), ctypes.c_void_p),
+                           None, None, None, None, mode, 0)
+        return rsi_tune(self.handle, job, candidates, reps, stream)
+
     def counters(self):
         return rsi_get_counters(self.handle)
 
@@ -316,6 +386,116 @@ class Mesh:
 
     def tree_info(self):
         return rsi_get_tree_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            rsi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None and t.numel() else 0
+                                             for t in tensors])
+    return arr
+
+
+class Batch:
+    """Many meshes in one handle: one build launch per stage for all of them,
+    one persistent query launch over every (mesh, segment) item, and an
+    optional HIP graph of rebuild + query replayed with one launch."""
+
+    def __init__(self, meshes, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0):
+        self.meshes = [(_dev_f32(V, "V"), _dev_i32(T, "T")) for V, T in meshes]
+        M = len(self.meshes)
+        self._V = _ptr_array([V for V, _ in self.meshes])
+        self._T = _ptr_array([T for _, T in self.meshes])
+        self._nv = (ctypes.c_int64 * M)(*[V.shape[0] for V, _ in self.meshes])
+        self._nt = (ctypes.c_int64 * M)(*[T.shape[0] for _, T in self.meshes])
+        o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk)
+        h = ctypes.c_void_p()
+        _check(lib().rsi_batch_create(M, ctypes.cast(self._V, ctypes.c_void_p), ctypes.cast(self._nv, ctypes.c_void_p),
+                                      ctypes.cast(self._T, ctypes.c_void_p), ctypes.cast(self._nt, ctypes.c_void_p),
+                                      ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+        self._graph_keep = None
+
+    @property
+    def n_meshes(self):
+        return len(self.meshes)
+
+    def rebuild(self, stream=None):
+        _check(lib().rsi_batch_rebuild(self.handle, _stream(stream)))
+
+    def alloc_outputs(self, segments, mode):
+        mode = parse_mode(mode)
+        outs = []
+        for S, _ in segments:
+            n = S.shape[0]
+            d = {}
+            if mode & RSI_BOOL:
+                d["hit"] = torch.empty(n, dtype=torch.uint8, device=S.device)
+            if mode & RSI_FIRST_HIT:
+                d["tri"] = torch.empty(n, dtype=torch.int32, device=S.device)
+                d["t"] = torch.empty(n, dtype=torch.float32, device=S.device)
+                d["uv"] = torch.empty(n, 2, dtype=torch.float32, device=S.device)
+                d["point"] = torch.empty(n, 3, dtype=torch.float32, device=S.device)
+            outs.append(d)
+        return outs
+
+    def _tables(self, segments, mode, outs, keep="_keep"):
+        if len(segments) != self.n_meshes or len(outs) != self.n_meshes:
+            raise ValueError("one (S, E) pair and one output dict per mesh")
+        segs = [(_dev_f32(S, "S"), _dev_f32(E, "E")) for S, E in segments]
+        S = _ptr_array([s for s, _ in segs])
+        E = _ptr_array([e for _, e in segs])
+        n = (ctypes.c_int64 * self.n_meshes)(*[s.shape[0] for s, _ in segs])
+        o = (rsi_outputs * self.n_meshes)(*[Mesh.outputs_struct(d, 1) for d in outs])
+        setattr(self, keep, (segs, outs, S, E, n, o))  # buffers the launch (or graph) refers to
+        c = lambda x: ctypes.cast(x, ctypes.c_void_p)
+        return c(S), c(E), c(n), parse_mode(mode), c(o)
+
+    def query_into(self, segments, mode, outs, stream=None):
+        S, E, n, m, o = self._tables(segments, mode, outs)
+        _check(lib().rsi_batch_query(self.handle, S, E, n, m, o, _stream(stream)))
+        return outs
+
+    def query(self, segments, mode="bool", stream=None):
+        outs = self.alloc_outputs(segments, mode)
+        return self.query_into(segments, mode, outs, stream)
+
+    def capture(self, segments, mode, outs, rebuild=True, stream=None):
+        # the graph keeps its own tables on the device; keep its buffers alive here
+        S, E, n, m, o = self._tables(segments, mode, outs, keep="_graph_keep")
+        _check(lib().rsi_batch_capture(self.handle, S, E, n, m, o, 1 if rebuild else 0, _stream(stream)))
+
+    def replay(self, stream=None):
+        _check(lib().rsi_batch_replay(self.handle, _stream(stream)))
+
+    def mesh_info(self, m):
+        return rsi_get_mesh_info(self.handle, m)
+
+    def set_opts(self, **opts):
+        rsi_set_opts(self.handle, **opts)
+
+    def opts(self):
+        return rsi_get_opts(self.handle)
+
+    def tune(self, segments, mode, candidates, reps=5, stream=None):
+        """Autotune the batched query of `segments`; the fastest candidate stays applied."""
+        outs = self.alloc_outputs(segments, mode)
+        S, E, n, m, o = self._tables(segments, mode, outs)
+        job = rsi_tune_job(None, 0, None, None, None, 0, None, S, E, n, o, m, 0)
+        return rsi_tune(self.handle, job, candidates, reps, stream)
+
+    def tree(self):
+        return rsi_export_tree(self.handle)
 
     def close(self):
         if self.handle:

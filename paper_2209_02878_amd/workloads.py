@@ -347,3 +347,35 @@ def subset(n_total: int, n_pick: int, seed: int) -> np.ndarray:
         return np.arange(n_total, dtype=np.int64)
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(n_total, size=n_pick, replace=False)).astype(np.int64)
+
+
+def config5(n_meshes: int = 64, tri_lo: float = 1e3, tri_hi: float = 2e5, seg_lo: float = 1e4,
+            seg_hi: float = 2e6, seed: int | None = None):
+    """Batched workload: meshes that are heightfields (value noise, grid
+    n = round(sqrt(N_t / 2)) + 1) or noisy geodesic spheres (frequency
+    round(sqrt(N_t / 20))) with equal probability, target triangle counts
+    log-uniform in [tri_lo, tri_hi]; per mesh a log-uniform number of
+    segments in [seg_lo, seg_hi], drawn like the 29,768-triangle workload's
+    (heightfields) or the closed sphere's (spheres).  Returns a list of
+    Workload objects."""
+    rng = np.random.default_rng(seed_for(5, 1) if seed is None else seed)
+    out = []
+    for m in range(n_meshes):
+        target = math.exp(rng.uniform(math.log(tri_lo), math.log(tri_hi)))
+        n_seg = int(math.exp(rng.uniform(math.log(seg_lo), math.log(seg_hi))))
+        mseed = int(rng.integers(1 << 31))
+        srng = np.random.default_rng(int(rng.integers(1 << 31)))
+        if rng.uniform() < 0.5:
+            n = max(2, int(round(math.sqrt(target / 2.0))) + 1)
+            V, T = noise_heightfield(n, mseed, 0.2, jitter=0.25 / (n - 1))
+            lo, hi = mesh_bbox(V)
+            S, E = segments_random_dir(srng, lo, hi, n_seg)
+            kind = "heightfield"
+        else:
+            f = max(1, int(round(math.sqrt(target / 20.0))))
+            V, T = noisy_sphere(f, mseed, 0.3)
+            lo, hi = mesh_bbox(V)
+            S, E = segments_in_box(srng, lo, hi, n_seg, scale=1.5)
+            kind = "sphere"
+        out.append(Workload(f"{kind}-{T.shape[0]}tri-{n_seg}seg", V, T, S, E))
+    return out
