@@ -41,8 +41,140 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 
 
+QUERY_SOURCES = ("paper_2209_02878_amd/csrc/query.hip", "paper_2209_02878_amd/csrc/rsi_device.h",
+                 "paper_2209_02878_amd/csrc/rsi_host.h")
+TRAFFIC_PROFILE = "profiles/hbm_traffic_k_query_heightfield29768_10Mseg.md"
+
+
+def query_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in QUERY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per boolean-query launch from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or
+    None when the kernel sources changed after those runs."""
+    import re
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic-record: (.*)$", text, re.M)
+    if not m:
+        return None
+    rec = dict(kv.split("=", 1) for kv in m.group(1).split())
+    if rec.get("sources") != query_sources_hash():
+        return None
+    return (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
+            float(rec["write_kib"]) * float(rec["write_scale"])) * 1024.0
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def extra_workloads(torch, rsi, wl, dev, stream, time_events, log):
+    """The other configurations, reported beside the headline."""
+    out = {}
+    med = lambda xs: float(np.median(xs))
+
+    # closed 499,280-triangle sphere: all crossings (capacity 4) + first hit
+    t0 = time.time()
+    w = wl.config3()
+    log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
+    V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
+    S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
+    m = rsi.Mesh(V, T)
+    o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
+    b = time_events(lambda: m.rebuild(V, T), 5)
+    q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
+    nspill = rsi.rsi_spill_info(m.handle)[0]
+    out["sphere_499280tri_10Mseg_all_first_k4"] = {
+        "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
+        "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "overflowed_segments": int(nspill)}
+    log(f"sphere all|first: query {med(q):.3f} ms, build {med(b):.3f} ms, spill {nspill}")
+    m.close()
+    del V, T, S, E, o
+
+    # differentiable first hit: 199,712-triangle heightfield, 4M segments
+    w = wl.config4()
+    Vg, _ = wl.config4_target()
+    V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
+    S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
+    n = 317
+    gz = torch.from_numpy(Vg[:, 2].astype(np.float32)).to(dev)
+    X = torch.clamp(S[:, 0] * (n - 1), 0, n - 1 - 1e-6)
+    Y = torch.clamp(S[:, 1] * (n - 1), 0, n - 1 - 1e-6)
+    i, j = X.long(), Y.long()
+    a, c = X - i, Y - j
+    k = j * n + i
+    target = (gz[k] * (1 - a) * (1 - c) + gz[k + 1] * a * (1 - c) + gz[k + n] * (1 - a) * c
+              + gz[k + n + 1] * a * c)
+    m = rsi.Mesh(V, T)
+    Vp = V.clone().requires_grad_(True)
+
+    def fwd():
+        with torch.no_grad():
+            _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
+            return ((P[:, 2] - target) ** 2).sum()
+
+    def fwd_bwd():
+        Vp.grad = None
+        _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
+        loss = ((P[:, 2] - target) ** 2).sum()
+        loss.backward()
+
+    f = time_events(fwd, 10)
+    fb = time_events(fwd_bwd, 10)
+    out["heightfield_199712tri_4Mseg_first_hit_grad"] = {
+        "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
+        "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
+        "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
+        "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
+    log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms")
+    m.close()
+    del V, T, S, E, Vp
+
+    # 64 meshes: one captured graph (rebuild all + one batched boolean query)
+    # against 64 sequential plain calls (rebuild + query per mesh)
+    t0 = time.time()
+    ws = wl.config5()
+    log(f"64-mesh batch generated in {time.time() - t0:.1f}s: {sum(x.n_t for x in ws)} triangles, "
+        f"{sum(x.n_r for x in ws)} segments")
+    meshes = [(torch.from_numpy(x.V).to(dev), torch.from_numpy(x.T).to(dev)) for x in ws]
+    segs = [(torch.from_numpy(x.S).to(dev), torch.from_numpy(x.E).to(dev)) for x in ws]
+    singles = [rsi.Mesh(Vm, Tm) for Vm, Tm in meshes]
+    souts = [sm.alloc_outputs(Sm.shape[0], "bool") for sm, (Sm, _) in zip(singles, segs)]
+
+    def sequential():
+        for sm, (Vm, Tm), (Sm, Em), so in zip(singles, meshes, segs, souts):
+            sm.rebuild(Vm, Tm)
+            sm.query_into(Sm, Em, "bool", so)
+
+    bt = rsi.Batch(meshes)
+    bouts = bt.alloc_outputs(segs, "bool")
+    bt.capture(segs, "bool", bouts, rebuild=True)
+    seq = time_events(sequential, 3)
+    rep = time_events(bt.replay, 10)
+    torch.cuda.synchronize()
+    same = all(torch.equal(bo["hit"], so["hit"]) for bo, so in zip(bouts, souts))
+    ntot = sum(x.n_r for x in ws)
+    out["batch_64_meshes_bool"] = {
+        "n_t": int(sum(x.n_t for x in ws)), "n_r": int(ntot),
+        "graph_replay_ms": round(med(rep), 4), "sequential_64_calls_ms": round(med(seq), 4),
+        "graph_msegments_per_s": round(ntot / med(rep) / 1e3, 2),
+        "speedup_vs_sequential": round(med(seq) / med(rep), 3), "identical_to_sequential": bool(same)}
+    log(f"batch: graph {med(rep):.3f} ms vs sequential {med(seq):.3f} ms, identical={same}")
+    bt.close()
+    for sm in singles:
+        sm.close()
+    return out
 
 
 def main():
@@ -53,6 +185,10 @@ def main():
     ap.add_argument("--n-r", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 29,768-triangle step (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device copy (known traffic for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the segment queries of this library run on a single "
@@ -126,6 +262,8 @@ def main():
     hits = int(out_b["hit"].sum().item())
     log(f"counters: {cnt}; hit fraction {hits / w.n_r:.4f}")
 
+    traffic = measured_traffic()
+    traffic = None if traffic is None else round(traffic)
     rec = {
         "metric": "Msegments/s vs 30k-tri mesh (bool & all-hits); fwd+bwd vs fwd at 1e-5 rel err",
         "value": round(value, 3),
@@ -160,18 +298,31 @@ def main():
             "peak": round(PEAK_VALU_TOPS, 3),
             "unit": "Tops/s",
             "frac": round(achieved_tops / PEAK_VALU_TOPS, 5),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "ops_per_launch": int(ops),
             "kernel_ms": round(kb, 4),
             "hbm_gbs_algorithmic": round(25.0 * w.n_r / (kb / 1e3) / 1e9, 2),
         },
     }
 
+    if args.copy_calibration:
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = 2 * x.numel() * 4
+        del x, y
+
+    if not args.headline_only:
+        mesh.close()
+        rec["extra"] = extra_workloads(torch, rsi, wl, dev, stream, time_events, log)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample, on the host cores
     if not args.no_cpu_baseline:
         import oracle
         threads = oracle.max_threads()
-        probe = 4000
+        probe = 100_000
         t1 = time.perf_counter()
         oracle.query(w.V, w.T, w.S[:probe], w.E[:probe])
         dt = time.perf_counter() - t1
@@ -189,7 +340,8 @@ def main():
             "cpu": platform.processor() or platform.machine(),
         }
         log(f"cpu baseline: {rec['cpu_baseline']}")
-    mesh.close()
+    if args.headline_only:
+        mesh.close()
     print(json.dumps(rec), flush=True)
 
 
