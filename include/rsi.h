@@ -172,12 +172,20 @@ rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *
 
 /* Work counters of the last query when it ran with counting enabled
  * (rsi_set_counting(h, 1)): node visits (internal nodes whose two child boxes
- * were tested), child box tests and triangle tests, summed over segments. */
+ * were tested), child box tests and triangle tests, summed over segments;
+ * then wave-level counts of the persistent query loop (each wave of 64 lanes
+ * adds one per iteration): all iterations, iterations that ran a node step,
+ * a leaf phase, a refill.  node_visits / (64 * wave_node_steps) is the share
+ * of lanes busy in node steps. */
 typedef struct {
     uint64_t node_visits;
     uint64_t box_tests;
     uint64_t tri_tests;
     uint64_t segments;
+    uint64_t wave_loops;
+    uint64_t wave_node_steps;
+    uint64_t wave_leaf_phases;
+    uint64_t wave_refills;
 } rsi_counters;
 rsi_status rsi_set_counting(rsi_handle h, int enable);
 rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);

@@ -722,6 +722,10 @@ rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out)
     out->box_tests = c.box_tests;
     out->tri_tests = c.tri_tests;
     out->segments = c.segments;
+    out->wave_loops = c.wave_loops;
+    out->wave_node_steps = c.wave_node_steps;
+    out->wave_leaf_phases = c.wave_leaf_phases;
+    out->wave_refills = c.wave_refills;
     return RSI_OK;
 }
 

@@ -256,7 +256,10 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
     }
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH>
+// HYB: the stack may outgrow its LDS part (entries from lds_depth on live in
+// gstack); without it the whole stack is in LDS and the global path is not
+// compiled.
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB>
 __global__ __launch_bounds__(256) void k_query(QArgs a)
 {
     extern __shared__ int32_t lds_stack[];
@@ -270,10 +273,16 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     Lane L;
     int64_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
     int32_t node = -1;   // next node to visit; < 0: none
+    // stack pointer kept as an element offset into the [depth][lane] LDS
+    // array (entries x stride), so a push or pop needs no multiply
     int32_t sp = 0;
-    int32_t leaf0 = 0, leaf1 = 0;  // pending leaf references (leaf refs are negative; 0 = none)
+    const int32_t depth_off = a.depth * stride;
+    const int32_t lds_off = a.lds_depth * stride;
+    int32_t leaf0 = 0, leaf1 = 0, leaf2 = 0;  // pending leaf references, filled in order
+                                              // (leaf refs are negative; 0 = none)
     int32_t steps = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
+    uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
     int64_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
     bool exhausted = false;                 // the global counter has passed the last item
 
@@ -283,10 +292,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         // lane can make progress), so the epilogue and the segment set-up run
         // with many lanes at once.  Items come from the wave's chunk; a new
         // chunk is claimed from the global counter with one atomic.
+        if (COUNT) ++w_loops;
         const bool done = item >= 0 && node < 0 && leaf0 == 0;
         const uint64_t waiting = __ballot(done || item == -1);
         if (waiting != 0 &&
             ((int)__popcll(waiting) >= a.refill || __ballot(item >= 0 && !done) == 0)) {
+            if (COUNT) ++w_refill;
             if (done) {
                 finish<MODE, SPILL, BATCH>(a, L);
                 item = -1;
@@ -358,14 +369,18 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         }
         if (__ballot(item >= 0) == 0) break;
 
-        // ---- one node step for every lane that has a node and no pending leaf
-        const bool want = node >= 0 && leaf0 == 0;
+        // ---- one node step for every lane that has a node and at most one
+        // pending leaf: a lane keeps walking past the first leaf it finds
+        // (speculatively, the leaf may end the walk) so that leaf tests are
+        // batched over more lanes and fewer lanes sit idle in node steps
+        const bool want = node >= 0 && leaf1 == 0;
         const uint64_t w = __ballot(want);
+        if (COUNT && w != 0) ++w_steps;
         if (want) {
             const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
             const float4 q0 = q[0], q1 = q[1], q2 = q[2];
             const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
-            const float lim = (MODE & M_ALL) ? 1.0f : L.tlim;
+            const float lim = (MODE & M_FIRST) && !(MODE & M_ALL) ? L.tlim : 1.0f;
             float tl, tr;
             const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
             const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
@@ -374,27 +389,39 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 boxes += 2;
             }
             const int32_t cl = q3.x, cr = q3.y;
-            if (hl && cl < 0) leaf0 = cl;
-            if (hr && cr < 0) {
-                if (leaf0 == 0) leaf0 = cr;
-                else leaf1 = cr;
+            // append the hit leaf children to the pending list (at most one
+            // entry is pending here, so three slots suffice)
+            int32_t n0 = (hl && cl < 0) ? cl : 0;
+            int32_t n1 = (hr && cr < 0) ? cr : 0;
+            if (n0 == 0) {
+                n0 = n1;
+                n1 = 0;
+            }
+            if (leaf0 == 0) {
+                leaf0 = n0;
+                leaf1 = n1;
+            } else {
+                leaf1 = n0;
+                leaf2 = n1;
             }
             const bool gl = hl && cl >= 0;
             const bool gr = hr && cr >= 0;
-            if (gl && gr && sp < a.depth) {
-                const bool left_first = tl <= tr;
-                const int32_t far_child = left_first ? cr : cl;
-                if (sp < a.lds_depth) stk[sp * stride] = far_child;
-                else a.gstack[(int64_t)(sp - a.lds_depth) * gstride + gtid] = far_child;
-                ++sp;
-                node = left_first ? cl : cr;
-            } else if (gl) {
-                node = cl;
-            } else if (gr) {
-                node = cr;
+            // descend into the nearer internal child that was hit; push the
+            // other one when both were (a full stack, possible only in a
+            // damaged tree, drops it)
+            const bool take_l = gl && (!gr || tl <= tr);
+            if (gl && gr && sp < depth_off) {
+                const int32_t far_child = take_l ? cr : cl;
+                if (!HYB || sp < lds_off) stk[sp] = far_child;
+                else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = far_child;
+                sp += stride;
+            }
+            if (gl || gr) {
+                node = take_l ? cl : cr;
             } else if (sp > 0) {
-                --sp;
-                node = sp < a.lds_depth ? stk[sp * stride] : a.gstack[(int64_t)(sp - a.lds_depth) * gstride + gtid];
+                sp -= stride;
+                if (!HYB || sp < lds_off) node = stk[sp];
+                else node = a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid];
             } else {
                 node = -1;
             }
@@ -405,13 +432,16 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         // ---- test pending leaves once few lanes can still step
         const uint64_t pend = __ballot(leaf0 != 0);
         if (pend != 0 && (int)__popcll(w) < a.defer) {
-            if (leaf0 != 0) {
-                bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
-                if (!stop && leaf1 != 0) stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf1, tests);
-                if (stop) node = -1;
-                leaf0 = 0;
-                leaf1 = 0;
-            }
+            if (COUNT) ++w_leaf;
+            do {
+                if (leaf0 != 0) {
+                    const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
+                    leaf0 = stop ? 0 : leaf1;
+                    leaf1 = stop ? 0 : leaf2;
+                    leaf2 = 0;
+                    if (stop) node = -1;
+                }
+            } while (__ballot(leaf0 != 0) != 0);
         }
 
     }
@@ -420,6 +450,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         wave_add_u64(&a.counters->box_tests, boxes);
         wave_add_u64(&a.counters->tri_tests, tests);
         wave_add_u64(&a.counters->segments, segs);
+        if (__lane_id() == 0) {
+            atomicAdd(&a.counters->wave_loops, (unsigned long long)w_loops);
+            atomicAdd(&a.counters->wave_node_steps, (unsigned long long)w_steps);
+            atomicAdd(&a.counters->wave_leaf_phases, (unsigned long long)w_leaf);
+            atomicAdd(&a.counters->wave_refills, (unsigned long long)w_refill);
+        }
     }
 }
 
@@ -453,13 +489,16 @@ __global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
         scalars[kOvfTotalLo] = 0;
         scalars[kOvfTotalHi] = 0;
     }
-    if (c) c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
+    if (c) {
+        c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
+        c->wave_loops = c->wave_node_steps = c->wave_leaf_phases = c->wave_refills = 0;
+    }
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH = false>
-hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB>
+hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    auto kern = k_query<MODE, SPILL, COUNT, BATCH>;
+    auto kern = k_query<MODE, SPILL, COUNT, BATCH, HYB>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess) return e;
@@ -486,6 +525,13 @@ hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, s, b);
     return hipGetLastError();
+}
+
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH = false>
+hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
+{
+    if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true>(a, block, lds, s);
+    return launch_kernel<MODE, SPILL, COUNT, BATCH, false>(a, block, lds, s);
 }
 
 template <bool COUNT>

@@ -25,6 +25,9 @@ enum Scalar {
 
 struct Counters {
     unsigned long long node_visits, box_tests, tri_tests, segments;
+    // per wave: loop iterations, iterations with a node step, with a leaf
+    // phase, with a refill
+    unsigned long long wave_loops, wave_node_steps, wave_leaf_phases, wave_refills;
 };
 
 // Radix-sort scratch sized for n elements.

@@ -60,7 +60,9 @@ class rsi_outputs(ctypes.Structure):
 
 class rsi_counters(ctypes.Structure):
     _fields_ = [("node_visits", ctypes.c_uint64), ("box_tests", ctypes.c_uint64),
-                ("tri_tests", ctypes.c_uint64), ("segments", ctypes.c_uint64)]
+                ("tri_tests", ctypes.c_uint64), ("segments", ctypes.c_uint64),
+                ("wave_loops", ctypes.c_uint64), ("wave_node_steps", ctypes.c_uint64),
+                ("wave_leaf_phases", ctypes.c_uint64), ("wave_refills", ctypes.c_uint64)]
 
 
 class rsi_tree_info(ctypes.Structure):
@@ -218,8 +220,7 @@ def rsi_set_counting(h, enable: bool):
 def rsi_get_counters(h):
     c = rsi_counters()
     _check(lib().rsi_get_counters(h, ctypes.byref(c)))
-    return {"node_visits": c.node_visits, "box_tests": c.box_tests, "tri_tests": c.tri_tests,
-            "segments": c.segments}
+    return {name: getattr(c, name) for name, _ in rsi_counters._fields_}
 
 
 def rsi_get_tree_info(h):
