@@ -99,8 +99,18 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log):
         "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
         "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "overflowed_segments": int(nspill)}
     log(f"sphere all|first: query {med(q):.3f} ms, build {med(b):.3f} ms, spill {nspill}")
+    # odd-parity inside test of 10M points against the same closed surface
+    P = torch.from_numpy(wl.inside_points(w.V, w.n_r, wl.seed_for(6, 1))).to(dev)
+    ins = torch.empty(w.n_r, dtype=torch.uint8, device=dev)
+    cnt = torch.empty(w.n_r, dtype=torch.int32, device=dev)
+    ends = torch.empty(w.n_r, 3, dtype=torch.float32, device=dev)
+    qi = time_events(lambda: rsi.rsi_inside(m.handle, P, ins, cnt, ends), 5)
+    out["sphere_499280tri_10Mpoint_inside"] = {
+        "ms": round(med(qi), 4), "mpoints_per_s": round(w.n_r / med(qi) / 1e3, 2),
+        "inside_fraction": round(float(ins.float().mean().item()), 5)}
+    log(f"inside test: {med(qi):.3f} ms for {w.n_r} points")
     m.close()
-    del V, T, S, E, o
+    del V, T, S, E, o, P, ins, cnt, ends
 
     # differentiable first hit: 199,712-triangle heightfield, 4M segments
     w = wl.config4()

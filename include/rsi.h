@@ -46,14 +46,20 @@ typedef enum {
     RSI_E_OVERFLOW = 4   /* a caller-sized buffer is too small; counts stay exact */
 } rsi_status;
 
-/* Query modes (bit mask).  RSI_FIRST_HIT and RSI_ALL_HITS may be combined;
- * RSI_BOOL may be added to either and is then derived from the same pass. */
+/* Query modes (bit mask).  RSI_FIRST_HIT may be combined with RSI_ALL_HITS
+ * or RSI_COUNT; RSI_BOOL may be added to any of them and is then derived
+ * from the same pass.  RSI_COUNT with RSI_ALL_HITS is the same as
+ * RSI_ALL_HITS alone (which always writes the exact count). */
 enum {
     RSI_BOOL = 1u,       /* crossing flag per segment (paper Section 1, default output) */
     RSI_FIRST_HIT = 2u,  /* crossing with the smallest t; exact ties go to the smaller
                             triangle id (our reading of `barycentric`, Section 2.4) */
-    RSI_ALL_HITS = 4u    /* exact count plus every crossing, ordered by (t, id)
-                            (`intercept_count`, Section 2.4 and 2.6) */
+    RSI_ALL_HITS = 4u,   /* exact count plus every crossing, ordered by (t, id)
+                            (Section 2.4 and 2.6) */
+    RSI_COUNT = 8u       /* exact number of crossings only, into out->count, no list
+                            (`intercept_count`, Section 2.4; by Section 2.6 its odd
+                            parity tells whether the start point lies inside a closed
+                            surface) */
 };
 
 /* Build / query options; a zero field selects the default. */
@@ -70,7 +76,11 @@ typedef struct {
                              device memory.  The whole stack (tree height + 1) stays in LDS by
                              default and for any value at or above it; a smaller value raises
                              occupancy. 1..255 */
-    int32_t reserved[2];
+    int32_t branching;    /* 2: traverse the binary tree of Section 3.1 (default); 4: traverse
+                             its four-way view (every node with its grandchildren as children,
+                             one 128-byte record per node, laid out after each build, rebuild
+                             and refit).  Both give the same results. */
+    int32_t reserved;
 } rsi_opts;
 
 /* Output buffers of rsi_query (host struct of device pointers, each [n_r...]).
@@ -169,6 +179,58 @@ rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossing
  * the segments themselves is unspecified. */
 rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *count,
                           int32_t *ids, float *ts, void *stream);
+
+/* Segment order (the paper's v2.2 step, Section 4.1: rays sorted so that
+ * neighbouring threads take similar paths).  order (device int32[n_r]) gets
+ * the segment indices sorted by a key whose 3 most significant bits are the
+ * octant of E - S and whose low 30 bits are the Morton code of the midpoint
+ * quantised to 2^10 levels per axis inside the midpoints' bounding box;
+ * stable (equal keys keep index order).  S, E: device float[3 n_r].  Uses
+ * scratch kept with the handle (12 bytes per segment plus sort buffers).
+ * Asynchronous on `stream`.  The order does not depend on the mesh: compute
+ * it once, gather the segments into it, and query any number of meshes
+ * (outputs then follow the gathered order). */
+rsi_status rsi_segment_order(rsi_handle h, const float *S, const float *E, int64_t n_r, int32_t *order,
+                             void *stream);
+
+/* S_out[k] = S[order[k]], E_out[k] = E[order[k]] (device float[3 n_r] each;
+ * must not alias S or E).  An order entry outside [0, n_r) reads segment 0
+ * (no fault; an order from rsi_segment_order is always a permutation).
+ * Asynchronous on `stream`. */
+rsi_status rsi_gather_segments(rsi_handle h, const float *S, const float *E, const int32_t *order, int64_t n_r,
+                               float *S_out, float *E_out, void *stream);
+
+/* Compact outputs (paper Section 2.4, extended usage): the ids of the
+ * segments that cross the mesh, in increasing order, and for `barycentric`
+ * their distances, triangles and points.  Selection: hit[i] != 0 when `hit`
+ * (an RSI_BOOL output) is given, else tri[i] >= 0 (an RSI_FIRST_HIT output).
+ * With `tri`: dist[k] = t[i] * |E_i - S_i| (the distance from the start,
+ * needs t, S, E), tri_out[k] = tri[i], point_out[3k..3k+2] = point[3i..];
+ * any of dist, tri_out, point_out may be NULL.  All arrays are device
+ * arrays; outputs need room for n_r entries (3 n_r floats for point_out).
+ * *n_out (host) receives the number written; the call waits for it.
+ * RSI_E_INVALID for NULL ids or n_out, n_r outside [0, 2^31), or a
+ * combination not listed. */
+rsi_status rsi_compact(rsi_handle h, const uint8_t *hit, const int32_t *tri, const float *t, const float *point,
+                       const float *S, const float *E, int64_t n_r, int32_t *ids, float *dist, int32_t *tri_out,
+                       float *point_out, int64_t *n_out, void *stream);
+
+/* Odd-parity inside test (paper Section 2.4 gives the intercept count of a
+ * segment, Section 2.6 notes that an odd count puts the segment's start point
+ * inside a closed surface).  For every point P_i (device, float[3 n_p], AoS) the library
+ * forms the segment from P_i to E_i = P_i + L_i u, u = (0.6, 0.41, 0.91)
+ * normalised (FP32 0.515216053, 0.352064312, 0.781410992), L_i = |P_i - c| +
+ * 2 R + 1 with c and R the centre and half diagonal of the mesh's bounding
+ * box, so E_i lies outside the box; then counts the crossings exactly
+ * (RSI_COUNT) and writes inside[i] = count & 1 (device, uint8[n_p]).
+ * count (device int32[n_p]) and E (device float[3 n_p]) are optional
+ * outputs: the counts and the far ends used; when NULL the library uses its
+ * own scratch (kept with the handle).  The answer is meaningful for closed
+ * (watertight) meshes; a segment through an edge or vertex is degenerate and
+ * may be miscounted.  Asynchronous on `stream`; RSI_E_INVALID for a batch
+ * handle, NULL pointers with n_p > 0, or n_p outside [0, 2^30). */
+rsi_status rsi_inside(rsi_handle h, const float *P, int64_t n_p, uint8_t *inside, int32_t *count, float *E,
+                      void *stream);
 
 /* Work counters of the last query when it ran with counting enabled
  * (rsi_set_counting(h, 1)): node visits (internal nodes whose two child boxes

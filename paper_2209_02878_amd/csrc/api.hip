@@ -47,7 +47,7 @@ void free_handle_memory(rsi_bvh *h)
 {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    void *ptrs[] = {h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
+    void *ptrs[] = {h->seg_keys, h->compact_counts, h->nodes4, h->aux_E, h->aux_count, h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
                     h->arrive, h->heights, h->climb, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
                     h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off, h->vert_off, h->mesh_bounds,
                     h->mesh_height, h->mesh_root, h->mesh_entry, h->bt.seg_off, h->bt.S, h->bt.E, h->bt.hit,
@@ -57,6 +57,7 @@ void free_handle_memory(rsi_bvh *h)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     rsi::free_sort_scratch(h->sort);
+    rsi::free_sort_scratch(h->seg_sort);
     if (h->h_scalars) (void)hipHostFree(h->h_scalars);
 }
 
@@ -70,8 +71,9 @@ void destroy_handle(rsi_bvh *h)
 rsi_status read_opts(const rsi_opts *opts, rsi_bvh *h)
 {
     int leaf = h->leaf_size, block = h->block_size, defer = h->defer_lanes, refill = h->refill_lanes;
-    int chunk = h->chunk, stack = h->stack_cap;
+    int chunk = h->chunk, stack = h->stack_cap, width = h->width;
     if (opts) {
+        if (opts->branching) width = opts->branching;
         if (opts->leaf_size) leaf = opts->leaf_size;
         if (opts->block_size) block = opts->block_size;
         if (opts->defer_lanes) defer = opts->defer_lanes;
@@ -85,12 +87,14 @@ rsi_status read_opts(const rsi_opts *opts, rsi_bvh *h)
     if (defer < 1 || defer > 64) return invalid("defer_lanes must be in 1..64");
     if (refill < 1 || refill > 64) return invalid("refill_lanes must be in 1..64");
     if (chunk != 0 && (chunk < 64 || chunk > (1 << 20))) return invalid("chunk must be 0 or 64..2^20");
+    if (width != 2 && width != 4) return invalid("branching must be 2 or 4");
     h->leaf_size = leaf;
     h->block_size = block;
     h->defer_lanes = defer;
     h->refill_lanes = refill;
     h->chunk = chunk;
     h->stack_cap = stack;
+    h->width = width;
     return RSI_OK;
 }
 
@@ -146,6 +150,7 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     if (e == hipSuccess) e = dalloc(&h->keys, n);
     if (e == hipSuccess) e = dalloc(&h->order, n);
     if (e == hipSuccess) e = dalloc(&h->nodes, n);
+    if (e == hipSuccess && h->width == 4) e = dalloc(&h->nodes4, n);
     if (e == hipSuccess) e = dalloc(&h->tris, n);
     if (e == hipSuccess) e = dalloc(&h->arrive, n);
     if (e == hipSuccess) e = dalloc(&h->heights, 2 * n);
@@ -219,7 +224,10 @@ hipError_t enqueue_build_batch(rsi_bvh *h, hipStream_t s)
     return e;
 }
 
-bool valid_mode(uint32_t mode) { return mode != 0 && !(mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS)); }
+bool valid_mode(uint32_t mode)
+{
+    return mode != 0 && !(mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS | RSI_COUNT));
+}
 
 hipError_t ensure_ovf(rsi_bvh *h, int64_t n_r)
 {
@@ -370,7 +378,8 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
     if (!out) return invalid("rsi_query: NULL outputs");
     if (n_r < 0) return invalid("rsi_query: negative n_r");
     if (!valid_mode(mode))
-        return invalid("rsi_query: mode must be a nonzero mask of RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS");
+        return invalid("rsi_query: mode must be a nonzero mask of RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS, RSI_COUNT");
+    if (mode & RSI_ALL_HITS) mode &= ~(uint32_t)RSI_COUNT;  // the all-hits pass writes the count anyway
     if (n_r == 0) return RSI_OK;  // nothing to read or write; output pointers may be NULL
     if (!S || !E) return invalid("rsi_query: NULL segment pointer");
     if ((mode & RSI_BOOL) && !out->hit) return invalid("rsi_query: RSI_BOOL needs out->hit");
@@ -380,6 +389,7 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
         if (!out->count || !out->ids || !out->ts) return invalid("rsi_query: RSI_ALL_HITS needs out->count, ids, ts");
         if (out->capacity < 1) return invalid("rsi_query: capacity must be >= 1");
     }
+    if ((mode & RSI_COUNT) && !out->count) return invalid("rsi_query: RSI_COUNT needs out->count");
     if (n_r >= (int64_t(1) << 30)) return invalid("rsi_query: n_r must be below 2^30");
     hipStream_t s = (hipStream_t)stream;
     rsi::QueryOut o = {out->hit, out->tri, out->t, out->uv, out->point, out->count, out->ids, out->ts,
@@ -418,6 +428,94 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
         }
     }
     return RSI_OK;
+}
+
+rsi_status rsi_inside(rsi_handle h, const float *P, int64_t n_p, uint8_t *inside, int32_t *count, float *E,
+                      void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_inside: NULL handle");
+    if (h->M != 1) return invalid("rsi_inside: batch handle");
+    if (n_p < 0) return invalid("rsi_inside: negative n_p");
+    if (n_p == 0) return RSI_OK;
+    if (!P || !inside) return invalid("rsi_inside: NULL point or output pointer");
+    if (n_p >= (int64_t(1) << 30)) return invalid("rsi_inside: n_p must be below 2^30");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((!E || !count) && h->aux_cap < n_p) {
+        if (h->aux_E) (void)hipFree(h->aux_E);
+        if (h->aux_count) (void)hipFree(h->aux_count);
+        h->aux_E = nullptr;
+        h->aux_count = nullptr;
+        h->aux_cap = 0;
+        e = hipMalloc(reinterpret_cast<void **>(&h->aux_E), sizeof(float) * 3 * (size_t)n_p);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&h->aux_count), sizeof(int32_t) * (size_t)n_p);
+        if (e != hipSuccess) return hip_fail(e, "rsi_inside: scratch");
+        h->aux_cap = n_p;
+    }
+    float *ends = E ? E : h->aux_E;
+    int32_t *cnt = count ? count : h->aux_count;
+    rsi_outputs o = {};
+    o.count = cnt;
+    if (h->n_t == 0) {
+        // no surface: every point is outside; the ends are the points themselves
+        e = hipMemcpyAsync(ends, P, sizeof(float) * 3 * (size_t)n_p, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n_p, s);
+        if (e == hipSuccess) e = rsi::launch_parity(cnt, n_p, inside, s);
+        return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_inside");
+    }
+    e = rsi::launch_inside_ends(h, P, n_p, ends, s);
+    if (e != hipSuccess) return hip_fail(e, "rsi_inside: segment ends");
+    const rsi_status st = rsi_query(h, P, ends, n_p, RSI_COUNT, &o, stream);
+    if (st != RSI_OK) return st;
+    e = rsi::launch_parity(cnt, n_p, inside, s);
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_inside: parity");
+}
+
+rsi_status rsi_segment_order(rsi_handle h, const float *S, const float *E, int64_t n_r, int32_t *order,
+                             void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_segment_order: NULL handle");
+    if (n_r < 0 || n_r >= (int64_t(1) << 31)) return invalid("rsi_segment_order: n_r must be in [0, 2^31)");
+    if (n_r == 0) return RSI_OK;
+    if (!S || !E || !order) return invalid("rsi_segment_order: NULL pointer");
+    hipError_t e = rsi::launch_segment_order(h, S, E, n_r, order, (hipStream_t)stream);
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_segment_order");
+}
+
+rsi_status rsi_gather_segments(rsi_handle h, const float *S, const float *E, const int32_t *order, int64_t n_r,
+                               float *S_out, float *E_out, void *stream)
+{
+    set_error("");
+    if (!h) return invalid("rsi_gather_segments: NULL handle");
+    if (n_r < 0 || n_r >= (int64_t(1) << 31)) return invalid("rsi_gather_segments: n_r must be in [0, 2^31)");
+    if (n_r == 0) return RSI_OK;
+    if (!S || !E || !order || !S_out || !E_out) return invalid("rsi_gather_segments: NULL pointer");
+    hipError_t e = rsi::launch_gather_segments(h, S, E, order, n_r, S_out, E_out, (hipStream_t)stream);
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_gather_segments");
+}
+
+rsi_status rsi_compact(rsi_handle h, const uint8_t *hit, const int32_t *tri, const float *t, const float *point,
+                       const float *S, const float *E, int64_t n_r, int32_t *ids, float *dist, int32_t *tri_out,
+                       float *point_out, int64_t *n_out, void *stream)
+{
+    set_error("");
+    if (!h || !n_out) return invalid("rsi_compact: NULL handle or count pointer");
+    *n_out = 0;
+    if (n_r < 0 || n_r >= (int64_t(1) << 31)) return invalid("rsi_compact: n_r must be in [0, 2^31)");
+    if (n_r == 0) return RSI_OK;
+    if (!ids) return invalid("rsi_compact: NULL ids");
+    if (hit) {
+        if (dist || tri_out || point_out) return invalid("rsi_compact: boolean selection gives ids only");
+    } else {
+        if (!tri) return invalid("rsi_compact: pass hit (boolean) or tri (first hit)");
+        if (dist && (!t || !S || !E)) return invalid("rsi_compact: distances need t, S and E");
+        if (point_out && !point) return invalid("rsi_compact: points need point");
+    }
+    hipError_t e = rsi::launch_compact(h, hit, S, E, tri, t, point, n_r, ids, dist, tri_out, point_out, n_out,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_compact");
 }
 
 rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,
@@ -595,13 +693,31 @@ static rsi_status drop_graph(rsi_bvh *h)
     return RSI_OK;
 }
 
+// Lay out the four-way view for the current tree when branching 4 is asked
+// for and the tree was built without it (synchronous: a short device pass).
+rsi_status apply_width(rsi_bvh *h, hipStream_t s)
+{
+    if (h->width == 2) {
+        h->width_built = 2;
+        return RSI_OK;
+    }
+    if (h->width_built == 4) return RSI_OK;
+    hipError_t e = hipSuccess;
+    if (!h->nodes4) e = dalloc(&h->nodes4, h->n_t);
+    if (e == hipSuccess) e = rsi::launch_widen(h, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "branching 4: four-way layout");
+}
+
 rsi_status rsi_set_opts(rsi_handle h, const rsi_opts *opts)
 {
     set_error("");
     if (!h) return invalid("rsi_set_opts: NULL handle");
     rsi_status st = drop_graph(h);
     if (st != RSI_OK) return st;
-    return read_opts(opts, h);
+    st = read_opts(opts, h);
+    if (st != RSI_OK) return st;
+    return apply_width(h, nullptr);
 }
 
 rsi_status rsi_get_opts(rsi_handle h, rsi_opts *out)
@@ -615,6 +731,7 @@ rsi_status rsi_get_opts(rsi_handle h, rsi_opts *out)
     out->refill_lanes = h->refill_lanes;
     out->chunk = h->chunk;
     out->stack_depth = h->stack_cap;
+    out->branching = h->width;
     return RSI_OK;
 }
 
@@ -647,8 +764,9 @@ rsi_status rsi_tune(rsi_handle h, const rsi_tune_job *job, const rsi_opts *cand,
     if (e != hipSuccess) return hip_fail(e, "rsi_tune: events");
     // options before tuning (set directly: a zero field in rsi_opts means "keep")
     const int32_t o_leaf = h->leaf_size, o_block = h->block_size, o_defer = h->defer_lanes;
-    const int32_t o_refill = h->refill_lanes, o_chunk = h->chunk, o_stack = h->stack_cap;
+    const int32_t o_refill = h->refill_lanes, o_chunk = h->chunk, o_stack = h->stack_cap, o_width = h->width;
     auto restore = [&]() {
+        h->width = o_width;
         h->leaf_size = o_leaf;
         h->block_size = o_block;
         h->defer_lanes = o_defer;
@@ -665,6 +783,7 @@ rsi_status rsi_tune(rsi_handle h, const rsi_tune_job *job, const rsi_opts *cand,
         restore();  // each candidate starts from the original options
         st = read_opts(&cand[c], h);
         if (st == RSI_OK && h->leaf_size != old_leaf) st = tune_rebuild(h, job, s);
+        if (st == RSI_OK) st = apply_width(h, s);
         if (st == RSI_OK) st = tune_run(h, job, s);  // warm-up
         for (int32_t r = 0; r < reps && st == RSI_OK; ++r) {
             e = hipEventRecord(e0, s);
@@ -691,12 +810,14 @@ rsi_status rsi_tune(rsi_handle h, const rsi_tune_job *job, const rsi_opts *cand,
         const int32_t cur_leaf = h->leaf_size;
         restore();
         if (h->leaf_size != cur_leaf) (void)tune_rebuild(h, job, s);
+        (void)apply_width(h, s);
         return st;
     }
     const int32_t old_leaf = h->leaf_size;
     restore();
     st = read_opts(&cand[best_i], h);
     if (st == RSI_OK && h->leaf_size != old_leaf) st = tune_rebuild(h, job, s);
+    if (st == RSI_OK) st = apply_width(h, s);
     *best = best_i;
     return st;
 }

@@ -422,6 +422,47 @@ __global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
     write_entry(a, m, lo, hi, c);
 }
 
+// Four-way view: record n lists the boxes and references of n's
+// grandchildren (a leaf child stands for itself), read from n's record and
+// its internal children's records.  Every record is rewritten, including
+// ones no traversal reaches (inside collapsed leaves), so references are
+// range-checked before use.
+__global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, int64_t n, Node4 *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const Node nd = nodes[j];
+    float box[4][6];
+    int32_t ref[4];
+    int k = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = nd.ref[side];
+        if (c >= 0 && c < n) {
+            const Node ch = nodes[c];
+            for (int g = 0; g < 2; ++g) {
+                for (int q = 0; q < 6; ++q) box[k][q] = ch.f[6 * g + q];
+                ref[k++] = ch.ref[g];
+            }
+        } else {
+            for (int q = 0; q < 6; ++q) box[k][q] = nd.f[6 * side + q];
+            ref[k++] = c < 0 ? c : leaf_ref(0, 1);
+        }
+    }
+    Node4 w;
+    for (int s = 0; s < 4; ++s) {
+        const bool used = s < k;
+        w.lx[s] = used ? box[s][0] : FLT_MAX;
+        w.ly[s] = used ? box[s][1] : FLT_MAX;
+        w.lz[s] = used ? box[s][2] : FLT_MAX;
+        w.hx[s] = used ? box[s][3] : FLT_MAX;
+        w.hy[s] = used ? box[s][4] : FLT_MAX;
+        w.hz[s] = used ? box[s][5] : FLT_MAX;
+        w.ref[s] = used ? ref[s] : leaf_ref(0, 1);
+        w.pad[s] = 0;
+    }
+    out[j] = w;
+}
+
 BuildArgs make_build_args(rsi_bvh *h, const float *V)
 {
     BuildArgs a;
@@ -476,6 +517,18 @@ hipError_t launch_gather(rsi_bvh *h, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_widen(rsi_bvh *h, hipStream_t s)
+{
+    if (h->width != 4 || h->n_t == 0 || !h->nodes4) {
+        h->width_built = 2;
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((h->n_t + 255) / 256)), dim3(256), 0, s, h->nodes, h->n_t,
+                       h->nodes4);
+    h->width_built = 4;
+    return hipGetLastError();
+}
+
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
 {
     const int64_t n = h->n_t;
@@ -489,7 +542,9 @@ hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
     if (e != hipSuccess) return e;
     e = radix_sort_pairs(h->keys, h->order, n, 63, h->sort, s, h->M > 1 ? h->tri_off : nullptr, h->M);
     if (e != hipSuccess) return e;
-    return run_hierarchy(a, s);
+    e = run_hierarchy(a, s);
+    if (e != hipSuccess) return e;
+    return launch_widen(h, s);
 }
 
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)
@@ -497,7 +552,9 @@ hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)
     if (h->n_t == 0) return hipSuccess;
     const BuildArgs a = make_build_args(h, V);
     hipLaunchKernelGGL(k_init, dim3(init_grid(a)), dim3(256), 0, s, a);
-    return run_hierarchy(a, s);
+    hipError_t e = run_hierarchy(a, s);
+    if (e != hipSuccess) return e;
+    return launch_widen(h, s);
 }
 
 }  // namespace rsi

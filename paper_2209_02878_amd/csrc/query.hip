@@ -41,10 +41,17 @@
 namespace rsi {
 namespace {
 
-enum : uint32_t { M_BOOL = RSI_BOOL, M_FIRST = RSI_FIRST_HIT, M_ALL = RSI_ALL_HITS };
+enum : uint32_t { M_BOOL = RSI_BOOL, M_FIRST = RSI_FIRST_HIT, M_ALL = RSI_ALL_HITS, M_COUNT = RSI_COUNT };
+// modes that must see every crossing (no early exit, no shrinking t limit)
+constexpr uint32_t M_FULL = M_ALL | M_COUNT;
+
+// Direction of the inside-test segments: (0.6, 0.41, 0.91) normalised, a
+// direction not parallel to any axis or coordinate plane.
+__constant__ float kInsideDir[3] = {0.515216053f, 0.352064312f, 0.781410992f};
 
 struct QArgs {
     const Node *nodes;
+    const Node4 *nodes4;  // four-way view (branching 4), else null
     const Tri *tris;
     int32_t entry;
     const float *S;
@@ -114,7 +121,7 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
         int32_t id;
         tri_load(a.tris, pos, v, id);
         if (COUNT) ++tests;
-        const float lim = (MODE & M_ALL) ? 1.0f : L.tlim;
+        const float lim = (MODE & M_FULL) ? 1.0f : L.tlim;
         const MTHit h = mt_test(L.seg, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], lim);
         if (!h.hit) continue;
         L.found = true;
@@ -125,9 +132,10 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
                 L.best_t = t;
                 L.best_id = id;
                 L.best_pos = pos;
-                if (!(MODE & M_ALL)) L.tlim = fminf(1.0f, t * (1.0f + 0x1p-20f));
+                if (!(MODE & M_FULL)) L.tlim = fminf(1.0f, t * (1.0f + 0x1p-20f));
             }
         }
+        if ((MODE & M_COUNT) && !(MODE & M_ALL)) ++L.count;
         if (MODE & M_ALL) {
             const int32_t c = L.count++;
             if (SPILL) {
@@ -229,6 +237,7 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
             pt[3 * i + 2] = 0.0f;
         }
     }
+    if ((MODE & M_COUNT) && !(MODE & M_ALL)) a.o.count[i] = L.count;
     if (MODE & M_ALL) {
         const int K = a.o.cap;
         a.o.count[i] = L.count;
@@ -258,8 +267,9 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
 
 // HYB: the stack may outgrow its LDS part (entries from lds_depth on live in
 // gstack); without it the whole stack is in LDS and the global path is not
-// compiled.
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB>
+// compiled.  WIDE: walk the four-way view (Node4 records) instead of the
+// binary nodes; leaves and triangles are the same, so are the results.
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE>
 __global__ __launch_bounds__(256) void k_query(QArgs a)
 {
     extern __shared__ int32_t lds_stack[];
@@ -278,8 +288,9 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     int32_t sp = 0;
     const int32_t depth_off = a.depth * stride;
     const int32_t lds_off = a.lds_depth * stride;
-    int32_t leaf0 = 0, leaf1 = 0, leaf2 = 0;  // pending leaf references, filled in order
-                                              // (leaf refs are negative; 0 = none)
+    // pending leaf references (leaf refs are negative; 0 = none): filled in
+    // order in the binary walk, by child slot in the four-way walk
+    int32_t leaf0 = 0, leaf1 = 0, leaf2 = 0, leaf3 = 0;
     int32_t steps = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
@@ -293,7 +304,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         // with many lanes at once.  Items come from the wave's chunk; a new
         // chunk is claimed from the global counter with one atomic.
         if (COUNT) ++w_loops;
-        const bool done = item >= 0 && node < 0 && leaf0 == 0;
+        const bool done = item >= 0 && node < 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf0 == 0);
         const uint64_t waiting = __ballot(done || item == -1);
         if (waiting != 0 &&
             ((int)__popcll(waiting) >= a.refill || __ballot(item >= 0 && !done) == 0)) {
@@ -373,14 +384,62 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         // pending leaf: a lane keeps walking past the first leaf it finds
         // (speculatively, the leaf may end the walk) so that leaf tests are
         // batched over more lanes and fewer lanes sit idle in node steps
-        const bool want = node >= 0 && leaf1 == 0;
+        const bool want = node >= 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf1 == 0);
         const uint64_t w = __ballot(want);
         if (COUNT && w != 0) ++w_steps;
-        if (want) {
+        auto push = [&](bool cond, int32_t child) {
+            if (cond && sp < depth_off) {
+                if (!HYB || sp < lds_off) stk[sp] = child;
+                else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = child;
+                sp += stride;
+            }
+        };
+        auto pop = [&]() -> int32_t {
+            if (sp <= 0) return -1;
+            sp -= stride;
+            if (!HYB || sp < lds_off) return stk[sp];
+            return a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid];
+        };
+        if constexpr (WIDE) {
+          if (want) {
+            const float4 *q = reinterpret_cast<const float4 *>(a.nodes4 + node);
+            const float4 LX = q[0], LY = q[1], LZ = q[2], HX = q[3], HY = q[4], HZ = q[5];
+            const int4 C = reinterpret_cast<const int4 *>(a.nodes4 + node)[6];
+            const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
+            float t0, t1, t2, t3;
+            const bool h0 = slab_hit(L.seg, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, lim, t0);
+            const bool h1 = slab_hit(L.seg, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, lim, t1);
+            const bool h2 = slab_hit(L.seg, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, lim, t2);
+            const bool h3 = slab_hit(L.seg, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, lim, t3);
+            if (COUNT) {
+                ++visits;
+                boxes += 4;
+            }
+            leaf0 = (h0 && C.x < 0) ? C.x : 0;
+            leaf1 = (h1 && C.y < 0) ? C.y : 0;
+            leaf2 = (h2 && C.z < 0) ? C.z : 0;
+            leaf3 = (h3 && C.w < 0) ? C.w : 0;
+            const bool g0 = h0 && C.x >= 0, g1 = h1 && C.y >= 0, g2 = h2 && C.z >= 0, g3 = h3 && C.w >= 0;
+            // descend into the nearest internal child that was hit; push the others
+            float bt = INFINITY;
+            int32_t near = -1;
+            if (g0) { bt = t0; near = C.x; }
+            if (g1 && t1 < bt) { bt = t1; near = C.y; }
+            if (g2 && t2 < bt) { bt = t2; near = C.z; }
+            if (g3 && t3 < bt) { bt = t3; near = C.w; }
+            push(g0 && C.x != near, C.x);
+            push(g1 && C.y != near, C.y);
+            push(g2 && C.z != near, C.z);
+            push(g3 && C.w != near, C.w);
+            node = near >= 0 ? near : pop();
+            // bound on the walk: a damaged tree can give wrong answers, never a hang
+            if (++steps >= a.max_steps) node = -1;
+          }
+        } else if (want) {
             const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
             const float4 q0 = q[0], q1 = q[1], q2 = q[2];
             const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
-            const float lim = (MODE & M_FIRST) && !(MODE & M_ALL) ? L.tlim : 1.0f;
+            const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
             float tl, tr;
             const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
             const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
@@ -410,30 +469,37 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             // other one when both were (a full stack, possible only in a
             // damaged tree, drops it)
             const bool take_l = gl && (!gr || tl <= tr);
-            if (gl && gr && sp < depth_off) {
-                const int32_t far_child = take_l ? cr : cl;
-                if (!HYB || sp < lds_off) stk[sp] = far_child;
-                else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = far_child;
-                sp += stride;
-            }
-            if (gl || gr) {
-                node = take_l ? cl : cr;
-            } else if (sp > 0) {
-                sp -= stride;
-                if (!HYB || sp < lds_off) node = stk[sp];
-                else node = a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid];
-            } else {
-                node = -1;
-            }
+            push(gl && gr, take_l ? cr : cl);
+            node = (gl || gr) ? (take_l ? cl : cr) : pop();
             // bound on the walk: a damaged tree can give wrong answers, never a hang
             if (++steps >= a.max_steps) node = -1;
         }
 
         // ---- test pending leaves once few lanes can still step
-        const uint64_t pend = __ballot(leaf0 != 0);
+        const uint64_t pend = __ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) != 0 : leaf0 != 0);
         if (pend != 0 && (int)__popcll(w) < a.defer) {
             if (COUNT) ++w_leaf;
-            do {
+            if constexpr (WIDE) {
+                // one pending leaf per lane and round, the first occupied slot
+                do {
+                    const int32_t cur = leaf0 ? leaf0 : (leaf1 ? leaf1 : (leaf2 ? leaf2 : leaf3));
+                    if (cur != 0) {
+                        const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, cur, tests);
+                        if (stop) {
+                            leaf0 = leaf1 = leaf2 = leaf3 = 0;
+                            node = -1;
+                        } else if (leaf0 == cur) {
+                            leaf0 = 0;
+                        } else if (leaf1 == cur) {
+                            leaf1 = 0;
+                        } else if (leaf2 == cur) {
+                            leaf2 = 0;
+                        } else {
+                            leaf3 = 0;
+                        }
+                    }
+                } while (__ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
+            } else do {
                 if (leaf0 != 0) {
                     const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
                     leaf0 = stop ? 0 : leaf1;
@@ -470,13 +536,40 @@ __global__ void k_fill_miss(int64_t n_r, uint32_t mode, QueryOut o)
         o.uv[2 * i] = o.uv[2 * i + 1] = 0.0f;
         o.point[3 * i] = o.point[3 * i + 1] = o.point[3 * i + 2] = 0.0f;
     }
+    if (mode & (M_ALL | M_COUNT)) o.count[i] = 0;
     if (mode & M_ALL) {
-        o.count[i] = 0;
         for (int c = 0; c < o.cap; ++c) {
             o.ids[i * (int64_t)o.cap + c] = -1;
             o.ts[i * (int64_t)o.cap + c] = INFINITY;
         }
     }
+}
+
+// Far end of the inside-test segment of every point: P + L u with the fixed
+// direction u and L = |P - c| + 2R + 1 (c, R: centre and half diagonal of
+// the mesh's bounding box, the entry node's first child box), so the end lies
+// outside the box and every crossing of the surface is counted.
+__global__ void k_inside_ends(const float *__restrict__ P, int64_t n, const Node *__restrict__ entry,
+                              float *__restrict__ E)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *b = entry->f;
+    const float cx = 0.5f * (b[0] + b[3]), cy = 0.5f * (b[1] + b[4]), cz = 0.5f * (b[2] + b[5]);
+    const float hx = 0.5f * (b[3] - b[0]), hy = 0.5f * (b[4] - b[1]), hz = 0.5f * (b[5] - b[2]);
+    const float R = sqrtf(hx * hx + hy * hy + hz * hz);
+    const float px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
+    const float qx = px - cx, qy = py - cy, qz = pz - cz;
+    const float L = sqrtf(qx * qx + qy * qy + qz * qz) + 2.0f * R + 1.0f;
+    E[3 * i] = px + L * kInsideDir[0];
+    E[3 * i + 1] = py + L * kInsideDir[1];
+    E[3 * i + 2] = pz + L * kInsideDir[2];
+}
+
+__global__ void k_parity(const int32_t *__restrict__ count, int64_t n, uint8_t *__restrict__ inside)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inside[i] = (uint8_t)(count[i] & 1);
 }
 
 // Reset the work counter (and the overflow totals for a first all-hits pass)
@@ -495,10 +588,10 @@ __global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
     }
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB>
+template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE>
 hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    auto kern = k_query<MODE, SPILL, COUNT, BATCH, HYB>;
+    auto kern = k_query<MODE, SPILL, COUNT, BATCH, HYB, WIDE>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
     if (e != hipSuccess) return e;
@@ -530,8 +623,12 @@ hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
 template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH = false>
 hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true>(a, block, lds, s);
-    return launch_kernel<MODE, SPILL, COUNT, BATCH, false>(a, block, lds, s);
+    if (a.nodes4) {
+        if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true, true>(a, block, lds, s);
+        return launch_kernel<MODE, SPILL, COUNT, BATCH, false, true>(a, block, lds, s);
+    }
+    if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true, false>(a, block, lds, s);
+    return launch_kernel<MODE, SPILL, COUNT, BATCH, false, false>(a, block, lds, s);
 }
 
 template <bool COUNT>
@@ -546,6 +643,10 @@ hipError_t dispatch(uint32_t mode, const QArgs &a, int block, size_t lds, hipStr
     case M_ALL | M_BOOL: return launch_mode<M_ALL | M_BOOL, false, COUNT>(a, block, lds, s);
     case M_ALL | M_FIRST: return launch_mode<M_ALL | M_FIRST, false, COUNT>(a, block, lds, s);
     case M_ALL | M_FIRST | M_BOOL: return launch_mode<M_ALL | M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_COUNT: return launch_mode<M_COUNT, false, COUNT>(a, block, lds, s);
+    case M_COUNT | M_BOOL: return launch_mode<M_COUNT | M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_COUNT | M_FIRST: return launch_mode<M_COUNT | M_FIRST, false, COUNT>(a, block, lds, s);
+    case M_COUNT | M_FIRST | M_BOOL: return launch_mode<M_COUNT | M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -559,17 +660,31 @@ int fit_block(int want, int depth)
     return b;
 }
 
-// LDS part of the stack: the whole stack unless a smaller cap is set.
+// Traversal-stack entries a lane can need: one pushed sibling per binary
+// level (height + 1); in the four-way walk up to three per four-way level,
+// of which there are at most (height + 2) / 2 + 1.
+int full_depth(const rsi_bvh *h)
+{
+    if (h->width_built == 4) return 3 * ((h->height + 2) / 2 + 1) + 1;
+    return h->height + 1;
+}
+
+// LDS part of the stack: the whole stack unless a smaller cap is set; the
+// four-way walk keeps 16 entries in LDS by default (its worst-case depth is
+// about 1.5x the binary one while typical walks stay far below it).
 int lds_part(const rsi_bvh *h)
 {
-    const int depth = h->height + 1;
-    return (h->stack_cap > 0 && h->stack_cap < depth) ? h->stack_cap : depth;
+    const int depth = full_depth(h);
+    int cap = h->stack_cap;
+    if (cap <= 0 && h->width_built == 4) cap = 16;
+    return (cap > 0 && cap < depth) ? cap : depth;
 }
 
 QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, const QueryOut &o)
 {
     QArgs a;
     a.nodes = h->nodes;
+    a.nodes4 = h->width_built == 4 ? h->nodes4 : nullptr;
     a.tris = h->tris;
     a.entry = h->n_t > 0 ? (int32_t)(h->h_tri_off[1] - 1) : -1;
     a.S = S;
@@ -584,7 +699,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.pool_ids = h->pool_ids;
     a.pool_ts = h->pool_ts;
     a.counters = h->counters;
-    a.depth = h->height + 1;
+    a.depth = full_depth(h);
     a.lds_depth = lds_part(h);
     a.gstack = h->gstack;
     a.gstack_cap = h->gstack_cap;
@@ -648,7 +763,7 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
 
 hipError_t ensure_gstack(rsi_bvh *h)
 {
-    const int depth = h->height + 1;
+    const int depth = full_depth(h);
     const int ld = lds_part(h);
     if (ld >= depth) return hipSuccess;
     int dev = 0, n_cu = 0, max_threads = 0;
@@ -665,6 +780,21 @@ hipError_t ensure_gstack(rsi_bvh *h)
     e = hipMalloc(reinterpret_cast<void **>(&h->gstack), sizeof(int32_t) * (size_t)need);
     if (e == hipSuccess) h->gstack_cap = need;
     return e;
+}
+
+hipError_t launch_inside_ends(const rsi_bvh *h, const float *P, int64_t n, float *E, hipStream_t s)
+{
+    if (n == 0 || h->n_t == 0) return hipSuccess;
+    const Node *entry = h->nodes + (h->h_tri_off[1] - 1);
+    hipLaunchKernelGGL(k_inside_ends, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, n, entry, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_parity(const int32_t *count, int64_t n, uint8_t *inside, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_parity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, count, n, inside);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s)

@@ -30,6 +30,21 @@ struct alignas(64) Node {
 };
 static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 
+// Node4 (128 bytes, one L2 line): the four-way view of binary node n, whose
+// children are n's grandchildren (a child that is a leaf stands for itself),
+// stored coordinate-major so each float4 holds one coordinate of the four
+// child boxes.  Record n of the Node4 array belongs to binary node n, so a
+// child reference (an internal grandchild's index, or a leaf) is valid in
+// both arrays.  Unused slots have the box (FLT_MAX, ..., FLT_MAX), which no
+// segment touches.
+struct alignas(128) Node4 {
+    float lx[4], ly[4], lz[4];
+    float hx[4], hy[4], hz[4];
+    int32_t ref[4];
+    int32_t pad[4];
+};
+static_assert(sizeof(Node4) == 128, "Node4 must be 128 bytes");
+
 // Tri: the three FP32 vertices of a triangle in Morton (sorted) order plus
 // its original id, 48 bytes = three 16-byte loads.  Storing the vertices
 // themselves (rather than edges) keeps the FP64 re-solve of reported hits
@@ -65,12 +80,18 @@ struct Seg {
 
 __device__ inline float guarded_rcp(float d)
 {
-    // A zero (or denormal) component is replaced by +-1e-30: every slab
-    // parameter stays finite or +-inf and never NaN, and shrinking |1/d|
-    // only widens the accepted interval, so the box test stays conservative.
+    // Components below 1e-30 in magnitude (zero included) use +-1e-30, so
+    // every slab parameter is finite or +-inf and never NaN.  A capped
+    // reciprocal keeps the box decision exact while every nonzero coordinate
+    // difference is at least 1e-30 (coordinates of magnitude >= ~1e-23, or
+    // zero): then |(plane - o) * 1e30| >= 1 lies outside [0, 1] on the same
+    // side as the exact parameter.  (plane == o with d == 0 is a segment
+    // lying in a box face, which meets the triangles inside only on their
+    // boundary.)  The hardware reciprocal is within 1 ulp, which the slack
+    // of slab_hit covers.
     const float tiny = 1e-30f;
-    float g = fabsf(d) < tiny ? copysignf(tiny, d) : d;
-    return 1.0f / g;
+    const float g = fabsf(d) < tiny ? copysignf(tiny, d) : d;
+    return __builtin_amdgcn_rcpf(g);
 }
 
 __device__ inline Seg make_seg(float sx, float sy, float sz, float ex, float ey, float ez)
@@ -85,10 +106,11 @@ __device__ inline Seg make_seg(float sx, float sy, float sz, float ex, float ey,
 }
 
 // Conservative segment / box test (slab method).  Each slab parameter is
-// (plane - o) * (1/d): a subtraction and a product, so its relative error is
-// at most about 3 ulp with no absolute term; accepting when
-// near <= far * (1 + 2^-20) therefore never rejects a box that the exact
-// segment touches within [0, tmax].  Returns the entry parameter in `tnear`.
+// (plane - o) * (1/d): a subtraction, a reciprocal within 1 ulp and a
+// product, so its relative error is at most about 4 ulp (2^-22) with no
+// absolute term; accepting when near <= far * (1 + 2^-20) therefore never
+// rejects a box that the exact segment touches within [0, tmax].  Returns
+// the entry parameter in `tnear`.
 __device__ inline bool slab_hit(const Seg &s, float lx, float ly, float lz,
                                 float hx, float hy, float hz, float tmax, float &tnear)
 {

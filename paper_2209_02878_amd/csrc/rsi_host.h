@@ -20,7 +20,8 @@ enum Scalar {
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments (lo, hi words)
     kOvfTotalHi = 11,
     kWorkNext = 12,    // next unclaimed work item of the running query kernel
-    kNumScalars = 16
+    kSegBounds = 16,   // 6 ordered ints: bounding box of segment midpoints (segment order)
+    kNumScalars = 32
 };
 
 struct Counters {
@@ -114,9 +115,29 @@ struct rsi_bvh {
     hipGraphExec_t graph = nullptr;
     hipStream_t capture_stream = nullptr;
 
+    // four-way view of the tree (branching 4): requested width, and the width
+    // the current tree was laid out for
+    int32_t width = 2;
+    int32_t width_built = 2;
+    rsi::Node4 *nodes4 = nullptr;
+
     // global part of the traversal stack when stack_cap is below the height
     int32_t *gstack = nullptr;
     int64_t gstack_cap = 0;
+
+    // segment order: keys and sort scratch sized for the segments
+    uint64_t *seg_keys = nullptr;
+    int64_t seg_key_cap = 0;
+    rsi::SortScratch seg_sort;
+
+    // stream compaction: per-block counts and their scan (+ total)
+    int32_t *compact_counts = nullptr;
+    int64_t compact_cap = 0;
+
+    // inside test: far ends and counts when the caller passes none
+    float *aux_E = nullptr;
+    int32_t *aux_count = nullptr;
+    int64_t aux_cap = 0;
 
     // pinned host mirror of `scalars`
     int32_t *h_scalars = nullptr;
@@ -154,6 +175,16 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
 hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mode, const QueryOut &o,
                         hipStream_t s);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);
+hipError_t launch_widen(rsi_bvh *h, hipStream_t s);
+hipError_t launch_segment_order(rsi_bvh *h, const float *S, const float *E, int64_t n, int32_t *order,
+                                hipStream_t s);
+hipError_t launch_gather_segments(rsi_bvh *h, const float *S, const float *E, const int32_t *order, int64_t n,
+                                  float *So, float *Eo, hipStream_t s);
+hipError_t launch_compact(rsi_bvh *h, const uint8_t *hit, const float *S, const float *E, const int32_t *tri,
+                          const float *t, const float *point, int64_t n, int32_t *ids, float *dist,
+                          int32_t *tri_out, float *point_out, int64_t *n_out, hipStream_t s);
+hipError_t launch_inside_ends(const rsi_bvh *h, const float *P, int64_t n, float *E, hipStream_t s);
+hipError_t launch_parity(const int32_t *count, int64_t n, uint8_t *inside, hipStream_t s);
 hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s);
 // size the global part of the traversal stack (call outside graph capture)
 hipError_t ensure_gstack(rsi_bvh *h);

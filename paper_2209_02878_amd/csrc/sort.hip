@@ -2,16 +2,20 @@
 // 8-bit digits, LDS-staged (the "sort Morton codes" step of the paper's
 // Table 2, which there ran on the host).
 //
-// One pass per digit, three launches per pass:
+// One pass per digit:
 //   k_hist     per-tile digit histogram in LDS -> hist[digit][tile]
 //   k_scan     one workgroup turns hist into exclusive global offsets
 //              (digit-major, so the offset of (digit, tile) is the count of
-//              all smaller digits plus this digit in earlier tiles); with at
-//              most 64 tiles every scatter workgroup derives its own offsets
-//              from the histograms instead and this launch is skipped
+//              all smaller digits plus this digit in earlier tiles)
 //   k_scatter  per tile: stable rank of every element among equal digits
 //              via wave64 ballots, reorder the tile in LDS by digit, then
 //              write each digit run to its global offset (contiguous runs)
+// With at most 64 tiles (inputs up to 128k elements, where the passes are
+// latency bound) every scatter workgroup derives its own offsets from the
+// raw histograms (no k_scan) and also counts the next pass's digits of the
+// elements it writes, per destination tile, so only the first pass needs
+// k_hist: one launch per pass.  Three histogram buffers rotate: pass p reads
+// H[p % 3], adds into H[(p + 1) % 3] and clears H[(p + 2) % 3] for pass p + 1.
 // Tiles are 256 threads x 8 items in striped order (item r of thread x is
 // element r*256 + x), which fixes the stable order (r, wave, lane).
 #include <hip/hip_runtime.h>
@@ -44,10 +48,13 @@ struct Digit {
 
 __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ vals, int64_t n, Digit dg,
-                                                   uint32_t *__restrict__ hist, int ntiles)
+                                                   uint32_t *__restrict__ hist, int ntiles,
+                                                   uint32_t *__restrict__ clear)
 {
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x;
+    // `clear` (may be null): a histogram buffer the next scatter adds into
+    if (clear) clear[(int64_t)tid * ntiles + blockIdx.x] = 0;
     h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -89,6 +96,56 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t *__restrict__ a, int64_t
     }
 }
 
+// Large tables (many tiles): a three-launch scan.  k_part_sums reduces
+// blocks of kScanChunk counts, k_scan scans those sums (one workgroup), and
+// k_part_apply rescans each block from its offset.
+constexpr int kScanChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_part_sums(const uint32_t *__restrict__ a, int64_t n,
+                                                   uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t ws[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (int k = threadIdx.x; k < kScanChunk; k += 256) {
+        const int64_t i = base + k;
+        if (i < n) s += a[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (__lane_id() == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_part_apply(uint32_t *__restrict__ a, int64_t n,
+                                                    const uint32_t *__restrict__ part)
+{
+    // each thread owns 16 consecutive counts of the block's 4096
+    __shared__ uint32_t ts[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * 16;
+    uint32_t v[16];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = base + k < n ? a[base + k] : 0u;
+        s += v[k];
+    }
+    ts[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t x = (int)threadIdx.x >= off ? ts[threadIdx.x - off] : 0u;
+        __syncthreads();
+        ts[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint32_t run = part[blockIdx.x] + ts[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+}
+
 __device__ inline uint64_t lanemask_lt()
 {
     const uint32_t lane = __lane_id();
@@ -117,28 +174,45 @@ __device__ inline void scan256(const uint32_t *in, uint32_t *out)
 }
 
 // FUSED: `offs` holds the raw per-tile histograms and each workgroup forms
-// its own global digit offsets (used when there are few tiles, which saves
-// the separate scan launch); otherwise `offs` is the scanned table.
+// its own global digit offsets (few tiles: this saves the separate scan
+// launch); it then also adds the next pass's digit counts of the elements it
+// writes into `hnext` (per destination tile) and clears `hclear`.  Otherwise
+// `offs` is the scanned table.
 template <bool FUSED>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                       int64_t n, Digit dg, const uint32_t *__restrict__ offs,
-                                                      int ntiles)
+                                                      int ntiles, Digit dnext, uint32_t *__restrict__ hnext,
+                                                      uint32_t *__restrict__ hclear)
 {
-    __shared__ uint32_t run[kRadix];          // elements of each digit ranked so far in this tile
-    __shared__ uint32_t wcnt[kWaves][kRadix]; // per-wave digit counts of the current round
-    __shared__ uint32_t start[kRadix];        // exclusive scan of the tile's digit counts
-    __shared__ uint32_t gbase[kRadix];        // global offset of (digit, this tile)
+    // wcnt[r][w][d]: elements with digit d held by wave w in round r; after
+    // the scan, the number of elements with digit d before (r, w) in the tile
+    __shared__ uint32_t wcnt[kItems][kWaves][kRadix];
+    __shared__ uint32_t run[kRadix];    // the tile's count of each digit
+    __shared__ uint32_t start[kRadix];  // exclusive scan of run[]
+    __shared__ uint32_t gbase[kRadix];  // global offset of (digit, this tile)
     __shared__ uint64_t skey[kTile];
     __shared__ uint32_t sval[kTile];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    run[tid] = 0;
+
+    // all loads first: one memory latency for the whole tile
+    uint64_t key[kItems];
+    uint32_t val[kItems];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + r * kThreads + tid;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0u;
+    }
+    if (FUSED && hclear) hclear[(int64_t)tid * ntiles + blockIdx.x] = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcnt[r][w][tid] = 0;
     if (FUSED) {
         // digit tid: elements in earlier tiles and in all tiles
         uint32_t before = 0, total = 0;
@@ -154,24 +228,19 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         gbase[tid] += before;
     } else {
         gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+        __syncthreads();
     }
-    __syncthreads();
 
-    uint64_t key[kItems];
-    uint32_t val[kItems];
+    // per round: the lanes of this wave holding the same digit (8 ballots);
+    // the lowest of them records the group size
     uint32_t dig[kItems];
-    uint32_t rank[kItems];
+    uint32_t below[kItems];
     const uint64_t lt = lanemask_lt();
-
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r * kThreads + tid;
-        const bool valid = i < n;
-        key[r] = valid ? kin[i] : 0ull;
-        val[r] = valid ? vin[i] : 0u;
+        const bool valid = base + r * kThreads + tid < n;
         const uint32_t d = valid ? dg(key[r], val[r]) : 0u;
         dig[r] = d;
-        // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -179,32 +248,31 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t below = (uint32_t)__popcll(peers & lt);
-        if (valid && below == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t before = run[d];
-        for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-        rank[r] = before + below;
-        __syncthreads();
-        uint32_t tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            tot += wcnt[w][tid];
-            wcnt[w][tid] = 0;
-        }
-        run[tid] += tot;
-        __syncthreads();
+        below[r] = (uint32_t)__popcll(peers & lt);
+        if (valid && below[r] == 0) wcnt[r][wave][d] = (uint32_t)__popcll(peers);
     }
-
-    // exclusive scan of the tile's per-digit counts (run[]) into start[]
+    __syncthreads();
+    // digit tid: exclusive prefix over (round, wave) in the tile's stable order
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int r = 0; r < kItems; ++r)
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wcnt[r][w][tid];
+                wcnt[r][w][tid] = acc;
+                acc += c;
+            }
+        run[tid] = acc;
+    }
+    __syncthreads();
     scan256(run, start);
     __syncthreads();
 
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + r * kThreads + tid;
-        if (i < n) {
-            const uint32_t p = start[dig[r]] + rank[r];
+        if (base + r * kThreads + tid < n) {
+            const uint32_t p = start[dig[r]] + wcnt[r][wave][dig[r]] + below[r];
             skey[p] = key[r];
             sval[p] = val[r];
         }
@@ -220,6 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         const int64_t dst = (int64_t)gbase[d] + (p - start[d]);
         kout[dst] = k;
         vout[dst] = v;
+        if (FUSED && hnext) atomicAdd(&hnext[(int64_t)dnext(k, v) * ntiles + dst / kTile], 1u);
     }
 }
 
@@ -249,7 +318,10 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
         sc.cap = n;
     }
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    const int64_t hn = ntiles * kRadix;
+    // fused path: three rotating histograms; else one table plus the
+    // partial sums of the three-launch scan
+    const int64_t hn = ntiles <= kFusedTiles ? 3 * ntiles * kRadix
+                                             : ntiles * kRadix + (ntiles * kRadix + kScanChunk - 1) / kScanChunk;
     if (hn > sc.hist_cap) {
         if (sc.hist) (void)hipFree(sc.hist);
         sc.hist = nullptr;
@@ -286,19 +358,39 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     }
     uint64_t *ka = keys, *kb = sc.keys_alt;
     uint32_t *va = vals, *vb = sc.vals_alt;
-    for (int p = 0; p < np; ++p) {
-        const Digit dg = passes[p];
-        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles);
-        if (ntiles <= kFusedTiles) {
-            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
-                               sc.hist, ntiles);
-        } else {
-            hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, (int64_t)ntiles * kRadix);
-            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
-                               sc.hist, ntiles);
+    const int64_t hsz = (int64_t)ntiles * kRadix;
+    if (ntiles <= kFusedTiles) {
+        // H[0] from k_hist (which also clears H[1]); then one scatter per pass
+        uint32_t *H[3] = {sc.hist, sc.hist + hsz, sc.hist + 2 * hsz};
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, passes[0], H[0], ntiles,
+                           np > 1 ? H[1] : nullptr);
+        for (int p = 0; p < np; ++p) {
+            const Digit dn = p + 1 < np ? passes[p + 1] : passes[p];
+            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, passes[p],
+                               H[p % 3], ntiles, dn, p + 1 < np ? H[(p + 1) % 3] : nullptr,
+                               p + 2 < np ? H[(p + 2) % 3] : nullptr);
+            uint64_t *tk = ka; ka = kb; kb = tk;
+            uint32_t *tv = va; va = vb; vb = tv;
         }
-        uint64_t *tk = ka; ka = kb; kb = tk;
-        uint32_t *tv = va; va = vb; vb = tv;
+    } else {
+        for (int p = 0; p < np; ++p) {
+            const Digit dg = passes[p];
+            hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles,
+                               nullptr);
+            if (hsz <= 4 * kScanChunk) {
+                hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, hsz);
+            } else {
+                const int64_t nparts = (hsz + kScanChunk - 1) / kScanChunk;
+                uint32_t *part = sc.hist + hsz;
+                hipLaunchKernelGGL(k_part_sums, dim3((unsigned)nparts), dim3(256), 0, s, sc.hist, hsz, part);
+                hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, part, nparts);
+                hipLaunchKernelGGL(k_part_apply, dim3((unsigned)nparts), dim3(256), 0, s, sc.hist, hsz, part);
+            }
+            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
+                               sc.hist, ntiles, dg, nullptr, nullptr);
+            uint64_t *tk = ka; ka = kb; kb = tk;
+            uint32_t *tv = va; va = vb; vb = tv;
+        }
     }
     if (ka != keys) {
         const int blk = 256;

@@ -19,11 +19,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librsi.so")
 
 RSI_OK, RSI_E_INVALID, RSI_E_NOMEM, RSI_E_HIP, RSI_E_OVERFLOW = range(5)
-RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS = 1, 2, 4
-MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS}
+RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS, RSI_COUNT = 1, 2, 4, 8
+MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS, "count": RSI_COUNT}
 
 EXPORTED = [
-    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_first_hit_backward",
+    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_compact", "rsi_segment_order", "rsi_gather_segments", "rsi_inside", "rsi_first_hit_backward",
     "rsi_spill_info", "rsi_spill_read",
     "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_get_mesh_info", "rsi_export_tree",
     "rsi_batch_create", "rsi_batch_rebuild", "rsi_batch_query", "rsi_batch_capture", "rsi_batch_replay",
@@ -41,7 +41,8 @@ class RsiError(RuntimeError):
 class rsi_opts(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("defer_lanes", ctypes.c_int32), ("refill_lanes", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("chunk", ctypes.c_int32), ("stack_depth", ctypes.c_int32), ("branching", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class rsi_tune_job(ctypes.Structure):
@@ -88,6 +89,10 @@ def lib():
     L.rsi_rebuild.argtypes = [H, P, i64, P, P]
     L.rsi_refit.argtypes = [H, P, P]
     L.rsi_query.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
+    L.rsi_inside.argtypes = [H, P, i64, P, P, P, P]
+    L.rsi_segment_order.argtypes = [H, P, P, i64, P, P]
+    L.rsi_gather_segments.argtypes = [H, P, P, P, i64, P, P, P]
+    L.rsi_compact.argtypes = [H, P, P, P, P, P, P, i64, P, P, P, P, ctypes.POINTER(i64), P]
     L.rsi_first_hit_backward.argtypes = [H, P, P, P, i64, P, P, P, P, P, P, P, P]
     L.rsi_spill_info.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.rsi_spill_read.argtypes = [H, P, P, P, P, P, P]
@@ -150,11 +155,12 @@ def _dev_i32(x, name):
 
 # ------------------------------------------------------------ C functions --
 
-def rsi_build(V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0):
+def rsi_build(V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0,
+              stack_depth=0, branching=0):
     V = _dev_f32(V, "V")
     T = _dev_i32(T, "T")
     h = ctypes.c_void_p()
-    o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk)
+    o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk, stack_depth, branching)
     _check(lib().rsi_build(_ptr(V), V.shape[0], _ptr(T), T.shape[0], ctypes.byref(o), _stream(stream),
                            ctypes.byref(h)))
     return h
@@ -200,6 +206,27 @@ def rsi_first_hit_backward(h, V, S, E, tri, g_t=None, g_uv=None, g_point=None, d
     _check(lib().rsi_first_hit_backward(h, _ptr(V), _ptr(S), _ptr(E), n, _ptr(tri), _ptr(g_t), _ptr(g_uv),
                                         _ptr(g_point), _ptr(dV), _ptr(dS), _ptr(dE), _stream(stream)))
     return dV, dS, dE
+
+
+def rsi_segment_order(h, S, E, order, stream=None):
+    _check(lib().rsi_segment_order(h, _ptr(S), _ptr(E), S.shape[0], _ptr(order), _stream(stream)))
+
+
+def rsi_gather_segments(h, S, E, order, S_out, E_out, stream=None):
+    _check(lib().rsi_gather_segments(h, _ptr(S), _ptr(E), _ptr(order), S.shape[0], _ptr(S_out), _ptr(E_out),
+                                     _stream(stream)))
+
+
+def rsi_compact(h, n_r, ids, hit=None, tri=None, t=None, point=None, S=None, E=None, dist=None, tri_out=None,
+                point_out=None, stream=None):
+    n = ctypes.c_int64()
+    _check(lib().rsi_compact(h, _ptr(hit), _ptr(tri), _ptr(t), _ptr(point), _ptr(S), _ptr(E), n_r, _ptr(ids),
+                             _ptr(dist), _ptr(tri_out), _ptr(point_out), ctypes.byref(n), _stream(stream)))
+    return n.value
+
+
+def rsi_inside(h, P, inside, count=None, E=None, stream=None):
+    _check(lib().rsi_inside(h, _ptr(P), P.shape[0], _ptr(inside), _ptr(count), _ptr(E), _stream(stream)))
 
 
 def rsi_spill_info(h):
@@ -251,7 +278,7 @@ def rsi_export_tree(h):
             **info}
 
 
-OPT_FIELDS = ("leaf_size", "block_size", "defer_lanes", "refill_lanes", "chunk", "stack_depth")
+OPT_FIELDS = ("leaf_size", "block_size", "defer_lanes", "refill_lanes", "chunk", "stack_depth", "branching")
 
 
 def make_opts(d=None):
@@ -301,11 +328,12 @@ class Mesh:
     """A BVH over a triangle mesh on the current HIP device."""
 
     def __init__(self, V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0,
-                 chunk=0):
+                 chunk=0, stack_depth=0, branching=0):
         self.V = V
         self.T = T
         self.n_t = T.shape[0]
-        self.handle = rsi_build(V, T, leaf_size, block_size, stream, defer_lanes, refill_lanes, chunk)
+        self.handle = rsi_build(V, T, leaf_size, block_size, stream, defer_lanes, refill_lanes, chunk,
+                                stack_depth, branching)
 
     def rebuild(self, V, T, stream=None):
         rsi_rebuild(self.handle, V, T, stream)
@@ -324,8 +352,9 @@ class Mesh:
             out["t"] = torch.empty(n_r, dtype=torch.float32, device=dev)
             out["uv"] = torch.empty(n_r, 2, dtype=torch.float32, device=dev)
             out["point"] = torch.empty(n_r, 3, dtype=torch.float32, device=dev)
-        if mode & RSI_ALL_HITS:
+        if mode & (RSI_ALL_HITS | RSI_COUNT):
             out["count"] = torch.empty(n_r, dtype=torch.int32, device=dev)
+        if mode & RSI_ALL_HITS:
             out["ids"] = torch.empty(n_r, capacity, dtype=torch.int32, device=dev)
             out["ts"] = torch.empty(n_r, capacity, dtype=torch.float32, device=dev)
         return out
@@ -355,6 +384,49 @@ class Mesh:
                       "ts": torch.empty(ntot, dtype=torch.float32, device=dev)}
                 rsi_spill_read(self.handle, sp["seg"], sp["offset"], sp["count"], sp["ids"], sp["ts"], stream)
                 out["spill"] = sp
+        return out
+
+    def barycentric(self, S, E, stream=None):
+        """The paper's `barycentric` output (Section 2.4): intersecting rays,
+        distances, intersecting triangles, intersecting points, for the
+        segments that cross the mesh (first hit of each)."""
+        r = self.query(S, E, "first", stream=stream)
+        n = S.shape[0]
+        dev = S.device
+        ids = torch.empty(n, dtype=torch.int32, device=dev)
+        dist = torch.empty(n, dtype=torch.float32, device=dev)
+        tri = torch.empty(n, dtype=torch.int32, device=dev)
+        pts = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        k = rsi_compact(self.handle, n, ids, tri=r["tri"], t=r["t"], point=r["point"], S=S, E=E, dist=dist,
+                        tri_out=tri, point_out=pts, stream=stream)
+        return {"intersecting_rays": ids[:k], "distances": dist[:k], "intersecting_triangles": tri[:k],
+                "intersecting_points": pts[:k]}
+
+    def segment_order(self, S, E, stream=None):
+        """Morton order of the segments (octant of the direction, then the
+        midpoint's 30-bit code) and the segments gathered into it."""
+        S, E = _dev_f32(S, "S"), _dev_f32(E, "E")
+        order = torch.empty(S.shape[0], dtype=torch.int32, device=S.device)
+        rsi_segment_order(self.handle, S, E, order, stream)
+        So, Eo = torch.empty_like(S), torch.empty_like(E)
+        rsi_gather_segments(self.handle, S, E, order, So, Eo, stream)
+        return order, So, Eo
+
+    def crossing_ids(self, hit, stream=None):
+        """Ids of the segments whose boolean output is set, in order."""
+        ids = torch.empty(hit.shape[0], dtype=torch.int32, device=hit.device)
+        k = rsi_compact(self.handle, hit.shape[0], ids, hit=hit, stream=stream)
+        return ids[:k]
+
+    def inside(self, P, stream=None):
+        """Odd-parity inside test of points P [n, 3]: returns inside (uint8),
+        the crossing counts and the far segment ends used."""
+        P = _dev_f32(P, "P")
+        n = P.shape[0]
+        out = {"inside": torch.empty(n, dtype=torch.uint8, device=P.device),
+               "count": torch.empty(n, dtype=torch.int32, device=P.device),
+               "E": torch.empty(n, 3, dtype=torch.float32, device=P.device)}
+        rsi_inside(self.handle, P, out["inside"], out["count"], out["E"], stream)
         return out
 
     def first_hit_backward(self, V, S, E, tri, g_t=None, g_uv=None, g_point=None, stream=None):
@@ -411,14 +483,15 @@ class Batch:
     one persistent query launch over every (mesh, segment) item, and an
     optional HIP graph of rebuild + query replayed with one launch."""
 
-    def __init__(self, meshes, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0):
+    def __init__(self, meshes, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0,
+                 stack_depth=0, branching=0):
         self.meshes = [(_dev_f32(V, "V"), _dev_i32(T, "T")) for V, T in meshes]
         M = len(self.meshes)
         self._V = _ptr_array([V for V, _ in self.meshes])
         self._T = _ptr_array([T for _, T in self.meshes])
         self._nv = (ctypes.c_int64 * M)(*[V.shape[0] for V, _ in self.meshes])
         self._nt = (ctypes.c_int64 * M)(*[T.shape[0] for _, T in self.meshes])
-        o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk)
+        o = rsi_opts(leaf_size, block_size, defer_lanes, refill_lanes, chunk, stack_depth, branching)
         h = ctypes.c_void_p()
         _check(lib().rsi_batch_create(M, ctypes.cast(self._V, ctypes.c_void_p), ctypes.cast(self._nv, ctypes.c_void_p),
                                       ctypes.cast(self._T, ctypes.c_void_p), ctypes.cast(self._nt, ctypes.c_void_p),

@@ -7,8 +7,8 @@ matter most first -- and remembers the winner per (device, workload kind,
 mode, size bucket) in a JSON file, so a later run of the same shape can skip
 the search.
 
-Tunable: block size, LDS stack depth, leaf size (needs a rebuild), defer and
-refill lane thresholds, chunk size.
+Tunable: branching (the binary tree or its four-way view), block size, LDS
+stack depth, leaf size (needs a rebuild), defer and refill lane thresholds.
 """
 from __future__ import annotations
 
@@ -22,8 +22,9 @@ DEFAULT_CACHE = os.environ.get("RSI_TUNE_CACHE", os.path.join(os.path.expanduser
 
 # staged search: each stage varies some options on top of the best so far
 STAGES = [
-    # stack_depth 255 keeps the whole stack in LDS (it is capped at the tree height + 1)
-    [{"block_size": b, "stack_depth": s} for b in (64, 128, 256) for s in (255, 8, 12, 16)],
+    [{"branching": w, "block_size": b} for w in (2, 4) for b in (64, 128, 256)],
+    # stack_depth 255 keeps the whole stack in LDS (it is capped at the walk's worst-case depth)
+    [{"stack_depth": s} for s in (255, 8, 12, 16, 24)],
     [{"defer_lanes": d, "refill_lanes": r} for d in (16, 32, 48) for r in (16, 32, 48)],
     [{"leaf_size": leaf} for leaf in (1, 2, 4)],
 ]

@@ -341,6 +341,15 @@ def config4(n_r: int = 4_000_000, n: int = 317) -> Workload:
     return Workload(f"heightfield-{T.shape[0]}tri-{n_r}seg-diff", V, T, S, E)
 
 
+def inside_points(V, n: int, seed: int) -> np.ndarray:
+    """Points for the odd-parity inside test: uniform in 1.5x the mesh box
+    (about centre), FP32."""
+    lo, hi = mesh_bbox(V)
+    c, h = 0.5 * (lo + hi), 0.75 * (hi - lo)
+    rng = np.random.default_rng(seed)
+    return rng.uniform(c - h, c + h, (n, 3)).astype(np.float32)
+
+
 def subset(n_total: int, n_pick: int, seed: int) -> np.ndarray:
     """Seeded sorted sample of segment indices."""
     if n_pick >= n_total:

@@ -1,0 +1,135 @@
+"""The four-way traversal (branching 4) gives exactly the binary walk's answers.
+
+The four-way view lists, for every binary node, the boxes of its
+grandchildren (the binary tree of Section 3.1 seen two levels at a time), so
+the same leaves are reached and the same triangle tests decide; the FP64
+re-solve of every reported crossing is the same too.  All outputs must
+therefore be bit-identical to the binary walk, in every mode, with a small
+LDS stack (device-memory tail), with larger leaves, after a refit, in a
+batch and in a captured graph; and they must match the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2209_02878_amd import rsi
+from paper_2209_02878_amd import workloads as wl
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
+
+
+def _equal(a, b, tag):
+    for key in a:
+        if isinstance(a[key], dict):
+            _equal(a[key], b[key], tag + "." + key)
+        else:
+            assert torch.equal(a[key], b[key]), (tag, key)
+
+
+def _both(mesh, S, E, mode, cap=4):
+    mesh.set_opts(branching=2)
+    r2 = mesh.query(S, E, mode, capacity=cap)
+    mesh.set_opts(branching=4)
+    assert mesh.opts()["branching"] == 4
+    r4 = mesh.query(S, E, mode, capacity=cap)
+    torch.cuda.synchronize()
+    return r2, r4
+
+
+@pytest.mark.parametrize("mode", ["bool", "first", "all|first", "count"])
+def test_wide_equals_binary_heightfield(mode):
+    w = wl.config2(n_r=200_000)
+    mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32))
+    r2, r4 = _both(mesh, _t(w.S), _t(w.E), mode, cap=2)
+    _equal(r2, r4, mode)
+    mesh.close()
+
+
+def test_wide_equals_binary_closed_sphere_with_spill_and_small_stack():
+    w = wl.config3(n_r=500_000)
+    mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32))
+    S, E = _t(w.S), _t(w.E)
+    r2, r4 = _both(mesh, S, E, "all|first|bool", cap=2)
+    _equal(r2, r4, "sphere")
+    assert "spill" in r4
+    # four LDS entries: the rest of the stack lives in device memory
+    mesh.set_opts(branching=4, stack_depth=4)
+    r4s = mesh.query(S, E, "all|first|bool", capacity=2)
+    torch.cuda.synchronize()
+    _equal(r2, r4s, "sphere-small-stack")
+    mesh.close()
+
+
+def test_wide_oracle_parity_config1_full():
+    w = wl.config1()
+    mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32), leaf_size=4)
+    mesh.set_opts(branching=4)
+    got = mesh.query(_t(w.S), _t(w.E), "bool|first")
+    torch.cuda.synchronize()
+    ref = parity.oracle_reference(w.V, w.T, w.S, w.E)
+    rep = parity.compare(ref, {k: v.cpu().numpy() for k, v in got.items()}, {"bool", "first"})
+    parity.assert_parity(rep)
+    mesh.close()
+
+
+def test_wide_after_refit_and_rebuild():
+    w = wl.config4(n_r=200_000)
+    V, T = _t(w.V), _t(w.T, torch.int32)
+    S, E = _t(w.S), _t(w.E)
+    mesh = rsi.Mesh(V, T, branching=4)
+    assert mesh.opts()["branching"] == 4
+    V2 = V.clone()
+    V2[:, 2] += 0.05 * torch.sin(7 * V2[:, 0])
+    mesh.refit(V2)
+    r4 = mesh.query(S, E, "first")
+    fresh = rsi.Mesh(V2, T)
+    r2 = fresh.query(S, E, "first")
+    torch.cuda.synchronize()
+    _equal(r2, r4, "refit")
+    mesh.rebuild(V, T)
+    r4b = mesh.query(S, E, "first")
+    fresh.rebuild(V, T)
+    r2b = fresh.query(S, E, "first")
+    torch.cuda.synchronize()
+    _equal(r2b, r4b, "rebuild")
+    mesh.close()
+    fresh.close()
+
+
+def test_wide_batch_and_graph():
+    ws = wl.config5(n_meshes=8, tri_lo=500, tri_hi=20_000, seg_lo=2_000, seg_hi=30_000, seed=321)
+    meshes = [(_t(w.V), _t(w.T, torch.int32)) for w in ws]
+    segs = [(_t(w.S), _t(w.E)) for w in ws]
+    b = rsi.Batch(meshes)
+    ref = b.query(segs, "bool|first")
+    b.set_opts(branching=4)
+    got = b.query(segs, "bool|first")
+    torch.cuda.synchronize()
+    for k in range(len(ws)):
+        _equal(ref[k], got[k], ws[k].name)
+    outs = b.alloc_outputs(segs, "bool|first")
+    b.capture(segs, "bool|first", outs, rebuild=True)
+    for _ in range(3):
+        b.replay()
+        torch.cuda.synchronize()
+        for k in range(len(ws)):
+            _equal(ref[k], outs[k], "graph-" + ws[k].name)
+        b.query(segs, "bool")  # eager work between replays
+    b.close()
+
+
+def test_branching_option_validation():
+    w = wl.config1(n_r=100)
+    mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32))
+    with pytest.raises(rsi.RsiError):
+        mesh.set_opts(branching=3)
+    assert mesh.opts()["branching"] == 2
+    mesh.close()

@@ -2,9 +2,12 @@
 
 The query kernel culls with a slab test in FP32: per axis the parameters
 (plane - o) * (1/d), each a subtraction and a product, with direction
-components below 1e-30 in magnitude replaced by +-1e-30, and acceptance
-when near <= far * (1 + 2^-20).  This test restates that arithmetic
-bit-exactly in Python (FP32 operations through numpy) and checks it against an
+components below 1e-30 in magnitude replaced by +-1e-30, the reciprocal
+taken by the hardware instruction (within 1 ulp), and acceptance when
+near <= far * (1 + 2^-20).  This test restates that arithmetic in Python
+(FP32 operations through numpy; the reciprocal correctly rounded and then
+moved by -1, 0 or +1 ulp at random, covering any result the instruction may
+give) and checks it against an
 exact rational slab test on the same FP32 segment, over random and
 adversarial cases: endpoints on faces, nearly parallel segments, flat boxes,
 origins far from short segments, zero and tiny direction components.  A
@@ -20,11 +23,18 @@ import pytest
 F32 = np.float32
 
 
+_ulp_rng = np.random.default_rng(5)
+
+
 def slab_accepts(s, e, lo, hi, tmax=F32(1.0)):
     d = (e - s).astype(F32)
     tiny = F32(1e-30)
     g = np.where(np.abs(d) < tiny, np.copysign(tiny, d), d).astype(F32)
     inv = (F32(1.0) / g).astype(F32)
+    for k in range(3):
+        step = _ulp_rng.integers(-1, 2)
+        if step:
+            inv[k] = np.nextafter(inv[k], F32(np.inf) if step > 0 else F32(-np.inf)).astype(F32)
     t0 = ((lo - s).astype(F32) * inv).astype(F32)
     t1 = ((hi - s).astype(F32) * inv).astype(F32)
     near = max(max(min(t0[0], t1[0]), min(t0[1], t1[1])), max(min(t0[2], t1[2]), F32(0.0)))

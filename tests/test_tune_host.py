@@ -28,16 +28,18 @@ def test_staged_search_keeps_best_of_each_stage():
 
     def run_stage(cands):
         seen.append(cands)
-        # prefer block 64 / stack 12, then defer 48 refill 16, then leaf 2
+        # prefer branching 4 / block 64, stack 12, then defer 48 refill 16, then leaf 2
         def cost(c):
-            return (abs(c.get("block_size", 128) - 64) + abs(c.get("stack_depth", 0) - 12)
+            return (abs(c.get("branching", 2) - 4) + abs(c.get("block_size", 128) - 64)
+                    + abs(c.get("stack_depth", 0) - 12)
                     + abs(c.get("defer_lanes", 32) - 48) + abs(c.get("refill_lanes", 32) - 16)
                     + abs(c.get("leaf_size", 1) - 2))
         ms = [float(cost(c)) for c in cands]
         return ms.index(min(ms)), ms
 
     best, log = tune.staged_search(run_stage)
-    assert best == {"block_size": 64, "stack_depth": 12, "defer_lanes": 48, "refill_lanes": 16, "leaf_size": 2}
+    assert best == {"branching": 4, "block_size": 64, "stack_depth": 12, "defer_lanes": 48, "refill_lanes": 16,
+                    "leaf_size": 2}
     assert len(seen) == len(tune.STAGES)
     # later stages carry the earlier winners
     assert all(c["block_size"] == 64 for c in seen[1])
