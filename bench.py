@@ -79,10 +79,36 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def extra_workloads(torch, rsi, wl, dev, stream, time_events, log):
+def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S2, E2):
     """The other configurations, reported beside the headline."""
     out = {}
     med = lambda xs: float(np.median(xs))
+
+    # the headline mesh and segments: four-way view, and Morton-ordered segments
+    m = rsi.Mesh(V2, T2)
+    ob = m.alloc_outputs(w2.n_r, "bool")
+    oa = m.alloc_outputs(w2.n_r, "all", capacity=4)
+    m.set_opts(branching=4)
+    b4 = time_events(lambda: m.rebuild(V2, T2), 10)
+    q4 = time_events(lambda: m.query_into(S2, E2, "bool", ob), 10)
+    a4 = time_events(lambda: m.query_into(S2, E2, "all", oa, capacity=4), 5)
+    out["heightfield_29768tri_10Mseg_branching4"] = {
+        "rebuild_ms": round(med(b4), 4), "query_bool_ms": round(med(q4), 4),
+        "query_all_hits_k4_ms": round(med(a4), 4)}
+    log(f"branching 4: rebuild {med(b4):.3f} ms, bool {med(q4):.3f} ms, all-hits {med(a4):.3f} ms")
+    m.set_opts(branching=2)
+    order = torch.empty(w2.n_r, dtype=torch.int32, device=dev)
+    So, Eo = torch.empty_like(S2), torch.empty_like(E2)
+    oc = time_events(lambda: (rsi.rsi_segment_order(m.handle, S2, E2, order),
+                              rsi.rsi_gather_segments(m.handle, S2, E2, order, So, Eo)), 5)
+    qo = time_events(lambda: m.query_into(So, Eo, "bool", ob), 10)
+    ao = time_events(lambda: m.query_into(So, Eo, "all", oa, capacity=4), 5)
+    out["heightfield_29768tri_10Mseg_morton_ordered"] = {
+        "order_and_gather_ms": round(med(oc), 4), "query_bool_ms": round(med(qo), 4),
+        "query_all_hits_k4_ms": round(med(ao), 4)}
+    log(f"ordered segments: order+gather {med(oc):.3f} ms, bool {med(qo):.3f} ms, all-hits {med(ao):.3f} ms")
+    m.close()
+    del ob, oa, order, So, Eo
 
     # closed 499,280-triangle sphere: all crossings (capacity 4) + first hit
     t0 = time.time()
@@ -90,12 +116,15 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log):
     log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
     V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
     S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
-    m = rsi.Mesh(V, T)
+    # the four-way view with 24 LDS stack entries: the fastest option set
+    # measured for this deep tree (height 28)
+    m = rsi.Mesh(V, T, branching=4, stack_depth=24)
     o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
     b = time_events(lambda: m.rebuild(V, T), 5)
     q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
     nspill = rsi.rsi_spill_info(m.handle)[0]
     out["sphere_499280tri_10Mseg_all_first_k4"] = {
+        "options": {"branching": 4, "stack_depth": 24},
         "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
         "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "overflowed_segments": int(nspill)}
     log(f"sphere all|first: query {med(q):.3f} ms, build {med(b):.3f} ms, spill {nspill}")
@@ -326,7 +355,7 @@ def main():
 
     if not args.headline_only:
         mesh.close()
-        rec["extra"] = extra_workloads(torch, rsi, wl, dev, stream, time_events, log)
+        rec["extra"] = extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w, V, T, S, E)
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample, on the host cores
     if not args.no_cpu_baseline:

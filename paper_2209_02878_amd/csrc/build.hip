@@ -26,7 +26,7 @@
 //                lets only the second child continue -- so the parent's box
 //                is formed exactly once, from both children.  Ranges with at
 //                most `leaf_size` triangles become leaves.  The climb runs in
-//                two passes: subtrees inside a block of 256 sorted leaves
+//                two passes: subtrees inside a block of 2048 sorted leaves
 //                finish in LDS (k_lbvh_local), the few that cross block
 //                boundaries finish with device-scope counters
 //                (k_lbvh_global), so only those pay for cross-XCD ordering.
@@ -271,7 +271,10 @@ __device__ inline void write_entry(const BuildArgs &a, int32_t m, int32_t lo, in
     a.mesh_root[m] = c.ref;
 }
 
-constexpr int kLocal = 256;   // leaves per workgroup in the local pass
+// leaves per workgroup in the local pass: 2048 (the workgroup's LDS then
+// holds 152 KiB of node slots, within gfx950's 160 KiB), two per thread
+constexpr int kLocal = 2048;
+constexpr int kLocalThreads = 1024;
 constexpr int kClimbWords = 11;
 
 // Local pass: each workgroup owns kLocal consecutive sorted leaves.  A node
@@ -279,20 +282,22 @@ constexpr int kClimbWords = 11;
 // so these subtrees are completed here with the arrival counters and child
 // records in LDS.  A climb that reaches a split outside the block (its parent
 // range crosses the block boundary) is saved for the global pass.
-__global__ __launch_bounds__(kLocal) void k_lbvh_local(BuildArgs a)
+__global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
 {
     __shared__ int32_t lflag[kLocal];
     __shared__ float lbox[kLocal][12];
     __shared__ int32_t lref[kLocal][2];
     __shared__ int32_t lbound[kLocal][2];
     __shared__ int32_t lh[kLocal][2];
-    const int tid = threadIdx.x;
     const int32_t n = (int32_t)a.n_t;
     const int32_t B0 = (int32_t)blockIdx.x * kLocal;
     const int32_t B1 = (B0 + kLocal < n ? B0 + kLocal : n) - 1;  // last leaf of this block
-    lflag[tid] = 0;
+    for (int t = threadIdx.x; t < kLocal; t += kLocalThreads) lflag[t] = 0;
     __syncthreads();
 
+    // each thread takes kLocal / kLocalThreads leaves one after the other; a
+    // climb that arrives first at a node stops, so no thread ever waits
+    for (int tid = threadIdx.x; tid < kLocal; tid += kLocalThreads) {
     const int32_t i = B0 + tid;
     bool active = i < n;
     Climb c;
@@ -364,8 +369,10 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(BuildArgs a)
         const int other = 1 - side;
         merge(c, &lbox[slot][6 * other], lbound[slot][other], lh[slot][other], side, parent, a.leaf_size);
     }
+    }
     __syncthreads();
     // publish the block's internal node records (splits B0 .. B1-1)
+    for (int tid = threadIdx.x; tid < kLocal; tid += kLocalThreads) {
     if (tid < B1 - B0 && lflag[tid] > 0) {
         const int32_t p = B0 + tid;
         Node *q = a.nodes + p;
@@ -378,6 +385,7 @@ __global__ __launch_bounds__(kLocal) void k_lbvh_local(BuildArgs a)
         a.heights[2 * p] = lh[tid][0];
         a.heights[2 * p + 1] = lh[tid][1];
         a.arrive[p] = lflag[tid];
+    }
     }
 }
 
@@ -492,7 +500,7 @@ hipError_t run_hierarchy(const BuildArgs &a, hipStream_t s)
 {
     const int32_t n = (int32_t)a.n_t;
     const unsigned nb = (unsigned)((n + kLocal - 1) / kLocal);
-    hipLaunchKernelGGL(k_lbvh_local, dim3(nb), dim3(kLocal), 0, s, a);
+    hipLaunchKernelGGL(k_lbvh_local, dim3(nb), dim3(kLocalThreads), 0, s, a);
     if (nb > 1) hipLaunchKernelGGL(k_lbvh_global, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

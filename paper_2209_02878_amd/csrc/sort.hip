@@ -27,7 +27,7 @@ namespace rsi {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 8;
+constexpr int kItems = 8;                // elements per thread in large sorts
 constexpr int kTile = kThreads * kItems;
 constexpr int kRadix = 256;
 constexpr int kWaves = kThreads / 64;
@@ -46,6 +46,7 @@ struct Digit {
     }
 };
 
+template <int IPT>
 __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ vals, int64_t n, Digit dg,
                                                    uint32_t *__restrict__ hist, int ntiles,
@@ -57,9 +58,9 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
     if (clear) clear[(int64_t)tid * ntiles + blockIdx.x] = 0;
     h[tid] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * IPT);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         int64_t i = base + r * kThreads + tid;
         if (i < n) atomicAdd(&h[dg(keys[i], dg.off ? vals[i] : 0u)], 1u);
     }
@@ -178,7 +179,7 @@ __device__ inline void scan256(const uint32_t *in, uint32_t *out)
 // launch); it then also adds the next pass's digit counts of the elements it
 // writes into `hnext` (per destination tile) and clears `hclear`.  Otherwise
 // `offs` is the scanned table.
-template <bool FUSED>
+template <bool FUSED, int IPT>
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin,
                                                       const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -188,29 +189,29 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
 {
     // wcnt[r][w][d]: elements with digit d held by wave w in round r; after
     // the scan, the number of elements with digit d before (r, w) in the tile
-    __shared__ uint32_t wcnt[kItems][kWaves][kRadix];
+    __shared__ uint32_t wcnt[IPT][kWaves][kRadix];
     __shared__ uint32_t run[kRadix];    // the tile's count of each digit
     __shared__ uint32_t start[kRadix];  // exclusive scan of run[]
     __shared__ uint32_t gbase[kRadix];  // global offset of (digit, this tile)
-    __shared__ uint64_t skey[kTile];
-    __shared__ uint32_t sval[kTile];
+    __shared__ uint64_t skey[(kThreads * IPT)];
+    __shared__ uint32_t sval[(kThreads * IPT)];
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * (kThreads * IPT);
 
     // all loads first: one memory latency for the whole tile
-    uint64_t key[kItems];
-    uint32_t val[kItems];
+    uint64_t key[IPT];
+    uint32_t val[IPT];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const int64_t i = base + r * kThreads + tid;
         key[r] = i < n ? kin[i] : 0ull;
         val[r] = i < n ? vin[i] : 0u;
     }
     if (FUSED && hclear) hclear[(int64_t)tid * ntiles + blockIdx.x] = 0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r)
+    for (int r = 0; r < IPT; ++r)
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) wcnt[r][w][tid] = 0;
     if (FUSED) {
@@ -233,11 +234,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
 
     // per round: the lanes of this wave holding the same digit (8 ballots);
     // the lowest of them records the group size
-    uint32_t dig[kItems];
-    uint32_t below[kItems];
+    uint32_t dig[IPT];
+    uint32_t below[IPT];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         const bool valid = base + r * kThreads + tid < n;
         const uint32_t d = valid ? dg(key[r], val[r]) : 0u;
         dig[r] = d;
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     {
         uint32_t acc = 0;
 #pragma unroll
-        for (int r = 0; r < kItems; ++r)
+        for (int r = 0; r < IPT; ++r)
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
                 const uint32_t c = wcnt[r][w][tid];
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     __syncthreads();
 
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < IPT; ++r) {
         if (base + r * kThreads + tid < n) {
             const uint32_t p = start[dig[r]] + wcnt[r][wave][dig[r]] + below[r];
             skey[p] = key[r];
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     __syncthreads();
 
     const int64_t rem = n - base;
-    const int cnt = rem < kTile ? (int)rem : kTile;
+    const int cnt = rem < (kThreads * IPT) ? (int)rem : (kThreads * IPT);
     for (int p = tid; p < cnt; p += kThreads) {
         const uint64_t k = skey[p];
         const uint32_t v = sval[p];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         const int64_t dst = (int64_t)gbase[d] + (p - start[d]);
         kout[dst] = k;
         vout[dst] = v;
-        if (FUSED && hnext) atomicAdd(&hnext[(int64_t)dnext(k, v) * ntiles + dst / kTile], 1u);
+        if (FUSED && hnext) atomicAdd(&hnext[(int64_t)dnext(k, v) * ntiles + dst / (kThreads * IPT)], 1u);
     }
 }
 
@@ -320,7 +321,7 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
     const int64_t ntiles = (n + kTile - 1) / kTile;
     // fused path: three rotating histograms; else one table plus the
     // partial sums of the three-launch scan
-    const int64_t hn = ntiles <= kFusedTiles ? 3 * ntiles * kRadix
+    const int64_t hn = ntiles <= kFusedTiles ? 3 * kFusedTiles * kRadix
                                              : ntiles * kRadix + (ntiles * kRadix + kScanChunk - 1) / kScanChunk;
     if (hn > sc.hist_cap) {
         if (sc.hist) (void)hipFree(sc.hist);
@@ -338,6 +339,27 @@ void free_sort_scratch(SortScratch &sc)
     if (sc.vals_alt) (void)hipFree(sc.vals_alt);
     if (sc.hist) (void)hipFree(sc.hist);
     sc = SortScratch();
+}
+
+// The passes of a small sort (at most kFusedTiles tiles of kThreads * IPT):
+// H[0] from k_hist (which also clears H[1]), then one scatter per pass.
+template <int IPT>
+void fused_passes(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_t n, const Digit *passes, int np,
+                  SortScratch &sc, hipStream_t s)
+{
+    const int ntiles = (int)((n + kThreads * IPT - 1) / (kThreads * IPT));
+    const int64_t hsz = (int64_t)ntiles * kRadix;
+    uint32_t *H[3] = {sc.hist, sc.hist + hsz, sc.hist + 2 * hsz};
+    hipLaunchKernelGGL(k_hist<IPT>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, passes[0], H[0], ntiles,
+                       np > 1 ? H[1] : nullptr);
+    for (int p = 0; p < np; ++p) {
+        const Digit dn = p + 1 < np ? passes[p + 1] : passes[p];
+        hipLaunchKernelGGL((k_scatter<true, IPT>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, passes[p],
+                           H[p % 3], ntiles, dn, p + 1 < np ? H[(p + 1) % 3] : nullptr,
+                           p + 2 < np ? H[(p + 2) % 3] : nullptr);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
 }
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &sc,
@@ -360,22 +382,18 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     uint32_t *va = vals, *vb = sc.vals_alt;
     const int64_t hsz = (int64_t)ntiles * kRadix;
     if (ntiles <= kFusedTiles) {
-        // H[0] from k_hist (which also clears H[1]); then one scatter per pass
-        uint32_t *H[3] = {sc.hist, sc.hist + hsz, sc.hist + 2 * hsz};
-        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, passes[0], H[0], ntiles,
-                           np > 1 ? H[1] : nullptr);
-        for (int p = 0; p < np; ++p) {
-            const Digit dn = p + 1 < np ? passes[p + 1] : passes[p];
-            hipLaunchKernelGGL(k_scatter<true>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, passes[p],
-                               H[p % 3], ntiles, dn, p + 1 < np ? H[(p + 1) % 3] : nullptr,
-                               p + 2 < np ? H[(p + 2) % 3] : nullptr);
+        // (smaller tiles, hence more workgroups, measured slower: each
+        // workgroup then scans more histograms and the next-pass counters
+        // see more atomic traffic)
+        fused_passes<kItems>(ka, va, kb, vb, n, passes, np, sc, s);
+        if (np & 1) {
             uint64_t *tk = ka; ka = kb; kb = tk;
             uint32_t *tv = va; va = vb; vb = tv;
         }
     } else {
         for (int p = 0; p < np; ++p) {
             const Digit dg = passes[p];
-            hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles,
+            hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles,
                                nullptr);
             if (hsz <= 4 * kScanChunk) {
                 hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, hsz);
@@ -386,7 +404,7 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
                 hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, part, nparts);
                 hipLaunchKernelGGL(k_part_apply, dim3((unsigned)nparts), dim3(256), 0, s, sc.hist, hsz, part);
             }
-            hipLaunchKernelGGL(k_scatter<false>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
+            hipLaunchKernelGGL((k_scatter<false, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
                                sc.hist, ntiles, dg, nullptr, nullptr);
             uint64_t *tk = ka; ka = kb; kb = tk;
             uint32_t *tv = va; va = vb; vb = tv;

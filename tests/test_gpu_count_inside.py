@@ -109,8 +109,16 @@ def test_inside_config3_mesh_two_million_points():
     r = np.linalg.norm(P.astype(np.float64), axis=1)
     inner, outer = r < 0.999 * r_in, r > 1.001 * r_out
     assert inner.sum() > 10_000 and outer.sum() > 10_000
-    assert np.all(ins[inner] == 1)
-    assert np.all(ins[outer] == 0)
+    # FP32 Moller-Trumbore is not watertight: a segment through a shared edge
+    # or vertex can be counted twice or not at all.  Every point whose parity
+    # disagrees with the closed form must be such a degenerate case.
+    wrong = np.nonzero((inner & (ins == 0)) | (outer & (ins == 1)))[0]
+    assert wrong.size <= 1e-4 * P.shape[0]
+    if wrong.size:
+        Ew = out["E"].cpu().numpy()[wrong]
+        L = float(np.linalg.norm(V.max(0) - V.min(0)))
+        deg = oracle.degenerate(V, T, P[wrong], Ew, 1e-6 * L)
+        assert np.all(deg != 0), wrong[deg == 0]
     sel = wl.subset(P.shape[0], 1000, wl.seed_for(6, 4))
     E = out["E"].cpu().numpy()[sel]
     ref = parity.oracle_reference(V, T, P[sel], E)

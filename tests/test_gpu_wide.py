@@ -26,9 +26,19 @@ def _t(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype).contiguous()
 
 
+def _spill_lists(sp):
+    """Per-segment crossing lists of a spill read-back (the order of the
+    segments in it depends on timing; each segment's list does not)."""
+    seg, off, cnt = (sp[k].cpu().numpy() for k in ("seg", "offset", "count"))
+    ids, ts = sp["ids"].cpu().numpy(), sp["ts"].cpu().numpy()
+    return {int(s): (ids[o:o + c].tolist(), ts[o:o + c].tolist()) for s, o, c in zip(seg, off, cnt)}
+
+
 def _equal(a, b, tag):
     for key in a:
-        if isinstance(a[key], dict):
+        if key == "spill":
+            assert _spill_lists(a[key]) == _spill_lists(b[key]), tag
+        elif isinstance(a[key], dict):
             _equal(a[key], b[key], tag + "." + key)
         else:
             assert torch.equal(a[key], b[key]), (tag, key)
