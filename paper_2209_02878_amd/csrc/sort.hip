@@ -1,5 +1,5 @@
 // sort.hip -- stable LSD radix sort of (uint64 key, uint32 value) pairs,
-// 8-bit digits, LDS-staged (the "sort Morton codes" step of the paper's
+// 8-bit digits, LDS-staged (the Morton-code sorting step timed in the paper's
 // Table 2, which there ran on the host).
 //
 // One pass per digit:
