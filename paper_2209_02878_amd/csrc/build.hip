@@ -54,6 +54,7 @@ struct BuildArgs {
     float *cent;
     uint64_t *keys;
     uint32_t *order;
+    int32_t *rank;
     Node *nodes;
     Tri *tris;
     int32_t *arrive;
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
             atomicOr(&a.scalars[kBadIndex], 2);
             id = lo;
         }
+        a.rank[id] = i;
         int32_t va = a.T[3 * id], vb = a.T[3 * id + 1], vd = a.T[3 * id + 2];
         // an out-of-range index is reported by k_centroids; read vertex 0
         // instead so that no access leaves the vertex array
@@ -483,6 +485,7 @@ BuildArgs make_build_args(rsi_bvh *h, const float *V)
     a.cent = h->cent;
     a.keys = h->keys;
     a.order = h->order;
+    a.rank = h->rank;
     a.nodes = h->nodes;
     a.tris = h->tris;
     a.arrive = h->arrive;

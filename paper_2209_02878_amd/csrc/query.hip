@@ -281,7 +281,9 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
     Lane L;
-    int64_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
+    // work items number below 2^30 (checked at the boundary), so item and
+    // chunk arithmetic is 32-bit; the chunk bounds are wave-uniform
+    int32_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
     int32_t node = -1;   // next node to visit; < 0: none
     // stack pointer kept as an element offset into the [depth][lane] LDS
     // array (entries x stride), so a push or pop needs no multiply
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     int32_t steps = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
-    int64_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
+    int32_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
+    const int32_t n_items = (int32_t)a.n_items;
     bool exhausted = false;                 // the global counter has passed the last item
 
     for (;;) {
@@ -314,11 +317,11 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 item = -1;
             }
             const uint64_t idle = __ballot(item == -1);
-            const int64_t n_idle = (int64_t)__popcll(idle);
-            const int64_t rank = (int64_t)lanes_below(idle);
-            int64_t k = -1;
-            const int64_t avail = chunk_end - chunk_next;
-            const int64_t used = avail < n_idle ? avail : n_idle;
+            const int32_t n_idle = (int32_t)__popcll(idle);
+            const int32_t rank = (int32_t)lanes_below(idle);
+            int32_t k = -1;
+            const int32_t avail = chunk_end - chunk_next;
+            const int32_t used = avail < n_idle ? avail : n_idle;
             if (rank < used) k = chunk_next + rank;
             chunk_next += used;
             if (used < n_idle && !exhausted) {
@@ -326,13 +329,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 int32_t base = 0;
                 if ((int)__lane_id() == leader) base = atomicAdd(work, a.chunk);
                 base = __shfl(base, leader, 64);
-                if (base >= a.n_items) {
+                if (base >= n_items) {
                     exhausted = true;
                 } else {
-                    chunk_next = base;
-                    chunk_end = base + a.chunk < a.n_items ? base + a.chunk : a.n_items;
-                    const int64_t room = chunk_end - chunk_next;
-                    const int64_t more = n_idle - used < room ? n_idle - used : room;
+                    chunk_next = __builtin_amdgcn_readfirstlane(base);
+                    chunk_end = base + a.chunk < n_items ? base + a.chunk : n_items;
+                    chunk_end = __builtin_amdgcn_readfirstlane(chunk_end);
+                    const int32_t room = chunk_end - chunk_next;
+                    const int32_t more = n_idle - used < room ? n_idle - used : room;
                     if (rank >= used && rank - used < more) k = chunk_next + (rank - used);
                     chunk_next += more;
                 }
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             if (item == -1) {
                 if (k >= 0) {
                     item = k;
-                    int64_t i = k;
+                    int32_t i = k;
                     int32_t entry = a.entry;
                     L.slot_base = (MODE & M_ALL) ? k * (int64_t)a.o.cap : 0;
                     L.spill_cap = 0;
@@ -351,15 +355,15 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     }
                     if (BATCH) {
                         const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
-                        i = k - a.bt.seg_off[m];
+                        i = (int32_t)(k - a.bt.seg_off[m]);
                         L.mesh = m;
-                        L.sp = a.bt.S[m] + 3 * i;
-                        L.ep = a.bt.E[m] + 3 * i;
+                        L.sp = a.bt.S[m] + 3 * (int64_t)i;
+                        L.ep = a.bt.E[m] + 3 * (int64_t)i;
                         entry = a.mesh_entry[m];
                     } else {
                         L.mesh = 0;
-                        L.sp = a.S + 3 * i;
-                        L.ep = a.E + 3 * i;
+                        L.sp = a.S + 3 * (int64_t)i;
+                        L.ep = a.E + 3 * (int64_t)i;
                     }
                     L.seg_i = i;
                     L.seg = make_seg(L.sp[0], L.sp[1], L.sp[2], L.ep[0], L.ep[1], L.ep[2]);

@@ -87,6 +87,7 @@ struct rsi_bvh {
     float *cent = nullptr;         // centroids SoA [3*n_t]
     uint64_t *keys = nullptr;      // Morton codes, sorted in place [n_t]
     uint32_t *order = nullptr;     // original triangle per sorted position [n_t]
+    int32_t *rank = nullptr;       // sorted position of each triangle (inverse of order) [n_t]
     rsi::Node *nodes = nullptr;    // [max(n_t, 1)]; each mesh's last record is its entry node
     rsi::Tri *tris = nullptr;      // [n_t] in sorted order
     int32_t *arrive = nullptr;     // arrival counters [n_t]
@@ -125,9 +126,12 @@ struct rsi_bvh {
     int32_t *gstack = nullptr;
     int64_t gstack_cap = 0;
 
-    // segment order: keys and sort scratch sized for the segments
+    // segment order (and the adjoint's hit order): keys, values and sort
+    // scratch sized for the segments
     uint64_t *seg_keys = nullptr;
     int64_t seg_key_cap = 0;
+    uint32_t *adj_vals = nullptr;
+    int64_t adj_val_cap = 0;
     rsi::SortScratch seg_sort;
 
     // stream compaction: per-block counts and their scan (+ total)
