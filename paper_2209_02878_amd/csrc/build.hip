@@ -28,8 +28,9 @@
 //                most `leaf_size` triangles become leaves.  The climb runs in
 //                two passes: subtrees inside a block of 2048 sorted leaves
 //                finish in LDS (k_lbvh_local), the few that cross block
-//                boundaries finish with device-scope counters
-//                (k_lbvh_global), so only those pay for cross-XCD ordering.
+//                boundaries finish in k_lbvh_global, which exchanges the
+//                climb data through memory past the per-XCD caches, so only
+//                those pay for cross-XCD ordering.
 //
 // The entry node of mesh m is its last record off[m+1] - 1 (unused by its
 // n - 1 internal nodes): its left child is the root and its right child an
@@ -392,9 +393,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
 }
 
 // Global pass: continue the climbs saved by the local pass.  Their parents
-// are shared between workgroups, so the arrival counter works at device
-// scope (the XCDs have separate L2 caches: release our writes, acquire the
-// sibling's).  Only the few subtrees that cross block boundaries remain.
+// are shared between workgroups on different XCDs, whose L2 caches are not
+// coherent with each other.  Release/acquire ordering at device scope would
+// write back and invalidate a whole L2 at every level of every climb;
+// instead the few words a sibling needs are written and read with
+// system-coherent accesses (past the per-XCD caches), the writes complete
+// before the arrival counter moves, and the counter is a system-coherent
+// atomic.  Only the subtrees that cross block boundaries remain.
 __global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
 {
     const int32_t n = (int32_t)a.n_t;
@@ -420,14 +425,27 @@ __global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
         int side;
         const int32_t parent = choose_parent(a.keys, lo, hi, c.l, c.r, side);
         Node *p = a.nodes + parent;
-        write_child(p, side, c.box, c.ref);
-        p->aux[side] = side ? c.r : c.l;
-        a.heights[2 * parent + side] = c.h;
-        const int32_t prev =
-            __hip_atomic_fetch_add(&a.arrive[parent], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // child data with system-coherent stores (they bypass the per-XCD
+        // caches), completed before the counter moves; the sibling reads
+        // them back with system-coherent loads, so no cache-wide write-back
+        // or invalidation is needed at any level
+        for (int k = 0; k < 6; ++k)
+            __hip_atomic_store(&p->f[6 * side + k], c.box[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&p->ref[side], c.ref, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&p->aux[side], side ? c.r : c.l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&a.heights[2 * parent + side], c.h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int32_t prev = __hip_atomic_fetch_add(&a.arrive[parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (prev == 0) return;  // the sibling finishes this parent
         const int other = 1 - side;
-        merge(c, p->f + 6 * other, p->aux[other], a.heights[2 * parent + other], side, parent, a.leaf_size);
+        float g[6];
+        for (int k = 0; k < 6; ++k)
+            g[k] = __hip_atomic_load(&p->f[6 * other + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const int32_t ob = __hip_atomic_load(&p->aux[other], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const int32_t oh = __hip_atomic_load(&a.heights[2 * parent + other], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        merge(c, g, ob, oh, side, parent, a.leaf_size);
     }
     write_entry(a, m, lo, hi, c);
 }
