@@ -32,8 +32,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # VALU lane-operations per unit of work, counted from the kernel source
-# (rsi_device.h): one segment / box slab test and one Moller-Trumbore test.
-OPS_PER_BOX_TEST = 26
+# (rsi_device.h, query.hip): one slab test of an exact box (binary walk), one
+# of a quantised box (four-way walk: each of the six planes is decoded with a
+# byte conversion and an fma before the multiply) plus the per-node set-up
+# of the four-way walk (exponent decode, corner offset, margin), and one
+# Moller-Trumbore test.
+OPS_PER_BOX_TEST = {2: 26, 4: 32}
+OPS_PER_NODE = {2: 0, 4: 18}
 OPS_PER_TRI_TEST = 45
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one VALU lane-op per lane per clock;
 # packed FP32 is not used)
@@ -84,19 +89,19 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     out = {}
     med = lambda xs: float(np.median(xs))
 
-    # the headline mesh and segments: four-way view, and Morton-ordered segments
+    # the headline mesh and segments: the binary walk, and Morton-ordered segments
     m = rsi.Mesh(V2, T2)
     ob = m.alloc_outputs(w2.n_r, "bool")
     oa = m.alloc_outputs(w2.n_r, "all", capacity=4)
-    m.set_opts(branching=4)
-    b4 = time_events(lambda: m.rebuild(V2, T2), 10)
-    q4 = time_events(lambda: m.query_into(S2, E2, "bool", ob), 10)
-    a4 = time_events(lambda: m.query_into(S2, E2, "all", oa, capacity=4), 5)
-    out["heightfield_29768tri_10Mseg_branching4"] = {
-        "rebuild_ms": round(med(b4), 4), "query_bool_ms": round(med(q4), 4),
-        "query_all_hits_k4_ms": round(med(a4), 4)}
-    log(f"branching 4: rebuild {med(b4):.3f} ms, bool {med(q4):.3f} ms, all-hits {med(a4):.3f} ms")
     m.set_opts(branching=2)
+    b2 = time_events(lambda: m.rebuild(V2, T2), 10)
+    q2 = time_events(lambda: m.query_into(S2, E2, "bool", ob), 10)
+    a2 = time_events(lambda: m.query_into(S2, E2, "all", oa, capacity=4), 5)
+    out["heightfield_29768tri_10Mseg_binary_walk"] = {
+        "rebuild_ms": round(med(b2), 4), "query_bool_ms": round(med(q2), 4),
+        "query_all_hits_k4_ms": round(med(a2), 4)}
+    log(f"binary walk: rebuild {med(b2):.3f} ms, bool {med(q2):.3f} ms, all-hits {med(a2):.3f} ms")
+    m.set_opts(branching=4)
     order = torch.empty(w2.n_r, dtype=torch.int32, device=dev)
     So, Eo = torch.empty_like(S2), torch.empty_like(E2)
     oc = time_events(lambda: (rsi.rsi_segment_order(m.handle, S2, E2, order),
@@ -116,15 +121,13 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
     V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
     S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
-    # the four-way view with 24 LDS stack entries: the fastest option set
-    # measured for this deep tree (height 28)
-    m = rsi.Mesh(V, T, branching=4, stack_depth=24)
+    m = rsi.Mesh(V, T)
     o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
     b = time_events(lambda: m.rebuild(V, T), 5)
     q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
     nspill = rsi.rsi_spill_info(m.handle)[0]
     out["sphere_499280tri_10Mseg_all_first_k4"] = {
-        "options": {"branching": 4, "stack_depth": 24},
+        "options": {k: m.opts()[k] for k in ("branching", "stack_depth")},
         "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
         "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "overflowed_segments": int(nspill)}
     log(f"sphere all|first: query {med(q):.3f} ms, build {med(b):.3f} ms, spill {nspill}")
@@ -226,6 +229,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 29,768-triangle step (for profiler runs)")
+    ap.add_argument("--branching", type=int, default=0, choices=(0, 2, 4),
+                    help="walk for the headline step: 4 = quantised four-way view (the default), 2 = binary tree")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (known traffic for HBM counter scaling)")
     args = ap.parse_args()
@@ -250,7 +255,7 @@ def main():
     E = torch.from_numpy(w.E).to(dev)
     stream = torch.cuda.current_stream()
 
-    mesh = rsi.Mesh(V, T)
+    mesh = rsi.Mesh(V, T, branching=args.branching)
     info = mesh.tree_info()
     out_b = mesh.alloc_outputs(w.n_r, "bool")
     out_a = mesh.alloc_outputs(w.n_r, "all", capacity=4)
@@ -296,7 +301,9 @@ def main():
     torch.cuda.synchronize()
     cnt = mesh.counters()
     mesh.set_counting(False)
-    ops = OPS_PER_BOX_TEST * cnt["box_tests"] + OPS_PER_TRI_TEST * cnt["tri_tests"]
+    br = mesh.opts()["branching"]
+    ops = (OPS_PER_BOX_TEST[br] * cnt["box_tests"] + OPS_PER_NODE[br] * cnt["node_visits"] +
+           OPS_PER_TRI_TEST * cnt["tri_tests"])
     achieved_tops = ops / (kb / 1e3) / 1e12
     hits = int(out_b["hit"].sum().item())
     log(f"counters: {cnt}; hit fraction {hits / w.n_r:.4f}")
@@ -321,6 +328,7 @@ def main():
                         "(start uniform in mesh box, direction uniform on sphere, length log-uniform [0.01,1]); "
                         "step = BVH rebuild + boolean query",
             "n_t": w.n_t, "n_r": w.n_r, "leaf_size": info["leaf_size"], "tree_height": info["height"],
+            "branching": mesh.opts()["branching"],
         },
         "query_bool_ms": round(float(np.median(q_bool)), 4),
         "query_bool_msegments_per_s": round(w.n_r / np.median(q_bool) / 1e3, 2),

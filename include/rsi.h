@@ -76,10 +76,14 @@ typedef struct {
                              device memory.  The whole stack (tree height + 1) stays in LDS by
                              default and for any value at or above it; a smaller value raises
                              occupancy. 1..255 */
-    int32_t branching;    /* 2: traverse the binary tree of Section 3.1 (default); 4: traverse
-                             its four-way view (every node with its grandchildren as children,
-                             one 128-byte record per node, laid out after each build, rebuild
-                             and refit).  Both give the same results. */
+    int32_t branching;    /* 4 (default): traverse the four-way view of the binary tree of
+                             Section 3.1 (every node with its grandchildren as children, child
+                             boxes quantised outward to 8 bits per plane, one 64-byte record
+                             per node, laid out after each build, rebuild and refit); 2:
+                             traverse the binary tree itself.  Both cull conservatively and
+                             decide with the same FP32 triangle test, so their answers agree
+                             except where that test is within rounding of its decision (the
+                             looser quantised boxes let a few more triangles reach it). */
     int32_t reserved;
 } rsi_opts;
 

@@ -48,7 +48,7 @@ void free_handle_memory(rsi_bvh *h)
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
     void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->compact_counts, h->nodes4, h->aux_E, h->aux_count, h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
-                    h->arrive, h->heights, h->climb, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
+                    h->arrive, h->heights, h->climb, h->split_prefix, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
                     h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off, h->vert_off, h->mesh_bounds,
                     h->mesh_height, h->mesh_root, h->mesh_entry, h->bt.seg_off, h->bt.S, h->bt.E, h->bt.hit,
                     h->bt.tri, h->bt.t, h->bt.uv, h->bt.point, h->bt_graph.seg_off, h->bt_graph.S,
@@ -59,6 +59,7 @@ void free_handle_memory(rsi_bvh *h)
     rsi::free_sort_scratch(h->sort);
     rsi::free_sort_scratch(h->seg_sort);
     if (h->h_scalars) (void)hipHostFree(h->h_scalars);
+    if (h->h_pub) (void)hipHostFree(h->h_pub);
 }
 
 void destroy_handle(rsi_bvh *h)
@@ -132,7 +133,6 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     h->n_t = h->h_tri_off[M];
     h->n_v = h->h_vert_off[M];
     h->h_height.assign(M, 0);
-    h->h_root.assign(M, 0);
     if (h->n_t >= (int64_t(1) << rsi::kLeafFirstBits)) {
         delete h;
         return invalid("total triangle count must be below 2^27");
@@ -156,6 +156,7 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     if (e == hipSuccess) e = dalloc(&h->arrive, n);
     if (e == hipSuccess) e = dalloc(&h->heights, 2 * n);
     if (e == hipSuccess) e = dalloc(&h->climb, 11 * n);
+    if (e == hipSuccess) e = dalloc(&h->split_prefix, n);
     if (e == hipSuccess) e = dalloc(&h->scalars, rsi::kNumScalars);
     if (e == hipSuccess) e = dalloc(&h->counters, 1);
     if (e == hipSuccess) e = dalloc(&h->tri_off, M + 1);
@@ -168,6 +169,8 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     if (e == hipSuccess && batch) e = alloc_tables(h->bt_graph, M);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->h_pub), sizeof(int32_t) * (2 + (size_t)M));
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&h->d_pub), h->h_pub, 0);
     if (e == hipSuccess && n > 0) e = rsi::ensure_sort_scratch(h->sort, n);
     if (e == hipSuccess)
         e = hipMemcpy(h->tri_off, h->h_tri_off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
@@ -183,26 +186,24 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     return RSI_OK;
 }
 
-// Wait for the build on `s`, then read back the index check and the tree
-// heights (which size the traversal stack).
+// Wait for the build on `s`, then read back the index checks and the tree
+// heights (which size the traversal stack): one small kernel writes them into
+// pinned host memory, so the wait ends right after the last build kernel.
 rsi_status finish_build(rsi_bvh *h, hipStream_t s, const char *who)
 {
     hipError_t e = hipSuccess;
-    if (h->n_t > 0) {
-        e = hipMemcpyAsync(h->h_scalars, h->scalars, sizeof(int32_t) * rsi::kNumScalars, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->h_height.data(), h->mesh_height, sizeof(int32_t) * h->M, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(h->h_root.data(), h->mesh_root, sizeof(int32_t) * h->M, hipMemcpyDeviceToHost, s);
-    }
+    if (h->n_t > 0) e = rsi::launch_publish(h, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, who);
     if (h->n_t > 0) {
-        if ((h->h_scalars[rsi::kBadIndex] & 1) || (h->src_V && h->h_scalars[rsi::kBadGather]))
-            return invalid("triangle index outside [0, n_v)");
-        if (h->h_scalars[rsi::kBadIndex]) return invalid("inconsistent build state (report this)");
+        const int32_t bad = h->h_pub[0], bad_gather = h->h_pub[1];
+        if ((bad & 1) || (h->src_V && bad_gather)) return invalid("triangle index outside [0, n_v)");
+        if (bad) return invalid("inconsistent build state (report this)");
         int32_t mx = 0;
-        for (int32_t v : h->h_height) mx = v > mx ? v : mx;
+        for (int32_t m = 0; m < h->M; ++m) {
+            h->h_height[m] = h->h_pub[2 + m];
+            mx = h->h_pub[2 + m] > mx ? h->h_pub[2 + m] : mx;
+        }
         h->height = mx;
     }
     return RSI_OK;

@@ -61,6 +61,7 @@ struct BuildArgs {
     int32_t *arrive;
     int32_t *heights;
     int32_t *climb;
+    uint8_t *prefix;       // [n_t] common-prefix length at sorted split k
     int32_t *bounds;       // [6M] ordered-int centroid bounds per mesh
     int32_t *mesh_height;  // [M]
     int32_t *mesh_root;    // [M]
@@ -203,15 +204,16 @@ __global__ void k_morton(BuildArgs a)
     a.order[j] = (uint32_t)j;
 }
 
-// Key distance between sorted neighbours k and k+1, compared
-// lexicographically as (key xor, index xor): equal keys are split by index,
-// so duplicate codes still form a valid radix tree.
-__device__ inline bool dist_less(const uint64_t *__restrict__ keys, int a, int b)
+// Common-prefix length of the augmented keys (key, index) of the sorted
+// neighbours k and k+1: the leading equal key bits while the keys differ,
+// else 64 plus the leading equal index bits, so equal keys are split by index
+// and duplicate codes still form a valid radix tree.  A longer prefix is a
+// smaller key distance.
+__device__ inline uint8_t split_prefix(const uint64_t *__restrict__ keys, int32_t k)
 {
-    const uint64_t xa = keys[a] ^ keys[a + 1];
-    const uint64_t xb = keys[b] ^ keys[b + 1];
-    if (xa != xb) return xa < xb;
-    return (uint32_t)(a ^ (a + 1)) < (uint32_t)(b ^ (b + 1));
+    const uint64_t x = keys[k] ^ keys[k + 1];
+    if (x) return (uint8_t)__clzll((long long)x);
+    return (uint8_t)(64 + __clz((int)((uint32_t)k ^ (uint32_t)(k + 1))));
 }
 
 __device__ inline void write_child(Node *__restrict__ p, int side, const float bx[6], int32_t ref)
@@ -230,12 +232,14 @@ struct Climb {
 };
 
 // The neighbour to join, within the mesh's leaf range [lo, hi]: across the
-// split with the smaller key distance.  Returns the parent index (= that
-// split position) and our side in it (0: left child, 1: right child).
-__device__ inline int32_t choose_parent(const uint64_t *__restrict__ keys, int32_t lo, int32_t hi, int32_t l,
-                                        int32_t r, int &side)
+// split with the longer common prefix (smaller key distance; the two splits
+// around a node of the radix tree never tie).  `prefix(k)` is the prefix
+// length at split k.  Returns the parent index (= that split position) and
+// our side in it (0: left child, 1: right child).
+template <typename Prefix>
+__device__ inline int32_t choose_parent(Prefix prefix, int32_t lo, int32_t hi, int32_t l, int32_t r, int &side)
 {
-    if (l == lo || (r != hi && dist_less(keys, r, l - 1))) {
+    if (l == lo || (r != hi && prefix(r) > prefix(l - 1))) {
         side = 0;
         return r;
     }
@@ -286,28 +290,47 @@ constexpr int kClimbWords = 11;
 // range crosses the block boundary) is saved for the global pass.
 __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
 {
+    constexpr int kPer = kLocal / kLocalThreads;  // leaves per thread
     __shared__ int32_t lflag[kLocal];
     __shared__ float lbox[kLocal][12];
     __shared__ int32_t lref[kLocal][2];
     __shared__ int32_t lbound[kLocal][2];
     __shared__ int32_t lh[kLocal][2];
+    __shared__ uint8_t lpre[kLocal + 1];  // prefix length at split k, k = B0-1 .. B1
     const int32_t n = (int32_t)a.n_t;
     const int32_t B0 = (int32_t)blockIdx.x * kLocal;
     const int32_t B1 = (B0 + kLocal < n ? B0 + kLocal : n) - 1;  // last leaf of this block
-    for (int t = threadIdx.x; t < kLocal; t += kLocalThreads) lflag[t] = 0;
+    // split prefixes of the block (and the split before it) into LDS; each
+    // split is also stored once for the global pass
+    for (int t = threadIdx.x; t <= kLocal; t += kLocalThreads) {
+        const int32_t k = B0 - 1 + t;
+        if (k >= 0 && k <= B1 && k < n - 1) {
+            const uint8_t p = split_prefix(a.keys, k);
+            lpre[t] = p;
+            if (t > 0) a.prefix[k] = p;
+        }
+        if (t < kLocal) lflag[t] = 0;
+    }
     __syncthreads();
+    const auto prefix = [&](int32_t k) { return (int32_t)lpre[k - B0 + 1]; };
 
-    // each thread takes kLocal / kLocalThreads leaves one after the other; a
-    // climb that arrives first at a node stops, so no thread ever waits
-    for (int tid = threadIdx.x; tid < kLocal; tid += kLocalThreads) {
-    const int32_t i = B0 + tid;
-    bool active = i < n;
-    Climb c;
-    int32_t m = 0, lo = 0, hi = 0;
-    if (active) {
-        m = mesh_of(a.off, a.M, i);
-        lo = (int32_t)a.off[m];
-        hi = (int32_t)a.off[m + 1] - 1;
+    // leaf set-up for all of this thread's leaves first (their loads overlap)
+    Climb cl[kPer];
+    int32_t lo_[kPer], hi_[kPer], m_[kPer];
+    bool act[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int32_t i = B0 + (int32_t)threadIdx.x + q * kLocalThreads;
+        act[q] = i < n;
+        m_[q] = lo_[q] = hi_[q] = 0;
+        if (!act[q]) continue;
+        Climb &c = cl[q];
+        const int32_t m = mesh_of(a.off, a.M, i);
+        const int32_t lo = (int32_t)a.off[m];
+        const int32_t hi = (int32_t)a.off[m + 1] - 1;
+        m_[q] = m;
+        lo_[q] = lo;
+        hi_[q] = hi;
         // leaf i: pack the triangle in sorted order and form its box
         int32_t id = (int32_t)a.order[i];
         if (id < lo || id > hi) {  // cannot happen after a correct sort; never read outside T
@@ -340,14 +363,23 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
         c.h = 0;
         a.climb[kClimbWords * (int64_t)i] = 0;  // no saved climb for this leaf unless set below
     }
+
+    // each thread climbs from its leaves one after the other; a climb that
+    // arrives first at a node stops, so no thread ever waits
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+    const int32_t i = B0 + (int32_t)threadIdx.x + q * kLocalThreads;
+    Climb &c = cl[q];
+    const int32_t m = m_[q], lo = lo_[q], hi = hi_[q];
     // a climb inside the block takes fewer than kLocal steps
-    for (int step = 0; active; ++step) {
+    for (int step = 0; act[q]; ++step) {
         if (c.l == lo && c.r == hi) {  // the whole mesh fits in this block
             write_entry(a, m, lo, hi, c);
             break;
         }
         int side;
-        const int32_t parent = choose_parent(a.keys, lo, hi, c.l, c.r, side);
+        // inside the block [l, r] lies in [B0, B1], so both splits are in lpre
+        const int32_t parent = choose_parent(prefix, lo, hi, c.l, c.r, side);
         if (parent < B0 || parent >= B1 || step >= kLocal) {
             // the parent's range crosses the block boundary: hand over
             int32_t *st = a.climb + kClimbWords * (int64_t)i;
@@ -423,7 +455,8 @@ __global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
             return;
         }
         int side;
-        const int32_t parent = choose_parent(a.keys, lo, hi, c.l, c.r, side);
+        const int32_t parent =
+            choose_parent([&](int32_t k) { return a.prefix[k]; }, lo, hi, c.l, c.r, side);
         Node *p = a.nodes + parent;
         // child data with system-coherent stores (they bypass the per-XCD
         // caches), completed before the counter moves; the sibling reads
@@ -452,9 +485,37 @@ __global__ __launch_bounds__(256) void k_lbvh_global(BuildArgs a)
 
 // Four-way view: record n lists the boxes and references of n's
 // grandchildren (a leaf child stands for itself), read from n's record and
-// its internal children's records.  Every record is rewritten, including
-// ones no traversal reaches (inside collapsed leaves), so references are
-// range-checked before use.
+// its internal children's records, quantised inside their union box.
+// Every record is rewritten, including ones no traversal reaches (inside
+// collapsed leaves), so references are range-checked before use.
+//
+// Grid step per axis: the smallest power of two 2^e with 255 * 2^e >= the
+// box extent (with a 2^-40 relative margin over the FP64 extent); planes are
+// placed in FP64, where the offset from the corner carries at most 2^-45
+// steps of rounding error, and rounded outward with a 2^-40-step margin, so
+// corner + q * step bounds the exact plane on the safe side.
+__device__ inline int quant_exponent(double ext)
+{
+    const double x = ext * (1.0 + 0x1p-40) / 255.0;
+    if (!(x > 0x1p-126)) return -126;
+    int k = 0;
+    const double m = frexp(x, &k);  // x = m 2^k, m in [0.5, 1)
+    const int e = (m == 0.5) ? k - 1 : k;
+    return e > 127 ? 127 : e;
+}
+
+__device__ inline uint32_t quant_down(double off, double step)
+{
+    const double q = floor(off / step - 0x1p-40);
+    return (uint32_t)fmin(fmax(q, 0.0), 255.0);
+}
+
+__device__ inline uint32_t quant_up(double off, double step)
+{
+    const double q = ceil(off / step + 0x1p-40);
+    return (uint32_t)fmin(fmax(q, 0.0), 255.0);
+}
+
 __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, int64_t n, Node4 *__restrict__ out)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,22 +533,50 @@ __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, i
                 ref[k++] = ch.ref[g];
             }
         } else {
+            // the entry record's far box (all FLT_MAX) is no child: the slot
+            // stays empty
+            bool far = true;
+            for (int q = 0; q < 6; ++q) far = far && nd.f[6 * side + q] == FLT_MAX;
+            if (far) continue;
             for (int q = 0; q < 6; ++q) box[k][q] = nd.f[6 * side + q];
             ref[k++] = c < 0 ? c : leaf_ref(0, 1);
         }
     }
+    // union box of the used slots
+    float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX}, hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+    for (int s = 0; s < k; ++s)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], box[s][a]);
+            hi[a] = fmaxf(hi[a], box[s][3 + a]);
+        }
     Node4 w;
-    for (int s = 0; s < 4; ++s) {
-        const bool used = s < k;
-        w.lx[s] = used ? box[s][0] : FLT_MAX;
-        w.ly[s] = used ? box[s][1] : FLT_MAX;
-        w.lz[s] = used ? box[s][2] : FLT_MAX;
-        w.hx[s] = used ? box[s][3] : FLT_MAX;
-        w.hy[s] = used ? box[s][4] : FLT_MAX;
-        w.hz[s] = used ? box[s][5] : FLT_MAX;
-        w.ref[s] = used ? ref[s] : leaf_ref(0, 1);
-        w.pad[s] = 0;
+    double step[3];
+    uint32_t exps = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int e = quant_exponent((double)hi[a] - (double)lo[a]);
+        step[a] = ldexp(1.0, e);
+        exps |= (uint32_t)(e + 127) << (8 * a);
     }
+    w.ox = lo[0];
+    w.oy = lo[1];
+    w.oz = lo[2];
+    w.exps = exps;
+    for (int a = 0; a < 3; ++a) {
+        uint32_t ql = 0, qh = 0;
+        for (int s = 0; s < 4; ++s) {
+            uint32_t l = 255u, h = 0u;  // unused slot: never read (kEmptySlot)
+            if (s < k) {
+                l = quant_down((double)box[s][a] - (double)lo[a], step[a]);
+                h = quant_up((double)box[s][3 + a] - (double)lo[a], step[a]);
+            }
+            ql |= l << (8 * s);
+            qh |= h << (8 * s);
+        }
+        w.lo[a] = ql;
+        w.hi[a] = qh;
+    }
+    w.pad[0] = w.pad[1] = 0;
+    for (int s = 0; s < 4; ++s) w.ref[s] = s < k ? ref[s] : kEmptySlot;
     out[j] = w;
 }
 
@@ -509,6 +598,7 @@ BuildArgs make_build_args(rsi_bvh *h, const float *V)
     a.arrive = h->arrive;
     a.heights = h->heights;
     a.climb = h->climb;
+    a.prefix = h->split_prefix;
     a.bounds = h->mesh_bounds;
     a.mesh_height = h->mesh_height;
     a.mesh_root = h->mesh_root;
@@ -530,6 +620,14 @@ unsigned init_grid(const BuildArgs &a)
 {
     const int64_t n = a.n_t > a.M ? a.n_t : a.M;
     return (unsigned)((n + 255) / 256);
+}
+
+// Copy the index flags and the tree heights into the pinned host block.
+__global__ void k_publish(const int32_t *__restrict__ scalars, const int32_t *__restrict__ mesh_height, int32_t M,
+                          int32_t *__restrict__ pub)
+{
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < M + 2; i += gridDim.x * blockDim.x)
+        pub[i] = i == 0 ? scalars[kBadIndex] : (i == 1 ? scalars[kBadGather] : mesh_height[i - 2]);
 }
 
 }  // namespace
@@ -574,6 +672,13 @@ hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
     e = run_hierarchy(a, s);
     if (e != hipSuccess) return e;
     return launch_widen(h, s);
+}
+
+hipError_t launch_publish(rsi_bvh *h, hipStream_t s)
+{
+    const int32_t n = h->M + 2;
+    hipLaunchKernelGGL(k_publish, dim3((n + 255) / 256), dim3(256), 0, s, h->scalars, h->mesh_height, h->M, h->d_pub);
+    return hipGetLastError();
 }
 
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)

@@ -288,6 +288,10 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     // stack pointer kept as an element offset into the [depth][lane] LDS
     // array (entries x stride), so a push or pop needs no multiply
     int32_t sp = 0;
+    // without a global part the stack pointer is the LDS address of the
+    // next free entry (a push or pop is one add)
+    int32_t *sptr = stk;
+    int32_t *const stk_end = stk + a.depth * stride;
     const int32_t depth_off = a.depth * stride;
     const int32_t lds_off = a.lds_depth * stride;
     // pending leaf references (leaf refs are negative; 0 = none): filled in
@@ -375,6 +379,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     L.found = false;
                     node = entry;  // < 0 for an empty mesh: the segment misses
                     sp = 0;
+                    sptr = stk;
                     steps = 0;
                     if (COUNT) ++segs;
                 } else if (exhausted) {
@@ -384,104 +389,141 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         }
         if (__ballot(item >= 0) == 0) break;
 
-        // ---- one node step for every lane that has a node and at most one
-        // pending leaf: a lane keeps walking past the first leaf it finds
-        // (speculatively, the leaf may end the walk) so that leaf tests are
-        // batched over more lanes and fewer lanes sit idle in node steps
-        const bool want = node >= 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf1 == 0);
-        const uint64_t w = __ballot(want);
-        if (COUNT && w != 0) ++w_steps;
         auto push = [&](bool cond, int32_t child) {
-            if (cond && sp < depth_off) {
-                if (!HYB || sp < lds_off) stk[sp] = child;
+            if constexpr (!HYB) {
+                if (cond && sptr < stk_end) {
+                    *sptr = child;
+                    sptr += stride;
+                }
+            } else if (cond && sp < depth_off) {
+                if (sp < lds_off) stk[sp] = child;
                 else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = child;
                 sp += stride;
             }
         };
         auto pop = [&]() -> int32_t {
-            if (sp <= 0) return -1;
-            sp -= stride;
-            if (!HYB || sp < lds_off) return stk[sp];
-            return a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid];
-        };
-        if constexpr (WIDE) {
-          if (want) {
-            const float4 *q = reinterpret_cast<const float4 *>(a.nodes4 + node);
-            const float4 LX = q[0], LY = q[1], LZ = q[2], HX = q[3], HY = q[4], HZ = q[5];
-            const int4 C = reinterpret_cast<const int4 *>(a.nodes4 + node)[6];
-            const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
-            float t0, t1, t2, t3;
-            const bool h0 = slab_hit(L.seg, LX.x, LY.x, LZ.x, HX.x, HY.x, HZ.x, lim, t0);
-            const bool h1 = slab_hit(L.seg, LX.y, LY.y, LZ.y, HX.y, HY.y, HZ.y, lim, t1);
-            const bool h2 = slab_hit(L.seg, LX.z, LY.z, LZ.z, HX.z, HY.z, HZ.z, lim, t2);
-            const bool h3 = slab_hit(L.seg, LX.w, LY.w, LZ.w, HX.w, HY.w, HZ.w, lim, t3);
-            if (COUNT) {
-                ++visits;
-                boxes += 4;
-            }
-            leaf0 = (h0 && C.x < 0) ? C.x : 0;
-            leaf1 = (h1 && C.y < 0) ? C.y : 0;
-            leaf2 = (h2 && C.z < 0) ? C.z : 0;
-            leaf3 = (h3 && C.w < 0) ? C.w : 0;
-            const bool g0 = h0 && C.x >= 0, g1 = h1 && C.y >= 0, g2 = h2 && C.z >= 0, g3 = h3 && C.w >= 0;
-            // descend into the nearest internal child that was hit; push the others
-            float bt = INFINITY;
-            int32_t near = -1;
-            if (g0) { bt = t0; near = C.x; }
-            if (g1 && t1 < bt) { bt = t1; near = C.y; }
-            if (g2 && t2 < bt) { bt = t2; near = C.z; }
-            if (g3 && t3 < bt) { bt = t3; near = C.w; }
-            push(g0 && C.x != near, C.x);
-            push(g1 && C.y != near, C.y);
-            push(g2 && C.z != near, C.z);
-            push(g3 && C.w != near, C.w);
-            node = near >= 0 ? near : pop();
-            // bound on the walk: a damaged tree can give wrong answers, never a hang
-            if (++steps >= a.max_steps) node = -1;
-          }
-        } else if (want) {
-            const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2];
-            const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
-            const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
-            float tl, tr;
-            const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
-            const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
-            if (COUNT) {
-                ++visits;
-                boxes += 2;
-            }
-            const int32_t cl = q3.x, cr = q3.y;
-            // append the hit leaf children to the pending list (at most one
-            // entry is pending here, so three slots suffice)
-            int32_t n0 = (hl && cl < 0) ? cl : 0;
-            int32_t n1 = (hr && cr < 0) ? cr : 0;
-            if (n0 == 0) {
-                n0 = n1;
-                n1 = 0;
-            }
-            if (leaf0 == 0) {
-                leaf0 = n0;
-                leaf1 = n1;
+            if constexpr (!HYB) {
+                if (sptr <= stk) return -1;
+                sptr -= stride;
+                return *sptr;
             } else {
-                leaf1 = n0;
-                leaf2 = n1;
+                if (sp <= 0) return -1;
+                sp -= stride;
+                if (sp < lds_off) return stk[sp];
+                return a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid];
             }
-            const bool gl = hl && cl >= 0;
-            const bool gr = hr && cr >= 0;
-            // descend into the nearer internal child that was hit; push the
-            // other one when both were (a full stack, possible only in a
-            // damaged tree, drops it)
-            const bool take_l = gl && (!gr || tl <= tr);
-            push(gl && gr, take_l ? cr : cl);
-            node = (gl || gr) ? (take_l ? cl : cr) : pop();
-            // bound on the walk: a damaged tree can give wrong answers, never a hang
-            if (++steps >= a.max_steps) node = -1;
-        }
+        };
+        // ---- node steps for every lane that has a node and at most one
+        // pending leaf: a lane keeps walking past the first leaf it finds
+        // (speculatively, the leaf may end the walk) so that leaf tests are
+        // batched over more lanes and fewer lanes sit idle in node steps.
+        // Steps repeat without the refill and leaf-phase checks while at
+        // least `defer` lanes step; pending leaves are tested after the first
+        // step made by fewer lanes.
+        auto can_step = [&]() {
+            return node >= 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf1 == 0);
+        };
+        uint64_t w;
+        do {
+            const bool want = can_step();
+            w = __ballot(want);
+            if (w == 0) break;
+            if (COUNT) ++w_steps;
+            if constexpr (WIDE) {
+              if (want) {
+                const uint4 *q = reinterpret_cast<const uint4 *>(a.nodes4 + node);
+                const uint4 P = q[0], Q = q[1], R = q[2];
+                const int4 C = reinterpret_cast<const int4 *>(a.nodes4 + node)[3];
+                const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
+                // grid steps, the corner's offset from the segment origin and
+                // the margin that makes the plane evaluation conservative
+                const float sx = __uint_as_float((P.w & 0xFFu) << 23);
+                const float sy = __uint_as_float((P.w & 0xFF00u) << 15);
+                const float sz = __uint_as_float((P.w & 0xFF0000u) << 7);
+                const float Dx = __uint_as_float(P.x) - L.seg.ox;
+                const float Dy = __uint_as_float(P.y) - L.seg.oy;
+                const float Dz = __uint_as_float(P.z) - L.seg.oz;
+                const float ex = fminf(fmaf(255.0f, sx, fabsf(Dx)), FLT_MAX) * 0x1p-19f;
+                const float ey = fminf(fmaf(255.0f, sy, fabsf(Dy)), FLT_MAX) * 0x1p-19f;
+                const float ez = fminf(fmaf(255.0f, sz, fabsf(Dz)), FLT_MAX) * 0x1p-19f;
+                const float Lx = Dx - ex, Ly = Dy - ey, Lz = Dz - ez;
+                const float Hx = Dx + ex, Hy = Dy + ey, Hz = Dz + ez;
+                // child c: lower planes in byte c of Q.x, Q.y, Q.z, upper
+                // planes in byte c of Q.w, R.x, R.y
+                auto qb = [](uint32_t v, int c) { return (float)((v >> (8 * c)) & 0xFFu); };
+                auto test = [&](int c, float &t) {
+                    return qslab_hit(L.seg, Lx, Ly, Lz, Hx, Hy, Hz, sx, sy, sz, qb(Q.x, c), qb(Q.y, c), qb(Q.z, c),
+                                     qb(Q.w, c), qb(R.x, c), qb(R.y, c), lim, t);
+                };
+                float t0, t1, t2, t3;
+                const bool h0 = test(0, t0) && C.x != kEmptySlot;
+                const bool h1 = test(1, t1) && C.y != kEmptySlot;
+                const bool h2 = test(2, t2) && C.z != kEmptySlot;
+                const bool h3 = test(3, t3) && C.w != kEmptySlot;
+                if (COUNT) {
+                    ++visits;
+                    boxes += (C.x != kEmptySlot) + (C.y != kEmptySlot) + (C.z != kEmptySlot) + (C.w != kEmptySlot);
+                }
+                leaf0 = (h0 && C.x < 0) ? C.x : 0;
+                leaf1 = (h1 && C.y < 0) ? C.y : 0;
+                leaf2 = (h2 && C.z < 0) ? C.z : 0;
+                leaf3 = (h3 && C.w < 0) ? C.w : 0;
+                const bool g0 = h0 && C.x >= 0, g1 = h1 && C.y >= 0, g2 = h2 && C.z >= 0, g3 = h3 && C.w >= 0;
+                // descend into the nearest internal child that was hit; push the others
+                float bt = INFINITY;
+                int32_t near = -1;
+                if (g0) { bt = t0; near = C.x; }
+                if (g1 && t1 < bt) { bt = t1; near = C.y; }
+                if (g2 && t2 < bt) { bt = t2; near = C.z; }
+                if (g3 && t3 < bt) { bt = t3; near = C.w; }
+                push(g0 && C.x != near, C.x);
+                push(g1 && C.y != near, C.y);
+                push(g2 && C.z != near, C.z);
+                push(g3 && C.w != near, C.w);
+                node = near >= 0 ? near : pop();
+                // bound on the walk: a damaged tree can give wrong answers, never a hang
+                if (++steps >= a.max_steps) node = -1;
+              }
+            } else if (want) {
+                const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
+                const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+                const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
+                const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
+                float tl, tr;
+                const bool hl = slab_hit(L.seg, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, lim, tl);
+                const bool hr = slab_hit(L.seg, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, lim, tr);
+                if (COUNT) {
+                    ++visits;
+                    boxes += 2;
+                }
+                const int32_t cl = q3.x, cr = q3.y;
+                // add the hit leaf children to the pending list, kept in
+                // ascending order: references are negative and 0 marks a free
+                // slot, so the pending entries come first (at most one is
+                // pending here, so three slots suffice); the order in which a
+                // lane tests its leaves changes no result
+                const int32_t n0 = (hl && cl < 0) ? cl : 0;
+                const int32_t n1 = (hr && cr < 0) ? cr : 0;
+                const int32_t lo01 = min(n0, n1), hi01 = max(n0, n1);
+                leaf2 = max(leaf0, hi01);
+                leaf1 = max(min(leaf0, hi01), lo01);
+                leaf0 = min(leaf0, lo01);
+                const bool gl = hl && cl >= 0;
+                const bool gr = hr && cr >= 0;
+                // descend into the nearer internal child that was hit; push the
+                // other one when both were (a full stack, possible only in a
+                // damaged tree, drops it)
+                const bool take_l = gl && (!gr || tl <= tr);
+                push(gl && gr, take_l ? cr : cl);
+                node = (gl || gr) ? (take_l ? cl : cr) : pop();
+                // bound on the walk: a damaged tree can give wrong answers, never a hang
+                if (++steps >= a.max_steps) node = -1;
+            }
+        } while ((int)__popcll(w) >= a.defer);
 
         // ---- test pending leaves once few lanes can still step
         const uint64_t pend = __ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) != 0 : leaf0 != 0);
-        if (pend != 0 && (int)__popcll(w) < a.defer) {
+        if (pend != 0) {
             if (COUNT) ++w_leaf;
             if constexpr (WIDE) {
                 // one pending leaf per lane and round, the first occupied slot
@@ -674,13 +716,14 @@ int full_depth(const rsi_bvh *h)
 }
 
 // LDS part of the stack: the whole stack unless a smaller cap is set; the
-// four-way walk keeps 16 entries in LDS by default (its worst-case depth is
-// about 1.5x the binary one while typical walks stay far below it).
+// four-way walk keeps 20 entries in LDS by default (its worst-case depth is
+// about 1.5x the binary one while typical walks stay far below it; 20
+// entries of 128 lanes leave room for eight waves per SIMD).
 int lds_part(const rsi_bvh *h)
 {
     const int depth = full_depth(h);
     int cap = h->stack_cap;
-    if (cap <= 0 && h->width_built == 4) cap = 16;
+    if (cap <= 0 && h->width_built == 4) cap = 20;
     return (cap > 0 && cap < depth) ? cap : depth;
 }
 

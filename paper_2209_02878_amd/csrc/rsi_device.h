@@ -30,20 +30,34 @@ struct alignas(64) Node {
 };
 static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 
-// Node4 (128 bytes, one L2 line): the four-way view of binary node n, whose
-// children are n's grandchildren (a child that is a leaf stands for itself),
-// stored coordinate-major so each float4 holds one coordinate of the four
-// child boxes.  Record n of the Node4 array belongs to binary node n, so a
-// child reference (an internal grandchild's index, or a leaf) is valid in
-// both arrays.  Unused slots have the box (FLT_MAX, ..., FLT_MAX), which no
-// segment touches.
-struct alignas(128) Node4 {
-    float lx[4], ly[4], lz[4];
-    float hx[4], hy[4], hz[4];
+// Node4 (64 bytes, four 16-byte loads like a binary step): the four-way
+// view of binary node n, whose children are n's grandchildren (a child that
+// is a leaf stands for itself), with the child boxes quantised to 8 bits per
+// plane on a grid anchored at the lower corner of n's box.  Record n of the
+// Node4 array belongs to binary node n, so a child reference (an internal
+// grandchild's index, or a leaf) is valid in both arrays.
+//
+//   ox, oy, oz   lower corner of n's box (exact)
+//   exps         bytes 0..2: biased exponents b of the x, y, z grid steps,
+//                step = 2^(b - 127), so 255 steps span n's box
+//   lo[a]        byte c: child c's lower plane on axis a in grid steps,
+//                rounded down;  hi[a] likewise for the upper plane, rounded
+//                up -- every quantised box contains its exact child box
+//   ref[c]       child reference, kEmptySlot for an unused slot
+//
+// Halving the record (the exact four-way layout needs 128 bytes) halves the
+// vector-cache lookups per visit, which bound the binary walk.  Any finite
+// box is representable (steps 2^-126 .. 2^122).
+constexpr int32_t kEmptySlot = 0x7FFFFFFF;
+struct alignas(64) Node4 {
+    float ox, oy, oz;
+    uint32_t exps;
+    uint32_t lo[3];
+    uint32_t hi[3];
+    uint32_t pad[2];
     int32_t ref[4];
-    int32_t pad[4];
 };
-static_assert(sizeof(Node4) == 128, "Node4 must be 128 bytes");
+static_assert(sizeof(Node4) == 64, "Node4 must be 64 bytes");
 
 // Tri: the three FP32 vertices of a triangle in Morton (sorted) order plus
 // its original id, 48 bytes = three 16-byte loads.  Storing the vertices
@@ -119,6 +133,32 @@ __device__ inline bool slab_hit(const Seg &s, float lx, float ly, float lz,
     float t0z = (lz - s.oz) * s.iz, t1z = (hz - s.oz) * s.iz;
     float n = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     float f = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tnear = n;
+    return n <= f * (1.0f + 0x1p-20f);
+}
+
+// Conservative segment / quantised-box test for the four-way view.  The
+// caller forms, per node and axis, D = corner - o and the margin
+// eps = min(255 step + |D|, FLT_MAX) 2^-19, and passes Dlo = D - eps and
+// Dhi = D + eps.  A plane's offset from the segment origin is then
+// fma(q, step, Dlo) (lower planes) or fma(q, step, Dhi) (upper planes):
+// q * step is exact, and the roundings of D, of D -+ eps and of the fma
+// together stay below 3 * 2^-24 (|D| + 255 step), under a fifth of eps, so
+// the lower offset never exceeds and the upper never falls below the exact
+// quantised plane: the tested box contains the quantised box, which
+// contains the child box.  (The FLT_MAX cap only binds where the offsets
+// approach the FP32 range; eps stays finite, so no inf - inf arises.)
+// Each offset times (1/d) then carries the relative error that slab_hit's
+// slack covers.  qlx..qhz are the quantised planes as floats (0..255).
+__device__ inline bool qslab_hit(const Seg &s, float Lx, float Ly, float Lz, float Hx, float Hy, float Hz,
+                                 float sx, float sy, float sz, float qlx, float qly, float qlz, float qhx,
+                                 float qhy, float qhz, float tmax, float &tnear)
+{
+    const float t0x = fmaf(qlx, sx, Lx) * s.ix, t1x = fmaf(qhx, sx, Hx) * s.ix;
+    const float t0y = fmaf(qly, sy, Ly) * s.iy, t1y = fmaf(qhy, sy, Hy) * s.iy;
+    const float t0z = fmaf(qlz, sz, Lz) * s.iz, t1z = fmaf(qhz, sz, Hz) * s.iz;
+    const float n = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    const float f = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     tnear = n;
     return n <= f * (1.0f + 0x1p-20f);
 }

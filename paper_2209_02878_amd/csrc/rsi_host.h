@@ -69,7 +69,7 @@ struct rsi_bvh {
     int32_t height = 0;            // largest tree height over the meshes
     bool counting = false;
     std::vector<int64_t> h_tri_off, h_vert_off;  // host copies of the offsets
-    std::vector<int32_t> h_height, h_root;
+    std::vector<int32_t> h_height;
 
     // mesh tables (device)
     int64_t *tri_off = nullptr;    // [M+1]
@@ -93,6 +93,7 @@ struct rsi_bvh {
     int32_t *arrive = nullptr;     // arrival counters [n_t]
     int32_t *heights = nullptr;    // child heights [2*n_t]
     int32_t *climb = nullptr;      // climbs handed from the local to the global build pass [11*n_t]
+    uint8_t *split_prefix = nullptr;  // common-prefix length at each sorted split [n_t]
     int32_t *scalars = nullptr;    // rsi::Scalar
     rsi::Counters *counters = nullptr;
     rsi::SortScratch sort;
@@ -118,7 +119,7 @@ struct rsi_bvh {
 
     // four-way view of the tree (branching 4): requested width, and the width
     // the current tree was laid out for
-    int32_t width = 2;
+    int32_t width = 4;
     int32_t width_built = 2;
     rsi::Node4 *nodes4 = nullptr;
 
@@ -145,6 +146,10 @@ struct rsi_bvh {
 
     // pinned host mirror of `scalars`
     int32_t *h_scalars = nullptr;
+    // pinned host block that k_publish fills after a build: the two index
+    // flags, then the M tree heights; d_pub is its device-side address
+    int32_t *h_pub = nullptr;
+    int32_t *d_pub = nullptr;
 };
 
 namespace rsi {
@@ -156,6 +161,7 @@ void set_error(const std::string &msg);
 hipError_t launch_gather(rsi_bvh *h, hipStream_t s);
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s);
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s);
+hipError_t launch_publish(rsi_bvh *h, hipStream_t s);
 
 // sort.hip: stable LSD radix sort of 63-bit keys with 32-bit values, in
 // place; with mesh_off (M > 1) the mesh of each value is the most

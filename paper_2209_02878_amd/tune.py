@@ -24,7 +24,7 @@ DEFAULT_CACHE = os.environ.get("RSI_TUNE_CACHE", os.path.join(os.path.expanduser
 STAGES = [
     [{"branching": w, "block_size": b} for w in (2, 4) for b in (64, 128, 256)],
     # stack_depth 255 keeps the whole stack in LDS (it is capped at the walk's worst-case depth)
-    [{"stack_depth": s} for s in (255, 8, 12, 16, 24)],
+    [{"stack_depth": s} for s in (255, 8, 12, 16, 20, 24)],
     [{"defer_lanes": d, "refill_lanes": r} for d in (16, 32, 48) for r in (16, 32, 48)],
     [{"leaf_size": leaf} for leaf in (1, 2, 4)],
 ]

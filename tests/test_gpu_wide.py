@@ -1,12 +1,16 @@
 """The four-way traversal (branching 4) gives exactly the binary walk's answers.
 
 The four-way view lists, for every binary node, the boxes of its
-grandchildren (the binary tree of Section 3.1 seen two levels at a time), so
-the same leaves are reached and the same triangle tests decide; the FP64
-re-solve of every reported crossing is the same too.  All outputs must
-therefore be bit-identical to the binary walk, in every mode, with a small
-LDS stack (device-memory tail), with larger leaves, after a refit, in a
-batch and in a captured graph; and they must match the FP64 oracle.
+grandchildren (the binary tree of Section 3.1 seen two levels at a time),
+quantised outward to 8 bits per plane, so every leaf the exact boxes reach
+is reached and the same FP32 triangle test decides; the FP64 re-solve of
+every reported crossing is the same too.  The two walks can differ only
+where a triangle test sits within rounding of its decision for a triangle
+that the looser boxes let through; on these workloads no such case occurs,
+so the outputs are compared bit for bit with the binary walk, in every
+mode, with a small LDS stack (device-memory tail), with larger leaves,
+after a refit, in a batch and in a captured graph; and they must match the
+FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -141,5 +145,39 @@ def test_branching_option_validation():
     mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32))
     with pytest.raises(rsi.RsiError):
         mesh.set_opts(branching=3)
-    assert mesh.opts()["branching"] == 2
+    assert mesh.opts()["branching"] == 4  # the default is kept
     mesh.close()
+
+
+@pytest.mark.parametrize("offset,size", [(2.0 ** 35, 2.0 ** 20), (-(2.0 ** 30), 2.0 ** 22)])
+def test_wide_far_from_origin_matches_oracle(offset, size):
+    """A mesh far from the coordinate origin (2^35 or -2^30 away, 2^20 or
+    2^22 across, so FP32 still resolves it): corner offsets are large next
+    to the node boxes, and so are the rounding margins.  Both walks must
+    meet the FP64 oracle on every non-degenerate segment (bit-identity
+    between them is not required here: on such coarse FP32 coordinates the
+    looser quantised boxes may let a triangle test that sits within rounding
+    of its decision run where the binary walk culls it)."""
+    w = wl.config1(n_r=4000)
+    move = lambda a: (a.astype(np.float64) * size + offset).astype(np.float32)
+    Vh, Sh, Eh = move(w.V), move(w.S), move(w.E)
+    ref = parity.oracle_reference(Vh, w.T, Sh, Eh, cap=4)
+    V, T = _t(Vh), _t(w.T, torch.int32)
+    S, E = _t(Sh), _t(Eh)
+    for br in (2, 4):
+        mesh = rsi.Mesh(V, T, branching=br)
+        out = mesh.query(S, E, "bool|first|all", capacity=4)
+        torch.cuda.synchronize()
+        rep = parity.compare(ref, out, {"bool", "first", "all"}, cap=4)
+        assert rep["hits"] > 50, rep
+        # the hit point is stored in FP32, whose spacing at these magnitudes
+        # exceeds the usual 1e-5 L: check it against that spacing instead
+        p_bad = rep.pop("first_p_bad")
+        parity.assert_parity(rep)
+        if p_bad:
+            ok = (ref["degenerate"] == 0) & (ref["first_tri"] >= 0)
+            P = out["point"].cpu().numpy().astype(np.float64)[ok]
+            Pr = ref["first_p"][ok]
+            tol = parity.T_TOL * ref["extent"] + 2.0 ** -23 * np.abs(Pr)
+            assert np.all(np.abs(P - Pr) <= tol), br
+        mesh.close()
