@@ -504,15 +504,16 @@ __device__ inline int quant_exponent(double ext)
     return e > 127 ? 127 : e;
 }
 
-__device__ inline uint32_t quant_down(double off, double step)
+// `inv_step` is 1 / step, a power of two, so the scaling is exact
+__device__ inline uint32_t quant_down(double off, double inv_step)
 {
-    const double q = floor(off / step - 0x1p-40);
+    const double q = floor(off * inv_step - 0x1p-40);
     return (uint32_t)fmin(fmax(q, 0.0), 255.0);
 }
 
-__device__ inline uint32_t quant_up(double off, double step)
+__device__ inline uint32_t quant_up(double off, double inv_step)
 {
-    const double q = ceil(off / step + 0x1p-40);
+    const double q = ceil(off * inv_step + 0x1p-40);
     return (uint32_t)fmin(fmax(q, 0.0), 255.0);
 }
 
@@ -550,11 +551,11 @@ __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, i
             hi[a] = fmaxf(hi[a], box[s][3 + a]);
         }
     Node4 w;
-    double step[3];
+    double inv_step[3];
     uint32_t exps = 0;
     for (int a = 0; a < 3; ++a) {
         const int e = quant_exponent((double)hi[a] - (double)lo[a]);
-        step[a] = ldexp(1.0, e);
+        inv_step[a] = ldexp(1.0, -e);
         exps |= (uint32_t)(e + 127) << (8 * a);
     }
     w.ox = lo[0];
@@ -566,8 +567,8 @@ __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, i
         for (int s = 0; s < 4; ++s) {
             uint32_t l = 255u, h = 0u;  // unused slot: never read (kEmptySlot)
             if (s < k) {
-                l = quant_down((double)box[s][a] - (double)lo[a], step[a]);
-                h = quant_up((double)box[s][3 + a] - (double)lo[a], step[a]);
+                l = quant_down((double)box[s][a] - (double)lo[a], inv_step[a]);
+                h = quant_up((double)box[s][3 + a] - (double)lo[a], inv_step[a]);
             }
             ql |= l << (8 * s);
             qh |= h << (8 * s);

@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const uint4 *q = reinterpret_cast<const uint4 *>(a.nodes4 + node);
                 const uint4 P = q[0], Q = q[1], R = q[2];
                 const int4 C = reinterpret_cast<const int4 *>(a.nodes4 + node)[3];
-                const float lim = (MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f;
+                const float lim = ((MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f) * (1.0f + 0x1p-20f);
                 // grid steps, the corner's offset from the segment origin and
                 // the margin that makes the plane evaluation conservative
                 const float sx = __uint_as_float((P.w & 0xFFu) << 23);
@@ -443,17 +443,24 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const float Dx = __uint_as_float(P.x) - L.seg.ox;
                 const float Dy = __uint_as_float(P.y) - L.seg.oy;
                 const float Dz = __uint_as_float(P.z) - L.seg.oz;
-                const float ex = fminf(fmaf(255.0f, sx, fabsf(Dx)), FLT_MAX) * 0x1p-19f;
-                const float ey = fminf(fmaf(255.0f, sy, fabsf(Dy)), FLT_MAX) * 0x1p-19f;
-                const float ez = fminf(fmaf(255.0f, sz, fabsf(Dz)), FLT_MAX) * 0x1p-19f;
-                const float Lx = Dx - ex, Ly = Dy - ey, Lz = Dz - ez;
-                const float Hx = Dx + ex, Hy = Dy + ey, Hz = Dz + ez;
+                // per axis the plane met first: the lower one for a
+                // non-negative direction component; the margin moves it
+                // toward the segment origin and the other plane away
+                const bool px = L.seg.ix >= 0.0f, py = L.seg.iy >= 0.0f, pz = L.seg.iz >= 0.0f;
+                const float mx = fminf(fmaf(255.0f, sx, fabsf(Dx)), FLT_MAX) * (px ? 0x1p-19f : -0x1p-19f);
+                const float my = fminf(fmaf(255.0f, sy, fabsf(Dy)), FLT_MAX) * (py ? 0x1p-19f : -0x1p-19f);
+                const float mz = fminf(fmaf(255.0f, sz, fabsf(Dz)), FLT_MAX) * (pz ? 0x1p-19f : -0x1p-19f);
+                const float Nx = Dx - mx, Ny = Dy - my, Nz = Dz - mz;
+                const float Fx = Dx + mx, Fy = Dy + my, Fz = Dz + mz;
                 // child c: lower planes in byte c of Q.x, Q.y, Q.z, upper
                 // planes in byte c of Q.w, R.x, R.y
+                const uint32_t nqx = px ? Q.x : Q.w, fqx = px ? Q.w : Q.x;
+                const uint32_t nqy = py ? Q.y : R.x, fqy = py ? R.x : Q.y;
+                const uint32_t nqz = pz ? Q.z : R.y, fqz = pz ? R.y : Q.z;
                 auto qb = [](uint32_t v, int c) { return (float)((v >> (8 * c)) & 0xFFu); };
                 auto test = [&](int c, float &t) {
-                    return qslab_hit(L.seg, Lx, Ly, Lz, Hx, Hy, Hz, sx, sy, sz, qb(Q.x, c), qb(Q.y, c), qb(Q.z, c),
-                                     qb(Q.w, c), qb(R.x, c), qb(R.y, c), lim, t);
+                    return qslab_hit(L.seg, Nx, Ny, Nz, Fx, Fy, Fz, sx, sy, sz, qb(nqx, c), qb(nqy, c), qb(nqz, c),
+                                     qb(fqx, c), qb(fqy, c), qb(fqz, c), lim, t);
                 };
                 float t0, t1, t2, t3;
                 const bool h0 = test(0, t0) && C.x != kEmptySlot;

@@ -90,6 +90,7 @@ struct Seg {
     float ox, oy, oz;
     float dx, dy, dz;
     float ix, iy, iz;
+    float jx, jy, jz;  // (1/d) (1 + 2^-20): the far planes' reciprocals in qslab_hit
 };
 
 __device__ inline float guarded_rcp(float d)
@@ -116,6 +117,9 @@ __device__ inline Seg make_seg(float sx, float sy, float sz, float ex, float ey,
     r.ix = guarded_rcp(r.dx);
     r.iy = guarded_rcp(r.dy);
     r.iz = guarded_rcp(r.dz);
+    r.jx = r.ix * (1.0f + 0x1p-20f);
+    r.jy = r.iy * (1.0f + 0x1p-20f);
+    r.jz = r.iz * (1.0f + 0x1p-20f);
     return r;
 }
 
@@ -139,28 +143,38 @@ __device__ inline bool slab_hit(const Seg &s, float lx, float ly, float lz,
 
 // Conservative segment / quantised-box test for the four-way view.  The
 // caller forms, per node and axis, D = corner - o and the margin
-// eps = min(255 step + |D|, FLT_MAX) 2^-19, and passes Dlo = D - eps and
-// Dhi = D + eps.  A plane's offset from the segment origin is then
-// fma(q, step, Dlo) (lower planes) or fma(q, step, Dhi) (upper planes):
-// q * step is exact, and the roundings of D, of D -+ eps and of the fma
-// together stay below 3 * 2^-24 (|D| + 255 step), under a fifth of eps, so
-// the lower offset never exceeds and the upper never falls below the exact
+// eps = min(255 step + |D|, FLT_MAX) 2^-19, and passes the bases of the
+// plane the segment meets first on that axis (the lower plane when the
+// direction component is non-negative -- 1/d keeps the sign of d, zero
+// included) and of the other one: N = D - eps, F = D + eps for a
+// non-negative component, N = D + eps, F = D - eps otherwise, with the
+// matching quantised planes qn, qf.  A plane's offset from the segment
+// origin is then fma(q, step, base): q * step is exact, and the roundings
+// of D, of D -+ eps and of the fma together stay below
+// 3 * 2^-24 (|D| + 255 step), under a fifth of eps, so a lower plane's
+// offset never exceeds and an upper plane's never falls below the exact
 // quantised plane: the tested box contains the quantised box, which
 // contains the child box.  (The FLT_MAX cap only binds where the offsets
 // approach the FP32 range; eps stays finite, so no inf - inf arises.)
-// Each offset times (1/d) then carries the relative error that slab_hit's
-// slack covers.  qlx..qhz are the quantised planes as floats (0..255).
-__device__ inline bool qslab_hit(const Seg &s, float Lx, float Ly, float Lz, float Hx, float Hy, float Hz,
-                                 float sx, float sy, float sz, float qlx, float qly, float qlz, float qhx,
-                                 float qhy, float qhz, float tmax, float &tnear)
+// Times 1/d, the first plane's offset gives the smaller parameter (the
+// offsets are ordered and 1/d has the direction's sign), so no per-axis
+// min/max is needed.  Each product carries the relative error that
+// slab_hit's slack covers; here the slack is folded into the far planes'
+// reciprocals (s.jx..s.jz) and into `tmax_s` = tmax (1 + 2^-20), which
+// scales every non-negative far parameter up by it (a negative one means
+// the box lies before t = 0, and its sign is exact).  qnx..qfz are the
+// quantised planes as floats.
+__device__ inline bool qslab_hit(const Seg &s, float Nx, float Ny, float Nz, float Fx, float Fy, float Fz,
+                                 float sx, float sy, float sz, float qnx, float qny, float qnz, float qfx,
+                                 float qfy, float qfz, float tmax_s, float &tnear)
 {
-    const float t0x = fmaf(qlx, sx, Lx) * s.ix, t1x = fmaf(qhx, sx, Hx) * s.ix;
-    const float t0y = fmaf(qly, sy, Ly) * s.iy, t1y = fmaf(qhy, sy, Hy) * s.iy;
-    const float t0z = fmaf(qlz, sz, Lz) * s.iz, t1z = fmaf(qhz, sz, Hz) * s.iz;
-    const float n = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-    const float f = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    const float nx = fmaf(qnx, sx, Nx) * s.ix, fx = fmaf(qfx, sx, Fx) * s.jx;
+    const float ny = fmaf(qny, sy, Ny) * s.iy, fy = fmaf(qfy, sy, Fy) * s.jy;
+    const float nz = fmaf(qnz, sz, Nz) * s.iz, fz = fmaf(qfz, sz, Fz) * s.jz;
+    const float n = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+    const float f = fminf(fminf(fx, fy), fminf(fz, tmax_s));
     tnear = n;
-    return n <= f * (1.0f + 0x1p-20f);
+    return n <= f;
 }
 
 // Moller-Trumbore segment / triangle test in FP32, division-free decision
