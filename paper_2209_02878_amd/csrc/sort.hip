@@ -293,6 +293,191 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     }
 }
 
+// Stable rank of one tile held in registers (item r of thread x is tile
+// element r * kThreads + x; `valid` marks live elements): on return pos[r]
+// is the item's position in the tile ordered by digit (ties in tile order),
+// run[d] the tile's count of digit d and start[d] its exclusive scan.
+// `wcnt` is LDS scratch of IPT * kWaves * kRadix words.
+template <int IPT>
+__device__ inline void rank_tile(const uint32_t (&dig)[IPT], const bool (&valid)[IPT], uint32_t (&pos)[IPT],
+                                 uint32_t *wcnt, uint32_t *run, uint32_t *start)
+{
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcnt[(r * kWaves + w) * kRadix + tid] = 0;
+    __syncthreads();
+    // per round: the lanes of this wave holding the same digit (8 ballots);
+    // the lowest of them records the group size
+    uint32_t below[IPT];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t d = dig[r];
+        uint64_t peers = __ballot(valid[r]);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        below[r] = (uint32_t)__popcll(peers & lt);
+        if (valid[r] && below[r] == 0) wcnt[(r * kWaves + wave) * kRadix + d] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // digit tid: exclusive prefix over (round, wave) in tile order
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t c = wcnt[(r * kWaves + w) * kRadix + tid];
+                wcnt[(r * kWaves + w) * kRadix + tid] = acc;
+                acc += c;
+            }
+        run[tid] = acc;
+    }
+    __syncthreads();
+    scan256(run, start);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) pos[r] = start[dig[r]] + wcnt[(r * kWaves + wave) * kRadix + dig[r]] + below[r];
+}
+
+// A bucket of at most IPT * kThreads elements: all low passes in LDS.
+template <int IPT>
+__device__ inline void sort_bucket_lds(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t b0,
+                                       uint32_t bn, int nlow, uint32_t *wcnt, uint32_t *run, uint32_t *start,
+                                       uint64_t *skey, uint32_t *sval)
+{
+    const int tid = threadIdx.x;
+    uint64_t key[IPT];
+    uint32_t val[IPT], dig[IPT], pos[IPT];
+    bool valid[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t i = (uint32_t)(r * kThreads + tid);
+        valid[r] = i < bn;
+        key[r] = valid[r] ? kin[b0 + i] : 0ull;
+        val[r] = valid[r] ? vin[b0 + i] : 0u;
+    }
+    for (int p = 0; p < nlow; ++p) {
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) dig[r] = valid[r] ? (uint32_t)(key[r] >> (8 * p)) & (kRadix - 1) : 0u;
+        rank_tile<IPT>(dig, valid, pos, wcnt, run, start);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (valid[r]) {
+                skey[pos[r]] = key[r];
+                sval[pos[r]] = val[r];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (valid[r]) {
+                key[r] = skey[r * kThreads + tid];
+                val[r] = sval[r * kThreads + tid];
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (valid[r]) {
+            kout[b0 + r * kThreads + tid] = key[r];
+            vout[b0 + r * kThreads + tid] = val[r];
+        }
+}
+
+// A larger bucket: the same stable low passes over its range in device
+// memory, one histogram sweep and one tile-by-tile scatter sweep per pass,
+// alternating between the range in kin and in kout (the result ends in kout).
+__device__ inline void sort_bucket_global(uint64_t *__restrict__ kin, uint32_t *__restrict__ vin,
+                                          uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t b0,
+                                          uint32_t bn, int nlow, uint32_t *wcnt, uint32_t *run, uint32_t *start,
+                                          uint32_t *gcount, uint32_t *gbase)
+{
+    const int tid = threadIdx.x;
+    uint64_t *ks = kin, *kd = kout;
+    uint32_t *vs = vin, *vd = vout;
+    for (int p = 0; p < nlow; ++p) {
+        const int shift = 8 * p;
+        gcount[tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < bn; i += kThreads)
+            atomicAdd(&gcount[(uint32_t)(ks[b0 + i] >> shift) & (kRadix - 1)], 1u);
+        __syncthreads();
+        scan256(gcount, gbase);
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < bn; c0 += kTile) {
+            uint64_t key[kItems];
+            uint32_t val[kItems], dig[kItems], pos[kItems];
+            bool valid[kItems];
+#pragma unroll
+            for (int r = 0; r < kItems; ++r) {
+                const uint32_t i = c0 + (uint32_t)(r * kThreads + tid);
+                valid[r] = i < bn;
+                key[r] = valid[r] ? ks[b0 + i] : 0ull;
+                val[r] = valid[r] ? vs[b0 + i] : 0u;
+                dig[r] = valid[r] ? (uint32_t)(key[r] >> shift) & (kRadix - 1) : 0u;
+            }
+            rank_tile<kItems>(dig, valid, pos, wcnt, run, start);
+#pragma unroll
+            for (int r = 0; r < kItems; ++r)
+                if (valid[r]) {
+                    const uint32_t dst = b0 + gbase[dig[r]] + (pos[r] - start[dig[r]]);
+                    kd[dst] = key[r];
+                    vd[dst] = val[r];
+                }
+            __syncthreads();
+            gbase[tid] += run[tid];
+            __syncthreads();
+        }
+        uint64_t *tk = ks; ks = kd; kd = tk;
+        uint32_t *tv = vs; vs = vd; vd = tv;
+    }
+    if (ks != kout) {  // an even number of passes left the result in kin's range
+        for (uint32_t i = tid; i < bn; i += kThreads) {
+            kout[b0 + i] = ks[b0 + i];
+            vout[b0 + i] = vs[b0 + i];
+        }
+    }
+}
+
+// One workgroup per top-digit bucket of a small sort.  kin/vin hold the
+// elements grouped by their top digit (stable), `hist` the per-tile counts
+// of that digit; each bucket is sorted by its `nlow` lower digits and written
+// to the same offsets in kout/vout.
+__global__ __launch_bounds__(kThreads) void k_bucket_sort(uint64_t *__restrict__ kin, uint32_t *__restrict__ vin,
+                                                          uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                          const uint32_t *__restrict__ hist, int ntiles, int nlow)
+{
+    __shared__ uint32_t wcnt[kItems * kWaves * kRadix];
+    __shared__ uint32_t run[kRadix], start[kRadix], gcount[kRadix], gbase[kRadix];
+    __shared__ uint64_t skey[kTile];
+    __shared__ uint32_t sval[kTile];
+    const int tid = threadIdx.x;
+    // bucket sizes and offsets: digit tid's total over the tiles, scanned
+    uint32_t tot = 0;
+    for (int b = 0; b < ntiles; ++b) tot += hist[(int64_t)tid * ntiles + b];
+    gcount[tid] = tot;
+    __syncthreads();
+    scan256(gcount, gbase);
+    __syncthreads();
+    const uint32_t b0 = gbase[blockIdx.x], bn = gcount[blockIdx.x];
+    __syncthreads();
+    if (bn == 0) return;
+    if (bn <= (uint32_t)kThreads)
+        sort_bucket_lds<1>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
+    else if (bn <= (uint32_t)kTile)
+        sort_bucket_lds<kItems>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
+    else
+        sort_bucket_global(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, gcount, gbase);
+}
+
 __global__ void k_copy_pairs(const uint64_t *__restrict__ ks, const uint32_t *__restrict__ vs,
                              uint64_t *__restrict__ kd, uint32_t *__restrict__ vd, int64_t n)
 {
@@ -381,6 +566,21 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     uint64_t *ka = keys, *kb = sc.keys_alt;
     uint32_t *va = vals, *vb = sc.vals_alt;
     const int64_t hsz = (int64_t)ntiles * kRadix;
+    if (ntiles <= kFusedTiles && np == (key_bits + 7) / 8 && key_bits > 8) {
+        // small sort of key digits only: one stable pass on the top 8 bits
+        // groups the elements into 256 buckets, then one workgroup per bucket
+        // sorts it by the lower bits (in LDS up to kTile elements), so three
+        // launches replace one per digit
+        const int top = key_bits - 8;
+        const Digit dtop{nullptr, 0, top};
+        hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist, ntiles,
+                           nullptr);
+        hipLaunchKernelGGL((k_scatter<true, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dtop,
+                           sc.hist, ntiles, dtop, nullptr, nullptr);
+        hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist, ntiles,
+                           (top + 7) / 8);
+        return hipGetLastError();
+    }
     if (ntiles <= kFusedTiles) {
         // (smaller tiles, hence more workgroups, measured slower: each
         // workgroup then scans more histograms and the next-pass counters

@@ -125,3 +125,24 @@ def test_sort_large_mesh():
     assert np.array_equal(tree["order"], np.argsort(_morton_reference(V, T), kind="stable"))
     _validate(tree, V, T, 1)
     m.close()
+
+
+@pytest.mark.parametrize("n_cluster", [300, 2500, 9000])
+def test_sort_clustered_buckets(n_cluster):
+    """Most triangles in one corner cell of the mesh box and a few far away:
+    the small-sort path groups the keys by their top 8 bits and then sorts
+    each group, in LDS up to 2048 elements and over device memory above
+    that; the sorted keys and the stable order must match numpy's."""
+    rng = np.random.default_rng(n_cluster)
+    c = rng.uniform(0.0, 1e-3, size=(n_cluster, 1, 3)) + rng.uniform(-1e-5, 1e-5, size=(n_cluster, 3, 3))
+    far = rng.uniform(0.5, 1.0, size=(40, 1, 3)) + rng.uniform(-1e-2, 1e-2, size=(40, 3, 3))
+    tris = np.concatenate([c, far], 0).astype(np.float32)
+    V = tris.reshape(-1, 3)
+    T = np.arange(V.shape[0], dtype=np.int32).reshape(-1, 3)
+    m = _mesh(V, T)
+    tree = m.tree()
+    ref = _morton_reference(V, T)
+    assert np.array_equal(tree["keys"], np.sort(ref, kind="stable"))
+    assert np.array_equal(tree["order"], np.argsort(ref, kind="stable"))
+    _validate(tree, V, T, 1)
+    m.close()
