@@ -398,11 +398,26 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
         lref[slot][side] = c.ref;
         lbound[slot][side] = side ? c.r : c.l;
         lh[slot][side] = c.h;
-        const int32_t prev =
-            __hip_atomic_fetch_add(&lflag[slot], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (prev == 0) break;  // the sibling finishes this parent
+        // A wave's LDS operations are performed in the order it issues them,
+        // so the child data above is in place before the counter moves, and
+        // the sibling's data read right after the counter update (before its
+        // result is known; unused if we arrive first) is complete whenever
+        // the counter shows that the sibling arrived.  The signal fences
+        // keep the compiler from moving LDS accesses across the update; one
+        // wait then covers the update and the reads.
         const int other = 1 - side;
-        merge(c, &lbox[slot][6 * other], lbound[slot][other], lh[slot][other], side, parent, a.leaf_size);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int32_t prev = __hip_atomic_fetch_add(&lflag[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        float g[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g[k] = lbox[slot][6 * other + k];
+        const int32_t ob = lbound[slot][other], oh = lh[slot][other];
+        // an empty statement that uses the loaded values keeps the compiler
+        // from sinking the reads below the branch (it emits no instruction)
+        asm volatile("" : : "v"(g[0]), "v"(g[1]), "v"(g[2]), "v"(g[3]), "v"(g[4]), "v"(g[5]), "v"(ob), "v"(oh));
+        if (prev == 0) break;  // the sibling finishes this parent
+        merge(c, g, ob, oh, side, parent, a.leaf_size);
     }
     }
     __syncthreads();
