@@ -242,7 +242,9 @@ rsi_status rsi_inside(rsi_handle h, const float *P, int64_t n_p, uint8_t *inside
  * then wave-level counts of the persistent query loop (each wave of 64 lanes
  * adds one per iteration): all iterations, iterations that ran a node step,
  * a leaf phase, a refill.  node_visits / (64 * wave_node_steps) is the share
- * of lanes busy in node steps. */
+ * of lanes busy in node steps; of the others, summed over node steps,
+ * lanes_blocked had a node but waited for pending leaf tests and
+ * lanes_waiting had no node (walk over, or no segment). */
 typedef struct {
     uint64_t node_visits;
     uint64_t box_tests;
@@ -252,6 +254,8 @@ typedef struct {
     uint64_t wave_node_steps;
     uint64_t wave_leaf_phases;
     uint64_t wave_refills;
+    uint64_t lanes_blocked;
+    uint64_t lanes_waiting;
 } rsi_counters;
 rsi_status rsi_set_counting(rsi_handle h, int enable);
 rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);

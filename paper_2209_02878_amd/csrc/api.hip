@@ -849,6 +849,8 @@ rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out)
     out->wave_node_steps = c.wave_node_steps;
     out->wave_leaf_phases = c.wave_leaf_phases;
     out->wave_refills = c.wave_refills;
+    out->lanes_blocked = c.lanes_blocked;
+    out->lanes_waiting = c.lanes_waiting;
     return RSI_OK;
 }
 

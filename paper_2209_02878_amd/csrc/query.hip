@@ -300,6 +300,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     int32_t steps = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
+    unsigned long long w_blocked = 0, w_waiting = 0;               // wave-uniform
     int32_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
     const int32_t n_items = (int32_t)a.n_items;
     bool exhausted = false;                 // the global counter has passed the last item
@@ -428,7 +429,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             const bool want = can_step();
             w = __ballot(want);
             if (w == 0) break;
-            if (COUNT) ++w_steps;
+            if (COUNT) {
+                ++w_steps;
+                const uint64_t has_node = __ballot(node >= 0);
+                w_blocked += (unsigned long long)__popcll(has_node & ~w);
+                w_waiting += (unsigned long long)(64 - __popcll(has_node));
+            }
             if constexpr (WIDE) {
               if (want) {
                 const uint4 *q = reinterpret_cast<const uint4 *>(a.nodes4 + node);
@@ -574,6 +580,8 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             atomicAdd(&a.counters->wave_node_steps, (unsigned long long)w_steps);
             atomicAdd(&a.counters->wave_leaf_phases, (unsigned long long)w_leaf);
             atomicAdd(&a.counters->wave_refills, (unsigned long long)w_refill);
+            atomicAdd(&a.counters->lanes_blocked, w_blocked);
+            atomicAdd(&a.counters->lanes_waiting, w_waiting);
         }
     }
 }
@@ -638,6 +646,7 @@ __global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
     if (c) {
         c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
         c->wave_loops = c->wave_node_steps = c->wave_leaf_phases = c->wave_refills = 0;
+        c->lanes_blocked = c->lanes_waiting = 0;
     }
 }
 

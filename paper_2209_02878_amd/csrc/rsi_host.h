@@ -29,6 +29,7 @@ struct Counters {
     // per wave: loop iterations, iterations with a node step, with a leaf
     // phase, with a refill
     unsigned long long wave_loops, wave_node_steps, wave_leaf_phases, wave_refills;
+    unsigned long long lanes_blocked, lanes_waiting;
 };
 
 // Radix-sort scratch sized for n elements.

@@ -63,7 +63,8 @@ class rsi_counters(ctypes.Structure):
     _fields_ = [("node_visits", ctypes.c_uint64), ("box_tests", ctypes.c_uint64),
                 ("tri_tests", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("wave_loops", ctypes.c_uint64), ("wave_node_steps", ctypes.c_uint64),
-                ("wave_leaf_phases", ctypes.c_uint64), ("wave_refills", ctypes.c_uint64)]
+                ("wave_leaf_phases", ctypes.c_uint64), ("wave_refills", ctypes.c_uint64),
+                ("lanes_blocked", ctypes.c_uint64), ("lanes_waiting", ctypes.c_uint64)]
 
 
 class rsi_tree_info(ctypes.Structure):
