@@ -410,6 +410,11 @@ __device__ inline void sort_bucket_global(uint64_t *__restrict__ kin, uint32_t *
         for (uint32_t i = tid; i < bn; i += kThreads)
             atomicAdd(&gcount[(uint32_t)(ks[b0 + i] >> shift) & (kRadix - 1)], 1u);
         __syncthreads();
+        // a digit that every element of the bucket shares changes no order
+        if (gcount[(uint32_t)(ks[b0] >> shift) & (kRadix - 1)] == bn) {
+            __syncthreads();
+            continue;
+        }
         scan256(gcount, gbase);
         __syncthreads();
         for (uint32_t c0 = 0; c0 < bn; c0 += kTile) {
