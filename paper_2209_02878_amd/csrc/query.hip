@@ -93,6 +93,9 @@ __device__ inline uint32_t lanes_below(uint64_t mask)
 }
 
 // Per-lane query state for the segment it currently owns.
+// All-hits capacities up to this many keep the hit list in registers.
+constexpr int kRegSlots = 4;
+
 struct Lane {
     Seg seg;
     float tlim;        // limit on t for boxes and triangles: 1, or just above the best t
@@ -106,6 +109,7 @@ struct Lane {
     const float *sp;   // this segment's start and end (3 floats each)
     const float *ep;
     int32_t mesh;      // batched queries: the segment's mesh
+    int32_t hp0, hp1, hp2, hp3;  // all hits, capacity <= 4: the last four hit positions
     bool found;
 };
 
@@ -142,6 +146,12 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
                 // the spill pass repeats the first pass's decisions; the
                 // bound only keeps a mismatch from writing past the segment
                 if (c < L.spill_cap) a.pool_ids[L.slot_base + c] = pos;
+            } else if (a.o.cap <= kRegSlots) {
+                // kept in registers until the segment is finished
+                L.hp3 = L.hp2;
+                L.hp2 = L.hp1;
+                L.hp1 = L.hp0;
+                L.hp0 = pos;
             } else if (c < a.o.cap) {
                 a.o.ids[L.slot_base + c] = pos;
             }
@@ -244,13 +254,66 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         int32_t *ids = a.o.ids + L.slot_base;
         float *ts = a.o.ts + L.slot_base;
         const int n_in = L.count < K ? L.count : K;
-        if (L.count <= K) {
+        if (K <= kRegSlots && L.count <= K) {
+            // the hits are in registers: re-solve, order by (t, id) with a
+            // sorting network (unused entries sort last) and store once
+            int32_t id[kRegSlots];
+            float t[kRegSlots];
+            const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
+#pragma unroll
+            for (int k = 0; k < kRegSlots; ++k) {
+                id[k] = 0x7FFFFFFF;
+                t[k] = INFINITY;
+                if (k < L.count) {
+                    float v[9];
+                    int32_t tid;
+                    tri_load(a.tris, hp[k], v, tid);
+                    double tt, u, w;
+                    mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
+                    id[k] = tid;
+                    t[k] = (float)tt;
+                }
+            }
+            auto cs = [&](int x, int y) {
+                if (t[y] < t[x] || (t[y] == t[x] && id[y] < id[x])) {
+                    const float tf = t[x];
+                    t[x] = t[y];
+                    t[y] = tf;
+                    const int32_t tk = id[x];
+                    id[x] = id[y];
+                    id[y] = tk;
+                }
+            };
+            cs(0, 1);
+            cs(2, 3);
+            cs(0, 2);
+            cs(1, 3);
+            cs(1, 2);
+#pragma unroll
+            for (int k = 0; k < kRegSlots; ++k)
+                if (k >= L.count) id[k] = -1;
+            const bool vec = K == kRegSlots &&
+                             ((reinterpret_cast<uintptr_t>(a.o.ids) | reinterpret_cast<uintptr_t>(a.o.ts)) & 15) == 0;
+            if (vec) {
+                *reinterpret_cast<int4 *>(ids) = make_int4(id[0], id[1], id[2], id[3]);
+                *reinterpret_cast<float4 *>(ts) = make_float4(t[0], t[1], t[2], t[3]);
+            } else {
+                for (int c = 0; c < K; ++c) {
+                    ids[c] = id[c];
+                    ts[c] = t[c];
+                }
+            }
+        } else if (K <= kRegSlots) {
+            // more hits than slots: the spill pass writes the slots
+        } else if (L.count <= K) {
             refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n_in);
             sort_slots(ids, ts, n_in);
         }
-        for (int c = n_in; c < K; ++c) {
-            ids[c] = -1;
-            ts[c] = INFINITY;
+        if (K > kRegSlots) {
+            for (int c = n_in; c < K; ++c) {
+                ids[c] = -1;
+                ts[c] = INFINITY;
+            }
         }
         if (L.count > K) {
             const int32_t e = atomicAdd(&a.scalars[kOvfSegs], 1);
