@@ -567,16 +567,18 @@ __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, i
         }
     Node4 w;
     double inv_step[3];
-    uint32_t exps = 0;
+    float step[3];
     for (int a = 0; a < 3; ++a) {
         const int e = quant_exponent((double)hi[a] - (double)lo[a]);
         inv_step[a] = ldexp(1.0, -e);
-        exps |= (uint32_t)(e + 127) << (8 * a);
+        step[a] = ldexpf(1.0f, e);  // a normal float for e in [-126, 127]
     }
     w.ox = lo[0];
     w.oy = lo[1];
     w.oz = lo[2];
-    w.exps = exps;
+    w.sx = step[0];
+    w.sy = step[1];
+    w.sz = step[2];
     for (int a = 0; a < 3; ++a) {
         uint32_t ql = 0, qh = 0;
         for (int s = 0; s < 4; ++s) {
@@ -591,7 +593,6 @@ __global__ __launch_bounds__(256) void k_widen(const Node *__restrict__ nodes, i
         w.lo[a] = ql;
         w.hi[a] = qh;
     }
-    w.pad[0] = w.pad[1] = 0;
     for (int s = 0; s < 4; ++s) w.ref[s] = s < k ? ref[s] : kEmptySlot;
     out[j] = w;
 }

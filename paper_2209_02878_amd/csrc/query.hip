@@ -360,7 +360,11 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     // pending leaf references (leaf refs are negative; 0 = none): filled in
     // order in the binary walk, by child slot in the four-way walk
     int32_t leaf0 = 0, leaf1 = 0, leaf2 = 0, leaf3 = 0;
-    int32_t steps = 0;
+    // bound on a walk (a damaged tree can give wrong answers, never a hang):
+    // the wave counts its node-step rounds, each lane notes the round its
+    // segment started in, and every 64 rounds lanes past max_steps rounds stop
+    int32_t wround = 0;      // wave-uniform
+    int32_t start_round = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
     unsigned long long w_blocked = 0, w_waiting = 0;               // wave-uniform
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     node = entry;  // < 0 for an empty mesh: the segment misses
                     sp = 0;
                     sptr = stk;
-                    steps = 0;
+                    start_round = wround;
                     if (COUNT) ++segs;
                 } else if (exhausted) {
                     item = -2;
@@ -506,9 +510,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const float lim = ((MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f) * (1.0f + 0x1p-20f);
                 // grid steps, the corner's offset from the segment origin and
                 // the margin that makes the plane evaluation conservative
-                const float sx = __uint_as_float((P.w & 0xFFu) << 23);
-                const float sy = __uint_as_float((P.w & 0xFF00u) << 15);
-                const float sz = __uint_as_float((P.w & 0xFF0000u) << 7);
+                const float sx = __uint_as_float(R.z), sy = __uint_as_float(R.w), sz = __uint_as_float(P.w);
                 const float Dx = __uint_as_float(P.x) - L.seg.ox;
                 const float Dy = __uint_as_float(P.y) - L.seg.oy;
                 const float Dz = __uint_as_float(P.z) - L.seg.oz;
@@ -557,8 +559,6 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 push(g2 && C.z != near, C.z);
                 push(g3 && C.w != near, C.w);
                 node = near >= 0 ? near : pop();
-                // bound on the walk: a damaged tree can give wrong answers, never a hang
-                if (++steps >= a.max_steps) node = -1;
               }
             } else if (want) {
                 const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
@@ -592,9 +592,8 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const bool take_l = gl && (!gr || tl <= tr);
                 push(gl && gr, take_l ? cr : cl);
                 node = (gl || gr) ? (take_l ? cl : cr) : pop();
-                // bound on the walk: a damaged tree can give wrong answers, never a hang
-                if (++steps >= a.max_steps) node = -1;
             }
+            if ((++wround & 63) == 0 && wround - start_round >= a.max_steps) node = -1;
         } while ((int)__popcll(w) >= a.defer);
 
         // ---- test pending leaves once few lanes can still step

@@ -38,8 +38,8 @@ static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 // grandchild's index, or a leaf) is valid in both arrays.
 //
 //   ox, oy, oz   lower corner of n's box (exact)
-//   exps         bytes 0..2: biased exponents b of the x, y, z grid steps,
-//                step = 2^(b - 127), so 255 steps span n's box
+//   sx, sy, sz   grid steps, powers of two (2^-126 .. 2^122) with 255
+//                steps spanning n's box on that axis
 //   lo[a]        byte c: child c's lower plane on axis a in grid steps,
 //                rounded down;  hi[a] likewise for the upper plane, rounded
 //                up -- every quantised box contains its exact child box
@@ -47,14 +47,13 @@ static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 //
 // Halving the record (the exact four-way layout needs 128 bytes) halves the
 // vector-cache lookups per visit, which bound the binary walk.  Any finite
-// box is representable (steps 2^-126 .. 2^122).
+// box is representable.
 constexpr int32_t kEmptySlot = 0x7FFFFFFF;
 struct alignas(64) Node4 {
-    float ox, oy, oz;
-    uint32_t exps;
+    float ox, oy, oz, sz;
     uint32_t lo[3];
     uint32_t hi[3];
-    uint32_t pad[2];
+    float sx, sy;
     int32_t ref[4];
 };
 static_assert(sizeof(Node4) == 64, "Node4 must be 64 bytes");
