@@ -10,14 +10,18 @@
 // waits for its slowest lane leaves most of its lanes idle, which the refill
 // avoids.
 //
-// A lane walks the tree from the entry node with a stack kept in LDS, laid
-// out [depth][lane] so a wave's pushes and pops hit distinct banks; the stack
-// is sized from the tree height, so it cannot overflow.  Each node step loads
-// one 64-byte node, tests the segment against both child boxes, remembers up
-// to two touched leaf children as pending, and descends into the nearer
-// touched internal child (pushing the other) or pops.  Pending leaves are
-// tested once few lanes can still take a node step, so the triangle test runs
-// with most lanes active.  The paper's bounded candidate list with resume
+// A lane walks the tree from the entry node with a stack laid out
+// [depth][lane] in LDS so a wave's pushes and pops hit distinct banks; its
+// depth is sized from the tree height, so it cannot overflow, and entries
+// beyond the LDS part (the four-way walk keeps 20 there by default) go to a
+// per-lane tail in device memory.  Each node step loads one 64-byte record.
+// The default four-way walk (Node4) tests the segment against the four
+// quantised boxes of the node's grandchildren, keeps the touched leaf
+// children as pending, descends into the nearest touched internal child and
+// pushes the others; the binary walk (Node, branching 2) tests the two exact
+// child boxes, keeps walking past one pending leaf and descends into the
+// nearer touched child.  Pending leaves are tested once few lanes can still
+// take a node step, so the triangle test runs with most lanes active.  The paper's bounded candidate list with resume
 // (Section 3.2) is therefore not needed: candidates are tested soon after
 // they are found, and the bounded buffers left are the stack and the
 // all-hits slots, whose overflow is detected and retried into a pool.

@@ -45,8 +45,8 @@ static_assert(sizeof(Node) == 64, "Node must be 64 bytes");
 //                up -- every quantised box contains its exact child box
 //   ref[c]       child reference, kEmptySlot for an unused slot
 //
-// Halving the record (the exact four-way layout needs 128 bytes) halves the
-// vector-cache lookups per visit, which bound the binary walk.  Any finite
+// With exact boxes the four-way record would need 128 bytes; 64 bytes halve
+// the vector-cache lookups per visited box, which bound the binary walk.  Any finite
 // box is representable.
 constexpr int32_t kEmptySlot = 0x7FFFFFFF;
 struct alignas(64) Node4 {
