@@ -37,6 +37,7 @@ struct SortScratch {
     uint64_t *keys_alt = nullptr;
     uint32_t *vals_alt = nullptr;
     uint32_t *hist = nullptr;
+    uint32_t *h_word = nullptr;  // pinned host word: a read-back of the sort
     int64_t cap = 0;
     int64_t hist_cap = 0;
 };

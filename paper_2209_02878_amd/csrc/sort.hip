@@ -452,35 +452,65 @@ __device__ inline void sort_bucket_global(uint64_t *__restrict__ kin, uint32_t *
     }
 }
 
-// One workgroup per top-digit bucket of a small sort.  kin/vin hold the
-// elements grouped by their top digit (stable), `hist` the per-tile counts
-// of that digit; each bucket is sorted by its `nlow` lower digits and written
-// to the same offsets in kout/vout.
+// One workgroup per top-digit bucket.  kin/vin hold the elements grouped
+// by their top digit (stable); `hist` holds that digit's per-tile counts
+// (digit-major), raw or (`scanned`) as the exclusive scan of the whole
+// table, whose entry (d, tile 0) is bucket d's offset.  Each bucket is
+// sorted by its `nlow` lower digits and written to the same offsets in
+// kout/vout: in LDS up to kBucketLds elements, else over device memory.
+constexpr int kBucketLds = 16 * kThreads;
+
 __global__ __launch_bounds__(kThreads) void k_bucket_sort(uint64_t *__restrict__ kin, uint32_t *__restrict__ vin,
                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                          const uint32_t *__restrict__ hist, int ntiles, int nlow)
+                                                          const uint32_t *__restrict__ hist, int ntiles, int64_t n,
+                                                          int scanned, int nlow)
 {
-    __shared__ uint32_t wcnt[kItems * kWaves * kRadix];
+    __shared__ uint32_t wcnt[16 * kWaves * kRadix];
     __shared__ uint32_t run[kRadix], start[kRadix], gcount[kRadix], gbase[kRadix];
-    __shared__ uint64_t skey[kTile];
-    __shared__ uint32_t sval[kTile];
+    __shared__ uint64_t skey[kBucketLds];
+    __shared__ uint32_t sval[kBucketLds];
     const int tid = threadIdx.x;
-    // bucket sizes and offsets: digit tid's total over the tiles, scanned
-    uint32_t tot = 0;
-    for (int b = 0; b < ntiles; ++b) tot += hist[(int64_t)tid * ntiles + b];
-    gcount[tid] = tot;
-    __syncthreads();
-    scan256(gcount, gbase);
-    __syncthreads();
-    const uint32_t b0 = gbase[blockIdx.x], bn = gcount[blockIdx.x];
-    __syncthreads();
+    uint32_t b0, bn;
+    if (scanned) {
+        const int d = blockIdx.x;
+        b0 = hist[(int64_t)d * ntiles];
+        const uint32_t end = d + 1 < kRadix ? hist[(int64_t)(d + 1) * ntiles] : (uint32_t)n;
+        bn = end - b0;
+    } else {
+        // bucket sizes and offsets: digit tid's total over the tiles, scanned
+        uint32_t tot = 0;
+        for (int b = 0; b < ntiles; ++b) tot += hist[(int64_t)tid * ntiles + b];
+        gcount[tid] = tot;
+        __syncthreads();
+        scan256(gcount, gbase);
+        __syncthreads();
+        b0 = gbase[blockIdx.x];
+        bn = gcount[blockIdx.x];
+        __syncthreads();
+    }
     if (bn == 0) return;
     if (bn <= (uint32_t)kThreads)
         sort_bucket_lds<1>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
     else if (bn <= (uint32_t)kTile)
         sort_bucket_lds<kItems>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
+    else if (bn <= (uint32_t)kBucketLds)
+        sort_bucket_lds<16>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
     else
         sort_bucket_global(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, gcount, gbase);
+}
+
+// Largest bucket of a scanned top-digit table (one workgroup of 256).
+__global__ __launch_bounds__(kThreads) void k_bucket_max(const uint32_t *__restrict__ hist, int ntiles, int64_t n,
+                                                         uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t m[kWaves];
+    const int d = threadIdx.x;
+    const uint32_t end = d + 1 < kRadix ? hist[(int64_t)(d + 1) * ntiles] : (uint32_t)n;
+    uint32_t size = end - hist[(int64_t)d * ntiles];
+    for (int off = 32; off > 0; off >>= 1) size = max(size, (uint32_t)__shfl_xor(size, off, 64));
+    if (__lane_id() == 0) m[d >> 6] = size;
+    __syncthreads();
+    if (d == 0) out[0] = max(max(m[0], m[1]), max(m[2], m[3]));
 }
 
 __global__ void k_copy_pairs(const uint64_t *__restrict__ ks, const uint32_t *__restrict__ vs,
@@ -511,8 +541,9 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
     const int64_t ntiles = (n + kTile - 1) / kTile;
     // fused path: three rotating histograms; else one table plus the
     // partial sums of the three-launch scan
-    const int64_t hn = ntiles <= kFusedTiles ? 3 * kFusedTiles * kRadix
-                                             : ntiles * kRadix + (ntiles * kRadix + kScanChunk - 1) / kScanChunk;
+    // (plus one word for the largest bucket of a bucket sort)
+    const int64_t hn = 1 + (ntiles <= kFusedTiles ? 3 * kFusedTiles * kRadix
+                                                  : ntiles * kRadix + (ntiles * kRadix + kScanChunk - 1) / kScanChunk);
     if (hn > sc.hist_cap) {
         if (sc.hist) (void)hipFree(sc.hist);
         sc.hist = nullptr;
@@ -520,6 +551,7 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
         if ((e = hipMalloc(&sc.hist, sizeof(uint32_t) * hn)) != hipSuccess) return e;
         sc.hist_cap = hn;
     }
+    if (!sc.h_word) e = hipHostMalloc(reinterpret_cast<void **>(&sc.h_word), sizeof(uint32_t));
     return e;
 }
 
@@ -528,6 +560,7 @@ void free_sort_scratch(SortScratch &sc)
     if (sc.keys_alt) (void)hipFree(sc.keys_alt);
     if (sc.vals_alt) (void)hipFree(sc.vals_alt);
     if (sc.hist) (void)hipFree(sc.hist);
+    if (sc.h_word) (void)hipHostFree(sc.h_word);
     sc = SortScratch();
 }
 
@@ -552,6 +585,25 @@ void fused_passes(uint64_t *ka, uint32_t *va, uint64_t *kb, uint32_t *vb, int64_
     }
 }
 
+// Exclusive scan of a digit-major histogram table in place: one workgroup
+// for small tables, else block sums, their scan and a rescan of each block.
+static void scan_table(uint32_t *hist, int64_t hsz, hipStream_t s)
+{
+    if (hsz <= 4 * kScanChunk) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, hsz);
+    } else {
+        const int64_t nparts = (hsz + kScanChunk - 1) / kScanChunk;
+        uint32_t *part = hist + hsz;
+        hipLaunchKernelGGL(k_part_sums, dim3((unsigned)nparts), dim3(256), 0, s, hist, hsz, part);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, part, nparts);
+        hipLaunchKernelGGL(k_part_apply, dim3((unsigned)nparts), dim3(256), 0, s, hist, hsz, part);
+    }
+}
+
+// Largest top-digit bucket for which large inputs take the bucket sort
+// (beyond it one workgroup would carry too much of the work).
+constexpr uint32_t kBucketLarge = 16384;
+
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &sc,
                             hipStream_t s, const int64_t *mesh_off, int32_t M)
 {
@@ -571,44 +623,65 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     uint64_t *ka = keys, *kb = sc.keys_alt;
     uint32_t *va = vals, *vb = sc.vals_alt;
     const int64_t hsz = (int64_t)ntiles * kRadix;
-    if (ntiles <= kFusedTiles && np == (key_bits + 7) / 8 && key_bits > 8) {
-        // small sort of key digits only: one stable pass on the top 8 bits
-        // groups the elements into 256 buckets, then one workgroup per bucket
-        // sorts it by the lower bits (in LDS up to kTile elements), so three
-        // launches replace one per digit
+    // Key digits by buckets: one stable pass on the top 8 bits groups the
+    // elements into 256 buckets, then one workgroup per bucket sorts it by
+    // the lower digits (k_bucket_sort), so three or four launches replace
+    // one or more per digit.  Small inputs always take this path; larger
+    // ones when their largest bucket stays within kBucketLarge (read back
+    // after the top digit's histogram; not while a graph is being
+    // captured, when the digit passes below run instead).
+    int p0 = 0;  // first pass still to run
+    if (key_bits > 8) {
         const int top = key_bits - 8;
         const Digit dtop{nullptr, 0, top};
-        hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist, ntiles,
-                           nullptr);
-        hipLaunchKernelGGL((k_scatter<true, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dtop,
-                           sc.hist, ntiles, dtop, nullptr, nullptr);
-        hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist, ntiles,
-                           (top + 7) / 8);
-        return hipGetLastError();
+        const int nlow = (top + 7) / 8;
+        if (ntiles <= kFusedTiles) {
+            hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist, ntiles,
+                               nullptr);
+            hipLaunchKernelGGL((k_scatter<true, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
+                               dtop, sc.hist, ntiles, dtop, nullptr, nullptr);
+            hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist, ntiles, n,
+                               0, nlow);
+            p0 = (key_bits + 7) / 8;
+        } else if (n <= (int64_t)kRadix * kBucketLarge) {  // else even the average bucket is too large
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            hipError_t ce = hipStreamIsCapturing(s, &cs);
+            if (ce != hipSuccess) return ce;
+            if (cs == hipStreamCaptureStatusNone) {
+                hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist,
+                                   ntiles, nullptr);
+                scan_table(sc.hist, hsz, s);
+                uint32_t *dmax = sc.hist + sc.hist_cap - 1;
+                hipLaunchKernelGGL(k_bucket_max, dim3(1), dim3(kThreads), 0, s, sc.hist, ntiles, n, dmax);
+                hipError_t me = hipMemcpyAsync(sc.h_word, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+                if (me == hipSuccess) me = hipStreamSynchronize(s);
+                if (me != hipSuccess) return me;
+                if (*sc.h_word <= (uint32_t)kBucketLarge) {
+                    hipLaunchKernelGGL((k_scatter<false, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb,
+                                       vb, n, dtop, sc.hist, ntiles, dtop, nullptr, nullptr);
+                    hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist,
+                                       ntiles, n, 1, nlow);
+                    p0 = (key_bits + 7) / 8;
+                }
+            }
+        }
     }
+    if (p0 == np) return hipGetLastError();
     if (ntiles <= kFusedTiles) {
         // (smaller tiles, hence more workgroups, measured slower: each
         // workgroup then scans more histograms and the next-pass counters
         // see more atomic traffic)
-        fused_passes<kItems>(ka, va, kb, vb, n, passes, np, sc, s);
-        if (np & 1) {
+        fused_passes<kItems>(ka, va, kb, vb, n, passes + p0, np - p0, sc, s);
+        if ((np - p0) & 1) {
             uint64_t *tk = ka; ka = kb; kb = tk;
             uint32_t *tv = va; va = vb; vb = tv;
         }
     } else {
-        for (int p = 0; p < np; ++p) {
+        for (int p = p0; p < np; ++p) {
             const Digit dg = passes[p];
             hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dg, sc.hist, ntiles,
                                nullptr);
-            if (hsz <= 4 * kScanChunk) {
-                hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, sc.hist, hsz);
-            } else {
-                const int64_t nparts = (hsz + kScanChunk - 1) / kScanChunk;
-                uint32_t *part = sc.hist + hsz;
-                hipLaunchKernelGGL(k_part_sums, dim3((unsigned)nparts), dim3(256), 0, s, sc.hist, hsz, part);
-                hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, part, nparts);
-                hipLaunchKernelGGL(k_part_apply, dim3((unsigned)nparts), dim3(256), 0, s, sc.hist, hsz, part);
-            }
+            scan_table(sc.hist, hsz, s);
             hipLaunchKernelGGL((k_scatter<false, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n, dg,
                                sc.hist, ntiles, dg, nullptr, nullptr);
             uint64_t *tk = ka; ka = kb; kb = tk;

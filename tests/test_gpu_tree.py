@@ -146,3 +146,27 @@ def test_sort_clustered_buckets(n_cluster):
     assert np.array_equal(tree["order"], np.argsort(ref, kind="stable"))
     _validate(tree, V, T, 1)
     m.close()
+
+
+@pytest.mark.parametrize("kind", ["sphere", "clustered"])
+def test_sort_large_inputs(kind):
+    """Above 131,072 keys the sort reads back the largest top-digit bucket:
+    a sphere of 180,500 triangles spreads over many buckets (bucket sort),
+    a mesh with most triangles in one corner cell does not (digit passes).
+    Either way the keys and the stable order must match numpy's."""
+    if kind == "sphere":
+        V, T = wl.noisy_sphere(95, 12, 0.3)
+    else:
+        rng = np.random.default_rng(7)
+        c = rng.uniform(0.0, 1e-3, size=(140_000, 1, 3)) + rng.uniform(-1e-5, 1e-5, size=(140_000, 3, 3))
+        far = rng.uniform(0.5, 1.0, size=(200, 1, 3)) + rng.uniform(-1e-2, 1e-2, size=(200, 3, 3))
+        V = np.concatenate([c, far], 0).astype(np.float32).reshape(-1, 3)
+        T = np.arange(V.shape[0], dtype=np.int32).reshape(-1, 3)
+    assert T.shape[0] > 131_072
+    m = _mesh(V, T)
+    tree = m.tree()
+    ref = _morton_reference(V, T)
+    assert np.array_equal(tree["keys"], np.sort(ref, kind="stable"))
+    assert np.array_equal(tree["order"], np.argsort(ref, kind="stable"))
+    _validate(tree, V, T, 1)
+    m.close()
