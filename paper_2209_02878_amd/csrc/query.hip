@@ -228,7 +228,12 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         float *tt = BATCH ? a.bt.t[L.mesh] : a.o.t;
         float *uv = BATCH ? a.bt.uv[L.mesh] : a.o.uv;
         float *pt = BATCH ? a.bt.point[L.mesh] : a.o.point;
-        if (L.best_pos >= 0) {
+        if (L.best_pos >= 0 && !(MODE & M_ALL)) {
+            // the hit's sorted position; k_refine_first re-solves it and
+            // writes the id, t, (u, v) and the point
+            tri[i] = L.best_pos;
+        } else if (L.best_pos >= 0) {
+            // with all hits the walk keeps many registers anyway: re-solve here
             float v[9];
             int32_t id;
             tri_load(a.tris, L.best_pos, v, id);
@@ -716,6 +721,57 @@ __global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
     }
 }
 
+// FP64 re-solve of every first hit, after a walk without all hits: the walk
+// leaves the sorted position of the hit triangle in tri (misses are
+// complete), and this pass writes the triangle's id, t, (u, v) and the
+// point.  Kept out of the walk, whose registers (hence waves per SIMD) it
+// would otherwise raise for the whole traversal.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_refine_first(QArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_items; k += stride) {
+        int64_t i = k;
+        const float *S = a.S, *E = a.E;
+        int32_t *tri = a.o.tri;
+        float *tt = a.o.t, *uv = a.o.uv, *pt = a.o.point;
+        if (BATCH) {
+            const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
+            i = k - a.bt.seg_off[m];
+            S = a.bt.S[m];
+            E = a.bt.E[m];
+            tri = a.bt.tri[m];
+            tt = a.bt.t[m];
+            uv = a.bt.uv[m];
+            pt = a.bt.point[m];
+        }
+        const int32_t pos = tri[i];
+        if (pos < 0) continue;
+        const float sx = S[3 * i], sy = S[3 * i + 1], sz = S[3 * i + 2];
+        const float ex = E[3 * i], ey = E[3 * i + 1], ez = E[3 * i + 2];
+        float v[9];
+        int32_t id;
+        tri_load(a.tris, pos, v, id);
+        double t, u, w;
+        mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
+        tri[i] = id;
+        tt[i] = (float)t;
+        uv[2 * i] = (float)u;
+        uv[2 * i + 1] = (float)w;
+        pt[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
+        pt[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
+        pt[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
+    }
+}
+
+template <bool BATCH>
+hipError_t launch_refine_first(const QArgs &a, hipStream_t s)
+{
+    const int64_t blocks = (a.n_items + 255) / 256;
+    hipLaunchKernelGGL(k_refine_first<BATCH>, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE>
 hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
@@ -854,8 +910,9 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
     QArgs a = make_args(h, S, E, n_r, o);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, (mode & M_ALL) ? 1 : 0,
                        h->counting ? h->counters : nullptr);
-    if (h->counting) return dispatch<true>(mode, a, block, lds, s);
-    return dispatch<false>(mode, a, block, lds, s);
+    hipError_t e = h->counting ? dispatch<true>(mode, a, block, lds, s) : dispatch<false>(mode, a, block, lds, s);
+    if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<false>(a, s);
+    return e;
 }
 
 hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mode, const QueryOut &o,
@@ -882,12 +939,15 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
     QArgs a = make_args(h, nullptr, nullptr, n_total, o);
     a.bt = bt;
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
+    hipError_t e;
     switch (mode) {
-    case M_BOOL: return launch_mode<M_BOOL, false, false, true>(a, block, lds, s);
-    case M_FIRST: return launch_mode<M_FIRST, false, false, true>(a, block, lds, s);
-    case M_FIRST | M_BOOL: return launch_mode<M_FIRST | M_BOOL, false, false, true>(a, block, lds, s);
+    case M_BOOL: e = launch_mode<M_BOOL, false, false, true>(a, block, lds, s); break;
+    case M_FIRST: e = launch_mode<M_FIRST, false, false, true>(a, block, lds, s); break;
+    case M_FIRST | M_BOOL: e = launch_mode<M_FIRST | M_BOOL, false, false, true>(a, block, lds, s); break;
     default: return hipErrorInvalidValue;
     }
+    if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<true>(a, s);
+    return e;
 }
 
 hipError_t ensure_gstack(rsi_bvh *h)
