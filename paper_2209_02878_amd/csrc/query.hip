@@ -527,11 +527,13 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 // non-negative direction component; the margin moves it
                 // toward the segment origin and the other plane away
                 const bool px = L.seg.ix >= 0.0f, py = L.seg.iy >= 0.0f, pz = L.seg.iz >= 0.0f;
-                const float mx = fminf(fmaf(255.0f, sx, fabsf(Dx)), FLT_MAX) * (px ? 0x1p-19f : -0x1p-19f);
-                const float my = fminf(fmaf(255.0f, sy, fabsf(Dy)), FLT_MAX) * (py ? 0x1p-19f : -0x1p-19f);
-                const float mz = fminf(fmaf(255.0f, sz, fabsf(Dz)), FLT_MAX) * (pz ? 0x1p-19f : -0x1p-19f);
-                const float Nx = Dx - mx, Ny = Dy - my, Nz = Dz - mz;
-                const float Fx = Dx + mx, Fy = Dy + my, Fz = Dz + mz;
+                const float mx = fmaf(255.0f, sx, fabsf(Dx)) * (px ? 0x1p-19f : -0x1p-19f);
+                const float my = fmaf(255.0f, sy, fabsf(Dy)) * (py ? 0x1p-19f : -0x1p-19f);
+                const float mz = fmaf(255.0f, sz, fabsf(Dz)) * (pz ? 0x1p-19f : -0x1p-19f);
+                // plane q of an axis lies at parameter fma(q, a, b)
+                const float ax = sx * L.seg.ix, ay = sy * L.seg.iy, az = sz * L.seg.iz;
+                const float bnx = (Dx - mx) * L.seg.ix, bny = (Dy - my) * L.seg.iy, bnz = (Dz - mz) * L.seg.iz;
+                const float bfx = (Dx + mx) * L.seg.ix, bfy = (Dy + my) * L.seg.iy, bfz = (Dz + mz) * L.seg.iz;
                 // child c: lower planes in byte c of Q.x, Q.y, Q.z, upper
                 // planes in byte c of Q.w, R.x, R.y
                 const uint32_t nqx = px ? Q.x : Q.w, fqx = px ? Q.w : Q.x;
@@ -539,7 +541,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const uint32_t nqz = pz ? Q.z : R.y, fqz = pz ? R.y : Q.z;
                 auto qb = [](uint32_t v, int c) { return (float)((v >> (8 * c)) & 0xFFu); };
                 auto test = [&](int c, float &t) {
-                    return qslab_hit(L.seg, Nx, Ny, Nz, Fx, Fy, Fz, sx, sy, sz, qb(nqx, c), qb(nqy, c), qb(nqz, c),
+                    return qslab_hit(ax, ay, az, bnx, bny, bnz, bfx, bfy, bfz, qb(nqx, c), qb(nqy, c), qb(nqz, c),
                                      qb(fqx, c), qb(fqy, c), qb(fqz, c), lim, t);
                 };
                 float t0, t1, t2, t3;

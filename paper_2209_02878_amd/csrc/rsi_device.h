@@ -89,7 +89,6 @@ struct Seg {
     float ox, oy, oz;
     float dx, dy, dz;
     float ix, iy, iz;
-    float jx, jy, jz;  // (1/d) (1 + 2^-20): the far planes' reciprocals in qslab_hit
 };
 
 __device__ inline float guarded_rcp(float d)
@@ -116,9 +115,6 @@ __device__ inline Seg make_seg(float sx, float sy, float sz, float ex, float ey,
     r.ix = guarded_rcp(r.dx);
     r.iy = guarded_rcp(r.dy);
     r.iz = guarded_rcp(r.dz);
-    r.jx = r.ix * (1.0f + 0x1p-20f);
-    r.jy = r.iy * (1.0f + 0x1p-20f);
-    r.jz = r.iz * (1.0f + 0x1p-20f);
     return r;
 }
 
@@ -140,36 +136,35 @@ __device__ inline bool slab_hit(const Seg &s, float lx, float ly, float lz,
     return n <= f * (1.0f + 0x1p-20f);
 }
 
-// Conservative segment / quantised-box test for the four-way view.  The
-// caller forms, per node and axis, D = corner - o and the margin
-// eps = min(255 step + |D|, FLT_MAX) 2^-19, and passes the bases of the
-// plane the segment meets first on that axis (the lower plane when the
-// direction component is non-negative -- 1/d keeps the sign of d, zero
-// included) and of the other one: N = D - eps, F = D + eps for a
-// non-negative component, N = D + eps, F = D - eps otherwise, with the
-// matching quantised planes qn, qf.  A plane's offset from the segment
-// origin is then fma(q, step, base): q * step is exact, and the roundings
-// of D, of D -+ eps and of the fma together stay below
-// 3 * 2^-24 (|D| + 255 step), under a fifth of eps, so a lower plane's
-// offset never exceeds and an upper plane's never falls below the exact
-// quantised plane: the tested box contains the quantised box, which
-// contains the child box.  (The FLT_MAX cap only binds where the offsets
-// approach the FP32 range; eps stays finite, so no inf - inf arises.)
-// Times 1/d, the first plane's offset gives the smaller parameter (the
-// offsets are ordered and 1/d has the direction's sign), so no per-axis
-// min/max is needed.  Each product carries the relative error that
-// slab_hit's slack covers; here the slack is folded into the far planes'
-// reciprocals (s.jx..s.jz) and into `tmax_s` = tmax (1 + 2^-20), which
-// scales every non-negative far parameter up by it (a negative one means
-// the box lies before t = 0, and its sign is exact).  qnx..qfz are the
-// quantised planes as floats.
-__device__ inline bool qslab_hit(const Seg &s, float Nx, float Ny, float Nz, float Fx, float Fy, float Fz,
-                                 float sx, float sy, float sz, float qnx, float qny, float qnz, float qfx,
-                                 float qfy, float qfz, float tmax_s, float &tnear)
+// Conservative segment / quantised-box test for the four-way view.  Per
+// node and axis the caller forms D = corner - o, the margin
+// eps = (255 step + |D|) 2^-19 and the parameter of grid plane q
+// as one fused multiply-add, fma(q, a, b), with a = step * (1/d) and
+// b = (D -+ eps) * (1/d): the lower sign for the plane the segment meets
+// first on that axis (the lower plane when the direction component is
+// non-negative -- 1/d keeps the sign of d, zero included), the upper sign
+// for the other one; qn and qf are those planes' quantised values as floats.
+// step is a power of two, so a is exact (barring underflow, i.e. |d| near
+// the FP32 range).  The roundings of D, of D -+ eps, of b and of the fma, and
+// the reciprocal's own error (within 1 ulp), add up to at most
+// 6 * 2^-24 (|D| + 255 step) in plane-offset units, under a fifth of eps: a
+// first plane's parameter never exceeds, and an other plane's never falls
+// below, that of the exact quantised plane, so the tested box contains the
+// quantised box, which contains the child box.  No per-axis min/max is
+// needed, and no further slack on the far side.  A product that leaves the
+// FP32 range makes the parameter an infinity with the sign of the exact
+// one, which then lies far outside [0, 1], or NaN (an exactly zero offset
+// with d near zero), which fmaxf / fminf skip with the bounds 0 and tmax_s
+// still in place, so such a plane never rejects a box that the exact test
+// accepts.  `tmax_s` is the segment's upper parameter with the slack that
+// covers the FP32 error of a first-hit bound.
+__device__ inline bool qslab_hit(float ax, float ay, float az, float bnx, float bny, float bnz, float bfx,
+                                 float bfy, float bfz, float qnx, float qny, float qnz, float qfx, float qfy,
+                                 float qfz, float tmax_s, float &tnear)
 {
-    const float nx = fmaf(qnx, sx, Nx) * s.ix, fx = fmaf(qfx, sx, Fx) * s.jx;
-    const float ny = fmaf(qny, sy, Ny) * s.iy, fy = fmaf(qfy, sy, Fy) * s.jy;
-    const float nz = fmaf(qnz, sz, Nz) * s.iz, fz = fmaf(qfz, sz, Fz) * s.jz;
+    const float nx = fmaf(qnx, ax, bnx), fx = fmaf(qfx, ax, bfx);
+    const float ny = fmaf(qny, ay, bny), fy = fmaf(qfy, ay, bfy);
+    const float nz = fmaf(qnz, az, bnz), fz = fmaf(qfz, az, bfz);
     const float n = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
     const float f = fminf(fminf(fx, fy), fminf(fz, tmax_s));
     tnear = n;
