@@ -383,7 +383,7 @@ def main():
             "cores": threads,
             "kind": "oracle",
             "sample": f"first {n_s} of the 10M segments against all 29,768 triangles, FP64 brute force "
-                      f"over every pair, {dt:.1f} s",
+                      f"over every pair (box-overlap check, then the exact test), {dt:.1f} s",
             "cpu": platform.processor() or platform.machine(),
         }
         log(f"cpu baseline: {rec['cpu_baseline']}")
