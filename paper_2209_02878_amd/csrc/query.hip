@@ -565,10 +565,39 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 if (g1 && t1 < bt) { bt = t1; near = C.y; }
                 if (g2 && t2 < bt) { bt = t2; near = C.z; }
                 if (g3 && t3 < bt) { bt = t3; near = C.w; }
-                push(g0 && C.x != near, C.x);
-                push(g1 && C.y != near, C.y);
-                push(g2 && C.z != near, C.z);
-                push(g3 && C.w != near, C.w);
+                const bool p0 = g0 && C.x != near, p1 = g1 && C.y != near;
+                const bool p2 = g2 && C.z != near, p3 = g3 && C.w != near;
+                // at most three pushes (the nearest child is taken, not
+                // pushed): with room for three more entries in LDS every
+                // child is written at the top and the top advances past the
+                // pushed ones only (a write past them lands in a free slot)
+                bool room;
+                if constexpr (HYB) room = sp + 3 * stride < lds_off;
+                else room = sptr + 3 * stride < stk_end;
+                if (room && HYB) {
+                    stk[sp] = C.x;
+                    sp += p0 ? stride : 0;
+                    stk[sp] = C.y;
+                    sp += p1 ? stride : 0;
+                    stk[sp] = C.z;
+                    sp += p2 ? stride : 0;
+                    stk[sp] = C.w;
+                    sp += p3 ? stride : 0;
+                } else if (room) {
+                    *sptr = C.x;
+                    sptr += p0 ? stride : 0;
+                    *sptr = C.y;
+                    sptr += p1 ? stride : 0;
+                    *sptr = C.z;
+                    sptr += p2 ? stride : 0;
+                    *sptr = C.w;
+                    sptr += p3 ? stride : 0;
+                } else {
+                    push(p0, C.x);
+                    push(p1, C.y);
+                    push(p2, C.z);
+                    push(p3, C.w);
+                }
                 node = near >= 0 ? near : pop();
               }
             } else if (want) {
