@@ -91,6 +91,10 @@ __device__ inline void wave_add_u64(unsigned long long *dst, unsigned long long 
     if (__lane_id() == 0) atomicAdd(dst, v);
 }
 
+// Mask of the wave's active lanes whose predicate holds (the predicate
+// stays a lane mask, never materialised as an integer per lane).
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline uint32_t lanes_below(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -389,15 +393,15 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         // chunk is claimed from the global counter with one atomic.
         if (COUNT) ++w_loops;
         const bool done = item >= 0 && node < 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf0 == 0);
-        const uint64_t waiting = __ballot(done || item == -1);
+        const uint64_t waiting = ballot(done || item == -1);
         if (waiting != 0 &&
-            ((int)__popcll(waiting) >= a.refill || __ballot(item >= 0 && !done) == 0)) {
+            ((int)__popcll(waiting) >= a.refill || ballot(item >= 0 && !done) == 0)) {
             if (COUNT) ++w_refill;
             if (done) {
                 finish<MODE, SPILL, BATCH>(a, L);
                 item = -1;
             }
-            const uint64_t idle = __ballot(item == -1);
+            const uint64_t idle = ballot(item == -1);
             const int32_t n_idle = (int32_t)__popcll(idle);
             const int32_t rank = (int32_t)lanes_below(idle);
             int32_t k = -1;
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 }
             }
         }
-        if (__ballot(item >= 0) == 0) break;
+        if (ballot(item >= 0) == 0) break;
 
         auto push = [&](bool cond, int32_t child) {
             if constexpr (!HYB) {
@@ -503,11 +507,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         uint64_t w;
         do {
             const bool want = can_step();
-            w = __ballot(want);
+            // the two conditions' masks, each straight from its compare
+            w = ballot(node >= 0) & ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf1 == 0);
             if (w == 0) break;
             if (COUNT) {
                 ++w_steps;
-                const uint64_t has_node = __ballot(node >= 0);
+                const uint64_t has_node = ballot(node >= 0);
                 w_blocked += (unsigned long long)__popcll(has_node & ~w);
                 w_waiting += (unsigned long long)(64 - __popcll(has_node));
             }
@@ -633,11 +638,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 push(gl && gr, take_l ? cr : cl);
                 node = (gl || gr) ? (take_l ? cl : cr) : pop();
             }
-            if ((++wround & 63) == 0 && wround - start_round >= a.max_steps) node = -1;
+            // the bound is checked every 64 rounds, behind a wave-uniform branch
+            if (__builtin_expect((++wround & 63) == 0, 0)) {
+                if (wround - start_round >= a.max_steps) node = -1;
+            }
         } while ((int)__popcll(w) >= a.defer);
 
         // ---- test pending leaves once few lanes can still step
-        const uint64_t pend = __ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) != 0 : leaf0 != 0);
+        const uint64_t pend = ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) != 0 : leaf0 != 0);
         if (pend != 0) {
             if (COUNT) ++w_leaf;
             if constexpr (WIDE) {
@@ -659,7 +667,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                             leaf3 = 0;
                         }
                     }
-                } while (__ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
+                } while (ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
             } else do {
                 if (leaf0 != 0) {
                     const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
@@ -668,7 +676,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     leaf2 = 0;
                     if (stop) node = -1;
                 }
-            } while (__ballot(leaf0 != 0) != 0);
+            } while (ballot(leaf0 != 0) != 0);
         }
 
     }
