@@ -100,6 +100,62 @@ __device__ inline uint32_t lanes_below(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// The four-way walk of a single mesh (boolean and counting modes) reads
+// the records of the top three levels (the entry record, its internal
+// children and theirs: at most 21) from a copy in LDS.  Every walk starts
+// there, so these are the most visited records; served by LDS they leave
+// the vector-memory path, which the walk keeps busy.  References at or above kTopRef name a record of the
+// copy (internal references stay below 2^27).
+constexpr int kTopNodes = 21;
+constexpr int32_t kTopRef = 0x40000000;
+
+// Modes that walk with the top copy: the boolean and counting walks.  The
+// first-hit and all-hits walks go deeper on large meshes, and there the
+// LDS entries the copy takes from the stack cost more than it saves.
+constexpr bool top_copy(uint32_t mode) { return !(mode & (M_ALL | M_FIRST)); }
+
+__device__ inline bool inner_ref(int32_t r) { return r >= 0 && r != kEmptySlot; }
+__device__ inline int32_t ref_at(const int4 &c, int k) { return k == 0 ? c.x : (k == 1 ? c.y : (k == 2 ? c.z : c.w)); }
+
+// Lane l < kTopNodes of the block's first wave fills slot l of the copy:
+// slot 0 the entry record, slots 1..4 its children, slot 5 + 4k + j child j
+// of slot 1 + k.  A slot whose record does not exist stays unused: no
+// reference names it.  References between copied records are rewritten to
+// kTopRef + slot.
+__device__ inline void load_top(const Node4 *__restrict__ nodes4, int32_t entry, uint4 *top, int l)
+{
+    if (l >= kTopNodes || entry < 0) return;
+    const int4 *rec = reinterpret_cast<const int4 *>(nodes4);
+    const int4 c0 = rec[4 * (int64_t)entry + 3];
+    int32_t id = -1;
+    if (l == 0) {
+        id = entry;
+    } else if (l < 5) {
+        const int32_t r = ref_at(c0, l - 1);
+        id = inner_ref(r) ? r : -1;
+    } else {
+        const int32_t p = ref_at(c0, (l - 5) >> 2);
+        if (inner_ref(p)) {
+            const int32_t r = ref_at(rec[4 * (int64_t)p + 3], (l - 5) & 3);
+            id = inner_ref(r) ? r : -1;
+        }
+    }
+    if (id < 0) return;
+    const uint4 *q = reinterpret_cast<const uint4 *>(nodes4 + id);
+    int4 c = rec[4 * (int64_t)id + 3];
+    if (l < 5) {
+        const int32_t base = kTopRef + (l == 0 ? 1 : 5 + 4 * (l - 1));
+        c.x = inner_ref(c.x) ? base : c.x;
+        c.y = inner_ref(c.y) ? base + 1 : c.y;
+        c.z = inner_ref(c.z) ? base + 2 : c.z;
+        c.w = inner_ref(c.w) ? base + 3 : c.w;
+    }
+    top[4 * l] = q[0];
+    top[4 * l + 1] = q[1];
+    top[4 * l + 2] = q[2];
+    top[4 * l + 3] = make_uint4((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w);
+}
+
 // Per-lane query state for the segment it currently owns.
 // All-hits capacities up to this many keep the hit list in registers.
 constexpr int kRegSlots = 4;
@@ -349,6 +405,12 @@ template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE
 __global__ __launch_bounds__(256) void k_query(QArgs a)
 {
     extern __shared__ int32_t lds_stack[];
+    constexpr bool TOP = WIDE && !BATCH && top_copy(MODE);
+    __shared__ uint4 top4[TOP ? 4 * kTopNodes : 4];
+    if constexpr (TOP) {
+        if (threadIdx.x < 64) load_top(a.nodes4, a.entry, top4, threadIdx.x);
+        __syncthreads();
+    }
     int32_t *const stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
     int32_t *const work = &a.scalars[kWorkNext];
@@ -430,7 +492,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 if (k >= 0) {
                     item = k;
                     int32_t i = k;
-                    int32_t entry = a.entry;
+                    int32_t entry = (TOP && a.entry >= 0) ? kTopRef : a.entry;
                     L.slot_base = (MODE & M_ALL) ? k * (int64_t)a.o.cap : 0;
                     L.spill_cap = 0;
                     if (SPILL) {
@@ -518,9 +580,22 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             }
             if constexpr (WIDE) {
               if (want) {
-                const uint4 *q = reinterpret_cast<const uint4 *>(a.nodes4 + node);
-                const uint4 P = q[0], Q = q[1], R = q[2];
-                const int4 C = reinterpret_cast<const int4 *>(a.nodes4 + node)[3];
+                uint4 P, Q, R;
+                int4 C;
+                if (TOP && node >= kTopRef) {
+                    const uint4 *t = top4 + 4 * (node - kTopRef);
+                    P = t[0];
+                    Q = t[1];
+                    R = t[2];
+                    const uint4 c = t[3];
+                    C = make_int4((int32_t)c.x, (int32_t)c.y, (int32_t)c.z, (int32_t)c.w);
+                } else {
+                    const uint4 *q = reinterpret_cast<const uint4 *>(a.nodes4 + node);
+                    P = q[0];
+                    Q = q[1];
+                    R = q[2];
+                    C = reinterpret_cast<const int4 *>(a.nodes4 + node)[3];
+                }
                 const float lim = ((MODE & M_FIRST) && !(MODE & M_FULL) ? L.tlim : 1.0f) * (1.0f + 0x1p-20f);
                 // grid steps, the corner's offset from the segment origin and
                 // the margin that makes the plane evaluation conservative
@@ -895,12 +970,13 @@ int full_depth(const rsi_bvh *h)
 // LDS part of the stack: the whole stack unless a smaller cap is set; the
 // four-way walk keeps 20 entries in LDS by default (its worst-case depth is
 // about 1.5x the binary one while typical walks stay far below it; 20
-// entries of 128 lanes leave room for eight waves per SIMD).
-int lds_part(const rsi_bvh *h)
+// entries of 128 lanes leave room for eight waves per SIMD), 17 when the
+// walk also holds the 1,344-byte copy of the top records (`top`).
+int lds_part(const rsi_bvh *h, bool top)
 {
     const int depth = full_depth(h);
     int cap = h->stack_cap;
-    if (cap <= 0 && h->width_built == 4) cap = 20;
+    if (cap <= 0 && h->width_built == 4) cap = top ? 17 : 20;
     return (cap > 0 && cap < depth) ? cap : depth;
 }
 
@@ -924,7 +1000,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.pool_ts = h->pool_ts;
     a.counters = h->counters;
     a.depth = full_depth(h);
-    a.lds_depth = lds_part(h);
+    a.lds_depth = lds_part(h, false);  // launches that differ set their own
     a.gstack = h->gstack;
     a.gstack_cap = h->gstack_cap;
     a.max_steps = (int32_t)(h->n_t + 1);
@@ -943,10 +1019,11 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
                         const QueryOut &o, hipStream_t s)
 {
     if (n_r == 0) return hipSuccess;
-    const int ld = lds_part(h);
+    const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n_r, o);
+    a.lds_depth = ld;
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, (mode & M_ALL) ? 1 : 0,
                        h->counting ? h->counters : nullptr);
     hipError_t e = h->counting ? dispatch<true>(mode, a, block, lds, s) : dispatch<false>(mode, a, block, lds, s);
@@ -960,7 +1037,7 @@ hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mod
     (void)mode;
     const int64_t n = h->last_ovf_segs;
     if (n == 0) return hipSuccess;
-    const int ld = lds_part(h);
+    const int ld = lds_part(h, false);
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n, o);
@@ -971,7 +1048,7 @@ hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mod
 hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s)
 {
     if (n_total == 0) return hipSuccess;
-    const int ld = lds_part(h);
+    const int ld = lds_part(h, false);
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QueryOut o = {};
@@ -992,7 +1069,7 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
 hipError_t ensure_gstack(rsi_bvh *h)
 {
     const int depth = full_depth(h);
-    const int ld = lds_part(h);
+    const int ld = lds_part(h, true);  // the smaller LDS part: the longer tail
     if (ld >= depth) return hipSuccess;
     int dev = 0, n_cu = 0, max_threads = 0;
     hipError_t e = hipGetDevice(&dev);

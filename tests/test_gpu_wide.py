@@ -82,6 +82,33 @@ def test_wide_equals_binary_closed_sphere_with_spill_and_small_stack():
     mesh.close()
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 9, 16, 17, 21, 22, 64, 85, 86, 300])
+def test_wide_small_meshes(n):
+    """Triangle soups small enough that the top three four-way levels (the
+    records the walk reads from its LDS copy) hold leaves, empty slots and
+    missing records: both walks agree bit for bit and match the oracle."""
+    rng = np.random.default_rng(1000 + n)
+    c = rng.uniform(0.0, 1.0, size=(n, 1, 3))
+    V = (c + rng.normal(0.0, 0.15, size=(n, 3, 3))).reshape(-1, 3).astype(np.float32)
+    T = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    S, E = wl.segments_in_box(rng, V.min(0), V.max(0), 3000, scale=1.5)
+    mesh = rsi.Mesh(_t(V), _t(T, torch.int32))
+    r2, r4 = _both(mesh, _t(S), _t(E), "bool|first|all", cap=4)
+    _equal(r2, r4, f"n={n}")
+    ref = parity.oracle_reference(V, T, S, E, cap=4)
+    rep = parity.compare(ref, r4, {"bool", "first", "all"}, cap=4)
+    parity.assert_parity(rep)
+    # the boolean and counting walks on their own (they take the LDS copy)
+    ok = ref["degenerate"] == 0
+    for mode, key in (("bool", "hit"), ("count", "count")):
+        a2, a4 = _both(mesh, _t(S), _t(E), mode)
+        _equal(a2, a4, f"n={n} {mode}")
+        got = a4[key].cpu().numpy().astype(np.int64)
+        want = ref["count"] if mode == "count" else (ref["count"] > 0)
+        assert np.array_equal(got[ok], want[ok].astype(np.int64)), (n, mode)
+    mesh.close()
+
+
 def test_wide_oracle_parity_config1_full():
     w = wl.config1()
     mesh = rsi.Mesh(_t(w.V), _t(w.T, torch.int32), leaf_size=4)
