@@ -13,18 +13,22 @@
 // A lane walks the tree from the entry node with a stack laid out
 // [depth][lane] in LDS so a wave's pushes and pops hit distinct banks; its
 // depth is sized from the tree height, so it cannot overflow, and entries
-// beyond the LDS part (the four-way walk keeps 20 there by default) go to a
-// per-lane tail in device memory.  Each node step loads one 64-byte record.
+// beyond the LDS part (the four-way walk keeps 20 there by default, 17 when
+// it holds the top copy below) go to a per-lane tail in device memory.
+// Each node step loads one 64-byte record; the boolean and counting walks of
+// a single mesh read the records of the top three four-way levels from a
+// per-workgroup copy in LDS instead.
 // The default four-way walk (Node4) tests the segment against the four
 // quantised boxes of the node's grandchildren, keeps the touched leaf
 // children as pending, descends into the nearest touched internal child and
 // pushes the others; the binary walk (Node, branching 2) tests the two exact
 // child boxes, keeps walking past one pending leaf and descends into the
 // nearer touched child.  Pending leaves are tested once few lanes can still
-// take a node step, so the triangle test runs with most lanes active.  The paper's bounded candidate list with resume
-// (Section 3.2) is therefore not needed: candidates are tested soon after
-// they are found, and the bounded buffers left are the stack and the
-// all-hits slots, whose overflow is detected and retried into a pool.
+// take a node step, so the triangle test runs with most lanes active.  The
+// paper's bounded candidate list with resume (Section 3.2) is therefore not
+// needed: candidates are tested soon after they are found, and the bounded
+// buffers left are the stack and the all-hits slots, whose overflow is
+// detected and retried into a pool.
 //
 // Modes
 //   bool only   stop at the first crossing (any-hit, Section 3.2)
