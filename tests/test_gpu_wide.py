@@ -79,6 +79,15 @@ def test_wide_equals_binary_closed_sphere_with_spill_and_small_stack():
     r4s = mesh.query(S, E, "all|first|bool", capacity=2)
     torch.cuda.synchronize()
     _equal(r2, r4s, "sphere-small-stack")
+    # the boolean and counting walks (which also read the LDS copy of the top
+    # records) with the same four-entry LDS stack
+    for mode in ("bool", "count"):
+        mesh.set_opts(branching=2, stack_depth=0)
+        b2 = mesh.query(S, E, mode)
+        mesh.set_opts(branching=4, stack_depth=4)
+        b4 = mesh.query(S, E, mode)
+        torch.cuda.synchronize()
+        _equal(b2, b4, f"sphere-small-stack-{mode}")
     mesh.close()
 
 
