@@ -13,10 +13,8 @@
 // One lane per segment.  (t, u, v) and the solve are recomputed in FP64 from
 // the FP32 inputs; dS and dE are stores, the nine vertex components go to dV
 // by FP32 atomic adds (a vertex is shared by the hits of many segments).
-// Device-wide atomics dominate the cost, so large batches take two passes:
-// the first, in segment order, solves every hit and keeps its nine vertex
-// contributions in a record; the records are then visited in the order of
-// the Morton position of the hit triangle (the build's radix sort), and
+// Device-wide atomics dominate the cost, so large batches are first ordered
+// by the Morton position of the hit triangle (the build's radix sort) and
 // each wave sums the contributions of its runs of equal triangles before
 // adding them.  A miss (tri < 0) contributes nothing and gets zero dS, dE.
 #include <hip/hip_runtime.h>
@@ -157,54 +155,42 @@ __global__ __launch_bounds__(256) void k_first_hit_adjoint(AdjArgs a)
     store_ends(a, i, o);
 }
 
-// First pass, one lane per segment in input order (every access but the
-// vertex gather coalesced): the adjoint of the segment, its dS and dE, and a
-// 48-byte record of its nine vertex contributions and hit triangle (-1 when
-// there is none or the solve was singular: the contributions are zero
-// then); plus the hit-order sort pair: key = the sorted (Morton) position
-// of the hit triangle, misses last; value = the segment index.
-__global__ __launch_bounds__(256) void k_adj_local(AdjArgs a, const int32_t *__restrict__ rank,
-                                                   float4 *__restrict__ rec, uint64_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ vals)
+// Hit-order keys: the sorted (Morton) position of the hit triangle, misses
+// last; values: segment indices.
+__global__ __launch_bounds__(256) void k_adj_keys(const int32_t *__restrict__ tri, int64_t n_r,
+                                                  const int32_t *__restrict__ rank, int32_t n_t,
+                                                  uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n_r) return;
-    const AdjOut o = adjoint_of(a, i);
-    store_ends(a, i, o);
-    const int32_t j = a.tri[i];
-    rec[3 * i] = make_float4(o.wv[0], o.wv[1], o.wv[2], o.wv[3]);
-    rec[3 * i + 1] = make_float4(o.wv[4], o.wv[5], o.wv[6], o.wv[7]);
-    rec[3 * i + 2] = make_float4(o.wv[8], __int_as_float(o.tri_ok ? j : -1), 0.0f, 0.0f);
-    keys[i] = o.tri_ok ? (uint64_t)rank[j] : (uint64_t)a.n_t;
+    if (i >= n_r) return;
+    const int32_t j = tri[i];
+    keys[i] = (j >= 0 && j < n_t) ? (uint64_t)rank[j] : (uint64_t)n_t;
     vals[i] = (uint32_t)i;
 }
 
-// Second pass, segments in hit-triangle order: lanes of a wave that hit
-// the same triangle form runs; a segmented sum over each run (shuffles up
-// the wave) leaves the run's total in its last lane, which alone adds it
-// to dV.  Consecutive segments share a triangle about N_r / N_t times, so
-// this cuts the device-wide atomics by about that factor; the records are
-// the only data read out of order.
-__global__ __launch_bounds__(256) void k_adj_scatter(AdjArgs a, const float4 *__restrict__ rec,
-                                                     const uint64_t *__restrict__ keys,
-                                                     const uint32_t *__restrict__ vals)
+// Segments in hit-triangle order: lanes of a wave that hit the same
+// triangle form runs; a segmented sum over each run (shuffles up the wave)
+// leaves the run's total in its last lane, which alone adds it to dV.
+// Consecutive segments share a triangle about N_r / N_t times, so this cuts
+// the device-wide atomics by about that factor.
+__global__ __launch_bounds__(256) void k_first_hit_adjoint_sorted(AdjArgs a, const uint64_t *__restrict__ keys,
+                                                                  const uint32_t *__restrict__ vals)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = k < a.n_r;
+    const int64_t i = in ? (int64_t)vals[k] : 0;
     // lanes past the end get a key no real segment has
     const uint64_t key = in ? keys[k] : ~0ull;
-    float acc[9];
-    int32_t j = -1;
+    AdjOut o;
     if (in) {
-        const int64_t i = (int64_t)vals[k];
-        const float4 r0 = rec[3 * i], r1 = rec[3 * i + 1], r2 = rec[3 * i + 2];
-        acc[0] = r0.x; acc[1] = r0.y; acc[2] = r0.z; acc[3] = r0.w;
-        acc[4] = r1.x; acc[5] = r1.y; acc[6] = r1.z; acc[7] = r1.w;
-        acc[8] = r2.x;
-        j = __float_as_int(r2.y);
+        o = adjoint_of(a, i);
+        store_ends(a, i, o);
     } else {
-        for (int q = 0; q < 9; ++q) acc[q] = 0.0f;
+        for (int q = 0; q < 9; ++q) o.wv[q] = 0.0f;
+        o.tri_ok = o.valid = false;
     }
+    float acc[9];
+    for (int q = 0; q < 9; ++q) acc[q] = o.wv[q];
     const int lane = (int)__lane_id();
     const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
     for (int off = 1; off < 64; off <<= 1) {
@@ -217,15 +203,9 @@ __global__ __launch_bounds__(256) void k_adj_scatter(AdjArgs a, const float4 *__
     }
     const uint32_t nlo = __shfl_down(klo, 1, 64), nhi = __shfl_down(khi, 1, 64);
     const bool last = lane == 63 || nlo != klo || nhi != khi;
-    // every lane of a run hit the same triangle (its indices were checked in
-    // the first pass), so the last lane's serves the run
-    if (in && j >= 0 && last) {
-        AdjOut o;
-        o.ia = a.T[3 * (int64_t)j];
-        o.ib = a.T[3 * (int64_t)j + 1];
-        o.ic = a.T[3 * (int64_t)j + 2];
-        add_vertices(a, o, acc);
-    }
+    // every lane of a run hit the same triangle, so the last lane's indices
+    // serve the run (its own solve may have been singular)
+    if (in && o.tri_ok && last) add_vertices(a, o, acc);
 }
 
 }  // namespace
@@ -252,14 +232,6 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
             return e;
         h->seg_key_cap = n_r;
     }
-    if (h->adj_rec_cap < n_r) {
-        if (h->adj_rec) (void)hipFree(h->adj_rec);
-        h->adj_rec = nullptr;
-        h->adj_rec_cap = 0;
-        if ((e = hipMalloc(reinterpret_cast<void **>(&h->adj_rec), 3 * sizeof(float4) * (size_t)n_r)) != hipSuccess)
-            return e;
-        h->adj_rec_cap = n_r;
-    }
     if (h->adj_val_cap < n_r) {
         if (h->adj_vals) (void)hipFree(h->adj_vals);
         h->adj_vals = nullptr;
@@ -268,14 +240,14 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
             return e;
         h->adj_val_cap = n_r;
     }
-    hipLaunchKernelGGL(k_adj_local, dim3(grid), dim3(blk), 0, s, a, h->rank, h->adj_rec, h->seg_keys,
+    hipLaunchKernelGGL(k_adj_keys, dim3(grid), dim3(blk), 0, s, tri, n_r, h->rank, (int32_t)h->n_t, h->seg_keys,
                        h->adj_vals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int bits = 1;
     while (bits < 63 && ((int64_t)1 << bits) <= h->n_t) ++bits;  // keys in [0, n_t]
     e = radix_sort_pairs(h->seg_keys, h->adj_vals, n_r, bits, h->seg_sort, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_scatter, dim3(grid), dim3(blk), 0, s, a, h->adj_rec, h->seg_keys, h->adj_vals);
+    hipLaunchKernelGGL(k_first_hit_adjoint_sorted, dim3(grid), dim3(blk), 0, s, a, h->seg_keys, h->adj_vals);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ void free_handle_memory(rsi_bvh *h)
 {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    void *ptrs[] = {h->rank, h->adj_vals, h->adj_rec, h->seg_keys, h->compact_counts, h->nodes4, h->aux_E, h->aux_count, h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
+    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->compact_counts, h->nodes4, h->aux_E, h->aux_count, h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
                     h->arrive, h->heights, h->climb, h->split_prefix, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
                     h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off, h->vert_off, h->mesh_bounds,
                     h->mesh_height, h->mesh_root, h->mesh_entry, h->bt.seg_off, h->bt.S, h->bt.E, h->bt.hit,

@@ -135,8 +135,6 @@ struct rsi_bvh {
     int64_t seg_key_cap = 0;
     uint32_t *adj_vals = nullptr;
     int64_t adj_val_cap = 0;
-    float4 *adj_rec = nullptr;     // the adjoint's per-segment records (3 x float4 each)
-    int64_t adj_rec_cap = 0;
     rsi::SortScratch seg_sort;
 
     // stream compaction: per-block counts and their scan (+ total)
