@@ -66,6 +66,13 @@ def test_adjoint_matches_oracle_random_upstream(n_half):
     rV, rS, rE, rabs = oracle.first_hit_grad(V, T, S, E, tri_in, ref["first_tuv"], g_t, g_uv, g_p,
                                              with_abs=True)
     _check_dv(dV.cpu().numpy().astype(np.float64), rV, rabs)
+    # a second call on the same inputs (the handle's scratch now reused)
+    # gives the same gradient up to the order of the atomic adds
+    dV2, dS2, dE2 = mesh.first_hit_backward(_t(V), _t(S), _t(E), _t(tri_in, torch.int32), _t(g_t), _t(g_uv),
+                                            _t(g_p))
+    torch.cuda.synchronize()
+    _check_dv(dV2.cpu().numpy().astype(np.float64), rV, rabs)
+    assert torch.equal(dS, dS2) and torch.equal(dE, dE2)
     _check_seg(dS.cpu().numpy()[ok].astype(np.float64), rS[ok])
     _check_seg(dE.cpu().numpy()[ok].astype(np.float64), rE[ok])
     assert not dS.cpu().numpy()[~ok].any() and not dE.cpu().numpy()[~ok].any()
