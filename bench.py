@@ -13,15 +13,18 @@ HBM before timing starts.  `value` = segments per second of that step.
 
 Also reported: the query alone in boolean and all-hits (capacity 4) modes,
 the build alone, the dominant kernel's average duration (HIP events on the
-launch stream) with its ALU roofline, and the FP64 oracle timed on the host's
-cores on a bounded sample (a baseline, not the target).
+launch stream) against the FP32 roofline (algorithmic FP32 operations of the
+launch: 25 per child-box slab test and 50 per triangle test), its HBM traffic
+and L2 hit rate from the committed counter profiles, the other workloads
+(1,922-triangle heightfield, 499,280-triangle closed sphere with all hits,
+differentiable first hit on 199,712 triangles, 64 meshes in one graph) and
+the FP64 oracle timed on the host's cores (a baseline, not the target).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
@@ -31,24 +34,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU lane-operations per unit of work, counted from the kernel source
-# (rsi_device.h, query.hip): one slab test of an exact box (binary walk), one
-# of a quantised box (four-way walk: each of the six planes is decoded with a
-# byte conversion and an fma before the multiply) plus the per-node set-up
-# of the four-way walk (exponent decode, corner offset, margin), and one
-# Moller-Trumbore test.
-OPS_PER_BOX_TEST = {2: 26, 4: 32}
-OPS_PER_NODE = {2: 0, 4: 18}
-OPS_PER_TRI_TEST = 45
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one VALU lane-op per lane per clock;
-# packed FP32 is not used)
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic FP32 work per unit: a slab test of one child box (6 fma-class
+# plane parameters counted as 2 ops each, 6 min/max, 4 reductions and
+# clamps, 1 compare = 25) and a Moller-Trumbore triangle test (about 44 flops,
+# 1 reciprocal, 6 compares = 50).  Counts of both come from the counting
+# variant of the same launch.
+OPS_PER_BOX_TEST = 25
+OPS_PER_TRI_TEST = 50
+# MI355X vector FP32: 157.3 TFLOP/s with packed (dual-issue) FP32, 78.6 without
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_TFLOPS_UNPACKED = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# Paper figures quoted as context (Section 1; Tables 1 and 3): PyVista on 8
+# logical CPU processors, ~60 s for 10M rays against ~30k triangles; the
+# CUDA LBVH on a GTX Titan X, 0.463 s (v2.1) and 0.228 s with sorted rays
+# (v2.2, sort excluded) for 10M rays against 29,284 triangles.
+PAPER_CONTEXT = {
+    "pyvista_cpu_s_10M_rays_30k_tris": 60.6,
+    "titan_x_v2_1_s_10M_rays_29284_tris": 0.463,
+    "titan_x_v2_2_sorted_rays_s": 0.228,
+}
 
 QUERY_SOURCES = ("paper_2209_02878_amd/csrc/query.hip", "paper_2209_02878_amd/csrc/rsi_device.h",
                  "paper_2209_02878_amd/csrc/rsi_host.h")
 TRAFFIC_PROFILE = "profiles/hbm_traffic_k_query_heightfield29768_10Mseg.md"
+L2_PROFILE = "profiles/l2_hit_rate_heightfield29768_10Mseg.md"
 
 
 def query_sources_hash():
@@ -60,34 +71,86 @@ def query_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per boolean-query launch from the committed counter runs
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size), or
-    None when the kernel sources changed after those runs."""
+def _profile_record(path, tag):
+    """key=value pairs of the `tag:` line of a committed profile summary, or
+    None when it is missing or was taken from other query sources."""
     import re
     try:
-        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as f:
+        with open(os.path.join(ROOT, path)) as f:
             text = f.read()
     except OSError:
         return None
-    m = re.search(r"^traffic-record: (.*)$", text, re.M)
+    m = re.search(rf"^{tag}: (.*)$", text, re.M)
     if not m:
         return None
     rec = dict(kv.split("=", 1) for kv in m.group(1).split())
     if rec.get("sources") != query_sources_hash():
         return None
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per boolean-query launch from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy of known size)."""
+    rec = _profile_record(TRAFFIC_PROFILE, "traffic-record")
+    if rec is None:
+        return None
     return (float(rec["fetch_kib"]) * float(rec["fetch_scale"]) +
             float(rec["write_kib"]) * float(rec["write_scale"])) * 1024.0
+
+
+def measured_l2():
+    """L2 hit rates (TCC_HIT / (TCC_HIT + TCC_MISS)) per query kernel from the
+    committed counter run."""
+    rec = _profile_record(L2_PROFILE, "l2-record")
+    if rec is None:
+        return None
+    return {k: float(v) for k, v in rec.items() if k != "sources"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S2, E2):
+def degenerate_fraction(w, n_pick, seed):
+    """Near-degenerate segments (the oracle's classifier, delta = 1e-6 of the
+    mesh diagonal) in a seeded sample of a workload."""
+    import oracle
+    idx = np.arange(w.n_r) if n_pick >= w.n_r else np.sort(
+        np.random.default_rng(seed).choice(w.n_r, n_pick, replace=False))
+    L = float(np.linalg.norm(w.V.astype(np.float64).max(0) - w.V.astype(np.float64).min(0)))
+    d = oracle.degenerate(w.V, w.T, w.S[idx], w.E[idx], 1e-6 * L)
+    n = int((d != 0).sum())
+    return {"sample": int(idx.size), "near_degenerate": n, "fraction": round(n / idx.size, 6)}
+
+
+def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2):
     """The other configurations, reported beside the headline."""
     out = {}
     med = lambda xs: float(np.median(xs))
+
+    # the 1,922-triangle heightfield, 100k segments, boolean
+    w = wl.config1()
+    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
+    m = rsi.Mesh(V, T)
+    o = m.alloc_outputs(w.n_r, "bool")
+    q = time_events(lambda: m.query_into(S, E, "bool", o), 20)
+    out["heightfield_1922tri_100kseg_bool"] = {"query_ms": round(med(q), 4),
+                                               "msegments_per_s": round(w.n_r / med(q) / 1e3, 2)}
+    log(f"1,922-triangle heightfield: bool {med(q):.4f} ms")
+    m.close()
 
     # the headline mesh and segments: the binary walk, and Morton-ordered segments
     m = rsi.Mesh(V2, T2)
@@ -119,18 +182,20 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     t0 = time.time()
     w = wl.config3()
     log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
-    V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
-    S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
+    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
     m = rsi.Mesh(V, T)
     o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
     b = time_events(lambda: m.rebuild(V, T), 5)
     q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
-    nspill = rsi.rsi_spill_info(m.handle)[0]
+    st = m.stats()
+    ob = m.alloc_outputs(w.n_r, "bool")
+    qb = time_events(lambda: m.query_into(S, E, "bool", ob), 5)
     out["sphere_499280tri_10Mseg_all_first_k4"] = {
-        "options": {k: m.opts()[k] for k in ("branching", "stack_depth")},
         "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
-        "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "overflowed_segments": int(nspill)}
-    log(f"sphere all|first: query {med(q):.3f} ms, build {med(b):.3f} ms, spill {nspill}")
+        "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "query_bool_ms": round(med(qb), 4),
+        "overflowed_segments": int(st["overflow_segments"]), "spilled_crossings": int(st["overflow_crossings"]),
+        "deep_pass_segments": int(st["deep_segments"])}
+    log(f"sphere all|first: query {med(q):.3f} ms, bool {med(qb):.3f} ms, build {med(b):.3f} ms, stats {st}")
     # odd-parity inside test of 10M points against the same closed surface
     P = torch.from_numpy(wl.inside_points(w.V, w.n_r, wl.seed_for(6, 1))).to(dev)
     ins = torch.empty(w.n_r, dtype=torch.uint8, device=dev)
@@ -142,13 +207,12 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
         "inside_fraction": round(float(ins.float().mean().item()), 5)}
     log(f"inside test: {med(qi):.3f} ms for {w.n_r} points")
     m.close()
-    del V, T, S, E, o, P, ins, cnt, ends
+    del V, T, S, E, o, ob, P, ins, cnt, ends
 
     # differentiable first hit: 199,712-triangle heightfield, 4M segments
     w = wl.config4()
     Vg, _ = wl.config4_target()
-    V, T = torch.from_numpy(w.V).to(dev), torch.from_numpy(w.T).to(dev)
-    S, E = torch.from_numpy(w.S).to(dev), torch.from_numpy(w.E).to(dev)
+    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
     n = 317
     gz = torch.from_numpy(Vg[:, 2].astype(np.float32)).to(dev)
     X = torch.clamp(S[:, 0] * (n - 1), 0, n - 1 - 1e-6)
@@ -176,6 +240,7 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     fb = time_events(fwd_bwd, 10)
     out["heightfield_199712tri_4Mseg_first_hit_grad"] = {
         "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
+        "backward_ms": round(med(fb) - med(f), 4),
         "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
         "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
         "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
@@ -183,8 +248,10 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     m.close()
     del V, T, S, E, Vp
 
-    # 64 meshes: one captured graph (rebuild all + one batched boolean query)
-    # against 64 sequential plain calls (rebuild + query per mesh)
+    # 64 meshes: one captured graph (rebuild all + one batched query) per mode,
+    # with options chosen by the autotuner on this batch, against 64
+    # sequential plain calls (rebuild + query per mesh)
+    from paper_2209_02878_amd import tune
     t0 = time.time()
     ws = wl.config5()
     log(f"64-mesh batch generated in {time.time() - t0:.1f}s: {sum(x.n_t for x in ws)} triangles, "
@@ -192,31 +259,80 @@ def extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w2, V2, T2, S
     meshes = [(torch.from_numpy(x.V).to(dev), torch.from_numpy(x.T).to(dev)) for x in ws]
     segs = [(torch.from_numpy(x.S).to(dev), torch.from_numpy(x.E).to(dev)) for x in ws]
     singles = [rsi.Mesh(Vm, Tm) for Vm, Tm in meshes]
-    souts = [sm.alloc_outputs(Sm.shape[0], "bool") for sm, (Sm, _) in zip(singles, segs)]
-
-    def sequential():
-        for sm, (Vm, Tm), (Sm, Em), so in zip(singles, meshes, segs, souts):
-            sm.rebuild(Vm, Tm)
-            sm.query_into(Sm, Em, "bool", so)
-
-    bt = rsi.Batch(meshes)
-    bouts = bt.alloc_outputs(segs, "bool")
-    bt.capture(segs, "bool", bouts, rebuild=True)
-    seq = time_events(sequential, 3)
-    rep = time_events(bt.replay, 10)
-    torch.cuda.synchronize()
-    same = all(torch.equal(bo["hit"], so["hit"]) for bo, so in zip(bouts, souts))
     ntot = sum(x.n_r for x in ws)
-    out["batch_64_meshes_bool"] = {
-        "n_t": int(sum(x.n_t for x in ws)), "n_r": int(ntot),
-        "graph_replay_ms": round(med(rep), 4), "sequential_64_calls_ms": round(med(seq), 4),
-        "graph_msegments_per_s": round(ntot / med(rep) / 1e3, 2),
-        "speedup_vs_sequential": round(med(seq) / med(rep), 3), "identical_to_sequential": bool(same)}
-    log(f"batch: graph {med(rep):.3f} ms vs sequential {med(seq):.3f} ms, identical={same}")
+    bt = rsi.Batch(meshes)
+    for mode in ("bool", "first"):
+        t0 = time.time()
+        opts = tune.autotune(bt, segs, mode=mode, kind="batch64", n_t=sum(x.n_t for x in ws), n_r=ntot,
+                             cache_path=None)
+        t_tune = time.time() - t0
+        for sm in singles:
+            sm.set_opts(**opts)  # a new leaf size applies at the rebuild of each sequential step
+        souts = [sm.alloc_outputs(Sm.shape[0], mode) for sm, (Sm, _) in zip(singles, segs)]
+
+        def sequential():
+            for sm, (Vm, Tm), (Sm, Em), so in zip(singles, meshes, segs, souts):
+                sm.rebuild(Vm, Tm)
+                sm.query_into(Sm, Em, mode, so)
+
+        bouts = bt.alloc_outputs(segs, mode)
+        bt.capture(segs, mode, bouts, rebuild=True)
+        seq = time_events(sequential, 3)
+        rep = time_events(bt.replay, 10)
+        torch.cuda.synchronize()
+        same = all(torch.equal(bo[key], so[key]) for bo, so in zip(bouts, souts) for key in so)
+        out[f"batch_64_meshes_{mode}"] = {
+            "n_t": int(sum(x.n_t for x in ws)), "n_r": int(ntot), "tuned_options": opts,
+            "autotune_s": round(t_tune, 2),
+            "graph_replay_ms": round(med(rep), 4), "sequential_64_calls_ms": round(med(seq), 4),
+            "graph_msegments_per_s": round(ntot / med(rep) / 1e3, 2),
+            "speedup_vs_sequential": round(med(seq) / med(rep), 3), "identical_to_sequential": bool(same)}
+        log(f"batch {mode}: tuned {opts} in {t_tune:.1f}s; graph {med(rep):.3f} ms vs sequential "
+            f"{med(seq):.3f} ms, identical={same}")
+        del bouts, souts
     bt.close()
     for sm in singles:
         sm.close()
     return out
+
+
+def cpu_baseline(w, threads_probe, seconds, log):
+    """The FP64 oracle (test infrastructure) on a bounded prefix of the
+    headline workload, on the host's cores; plus the 1,922-triangle workload
+    in full with all threads and with one."""
+    import oracle
+    from paper_2209_02878_amd import workloads as wl
+    threads = oracle.max_threads()
+    probe = 100_000
+    t1 = time.perf_counter()
+    oracle.query(w.V, w.T, w.S[:probe], w.E[:probe])
+    dt = time.perf_counter() - t1
+    n_s = int(min(w.n_r, max(probe, probe * seconds / max(dt, 1e-6))))
+    t1 = time.perf_counter()
+    oracle.query(w.V, w.T, w.S[:n_s], w.E[:n_s])
+    dt = time.perf_counter() - t1
+    rate = n_s / dt
+    w1 = wl.config1()
+    t1 = time.perf_counter()
+    oracle.query(w1.V, w1.T, w1.S, w1.E)
+    c1_all = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    oracle.query(w1.V, w1.T, w1.S, w1.E, threads=1)
+    c1_one = time.perf_counter() - t1
+    return {
+        "value": round(rate / 1e6, 5),
+        "unit": "Msegments/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {n_s} of the 10M segments against all 29,768 triangles, FP64 brute force "
+                  f"over every pair (box-overlap check, then the exact test), {dt:.1f} s",
+        "cpu_model": cpu_model(),
+        "pair_tests_per_s": round(n_s * w.n_t / dt, 1),
+        "extrapolated_full_10M_s": round(w.n_r / rate, 2),
+        "heightfield_1922tri_100kseg_full": {"threads": threads, "s": round(c1_all, 3), "one_thread_s": round(c1_one, 3),
+                                             "pair_tests_per_s_one_thread": round(w1.n_r * w1.n_t / c1_one, 1)},
+        "paper_context": PAPER_CONTEXT,
+    }
 
 
 def main():
@@ -277,7 +393,7 @@ def main():
     value = w.n_r / (ms_per_step / 1e3) / 1e6
     log(f"step (rebuild + bool query): {ms_per_step:.3f} ms -> {value:.1f} Msegments/s")
 
-    # ---- dominant kernel: the boolean query launch, timed with HIP events
+    # ---- the query launches, timed with HIP events on the launch stream
     def time_events(fn, reps):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
         for a, b in evs:
@@ -290,26 +406,28 @@ def main():
     reps = max(args.steps, 10)
     q_bool = time_events(lambda: mesh.query_into(S, E, "bool", out_b), reps)
     q_all = time_events(lambda: mesh.query_into(S, E, "all", out_a, capacity=4), max(5, reps // 2))
+    st_all = mesh.stats()
     b_only = time_events(lambda: mesh.rebuild(V, T), reps)
     kb = float(np.mean(q_bool))
-    log(f"bool query kernel: mean {kb:.3f} ms, median {np.median(q_bool):.3f} ms; "
-        f"all-hits query: median {np.median(q_all):.3f} ms; rebuild: median {np.median(b_only):.3f} ms")
+    log(f"bool query: mean {kb:.3f} ms, median {np.median(q_bool):.3f} ms; "
+        f"all-hits query: median {np.median(q_all):.3f} ms ({st_all}); rebuild: median {np.median(b_only):.3f} ms")
 
     # ---- algorithmic work of that launch, from the counting variant (untimed)
     mesh.set_counting(True)
     mesh.query_into(S, E, "bool", out_b)
     torch.cuda.synchronize()
     cnt = mesh.counters()
+    st_bool = mesh.stats()
     mesh.set_counting(False)
-    br = mesh.opts()["branching"]
-    ops = (OPS_PER_BOX_TEST[br] * cnt["box_tests"] + OPS_PER_NODE[br] * cnt["node_visits"] +
-           OPS_PER_TRI_TEST * cnt["tri_tests"])
-    achieved_tops = ops / (kb / 1e3) / 1e12
+    flops = OPS_PER_BOX_TEST * cnt["box_tests"] + OPS_PER_TRI_TEST * cnt["tri_tests"]
+    achieved = flops / (kb / 1e3) / 1e12
     hits = int(out_b["hit"].sum().item())
-    log(f"counters: {cnt}; hit fraction {hits / w.n_r:.4f}")
+    lane_visit_share = cnt["node_visits"] / max(1, 64 * cnt["wave_node_steps"])
+    log(f"counters: {cnt}; hit fraction {hits / w.n_r:.4f}; lane-visit share {lane_visit_share:.3f}")
 
     traffic = measured_traffic()
     traffic = None if traffic is None else round(traffic)
+    l2 = measured_l2()
     rec = {
         "metric": "Msegments/s vs 30k-tri mesh (bool & all-hits); fwd+bwd vs fwd at 1e-5 rel err",
         "value": round(value, 3),
@@ -334,20 +452,28 @@ def main():
         "query_bool_msegments_per_s": round(w.n_r / np.median(q_bool) / 1e3, 2),
         "query_all_hits_k4_ms": round(float(np.median(q_all)), 4),
         "query_all_hits_k4_msegments_per_s": round(w.n_r / np.median(q_all) / 1e3, 2),
+        "all_hits_over_bool_time": round(float(np.median(q_all) / np.median(q_bool)), 3),
+        "all_hits_overflowed_segments": int(st_all["overflow_segments"]),
+        "deep_pass_segments_bool": int(st_bool["deep_segments"]),
         "rebuild_ms": round(float(np.median(b_only)), 4),
         "hit_fraction": round(hits / w.n_r, 5),
         "work_per_segment": {"node_visits": cnt["node_visits"] / w.n_r, "box_tests": cnt["box_tests"] / w.n_r,
                              "tri_tests": cnt["tri_tests"] / w.n_r},
+        "lane_visit_share": round(lane_visit_share, 4),
         "roofline": {
             "bound": "alu",
-            "kernel": "k_query<bool>",
-            "achieved": round(achieved_tops, 4),
-            "peak": round(PEAK_VALU_TOPS, 3),
-            "unit": "Tops/s",
-            "frac": round(achieved_tops / PEAK_VALU_TOPS, 5),
+            "kernel": "k_query<bool> (quantised four-way walk)",
+            "achieved": round(achieved, 4),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 5),
+            "frac_of_unpacked_fp32_78p6": round(achieved / PEAK_FP32_TFLOPS_UNPACKED, 5),
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "ops_per_launch": int(ops),
+            "hbm_frac": None if traffic is None else round(traffic / (kb / 1e3) / 1e9 / PEAK_HBM_GBS, 5),
+            "l2_hit_rate": l2,
+            "fp32_ops_per_launch": int(flops),
+            "box_tests": int(cnt["box_tests"]), "tri_tests": int(cnt["tri_tests"]),
             "kernel_ms": round(kb, 4),
             "hbm_gbs_algorithmic": round(25.0 * w.n_r / (kb / 1e3) / 1e9, 2),
         },
@@ -363,29 +489,20 @@ def main():
 
     if not args.headline_only:
         mesh.close()
-        rec["extra"] = extra_workloads(torch, rsi, wl, dev, stream, time_events, log, w, V, T, S, E)
+        rec["extra"] = extra_workloads(torch, rsi, wl, dev, time_events, w, V, T, S, E)
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample, on the host cores
     if not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.max_threads()
-        probe = 100_000
-        t1 = time.perf_counter()
-        oracle.query(w.V, w.T, w.S[:probe], w.E[:probe])
-        dt = time.perf_counter() - t1
-        n_s = int(min(w.n_r, max(probe, probe * args.cpu_seconds / max(dt, 1e-6))))
-        t1 = time.perf_counter()
-        oracle.query(w.V, w.T, w.S[:n_s], w.E[:n_s])
-        dt = time.perf_counter() - t1
-        rec["cpu_baseline"] = {
-            "value": round(n_s / dt / 1e6, 5),
-            "unit": "Msegments/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n_s} of the 10M segments against all 29,768 triangles, FP64 brute force "
-                      f"over every pair (box-overlap check, then the exact test), {dt:.1f} s",
-            "cpu": platform.processor() or platform.machine(),
+        # near-degenerate segments per workload (oracle classifier on samples)
+        t0 = time.time()
+        rec["near_degenerate"] = {
+            "heightfield_1922tri_100kseg": degenerate_fraction(wl.config1(), 100_000, 1),
+            "heightfield_29768tri_10Mseg": degenerate_fraction(w, 50_000, 2),
+            # (4,000 and 50,000 segments drawn by the same recipes as the full workloads)
+            "sphere_499280tri_10Mseg": degenerate_fraction(wl.config3(n_r=4_000), 4_000, 3),
+            "heightfield_199712tri_4Mseg": degenerate_fraction(wl.config4(n_r=50_000), 50_000, 4),
         }
+        log(f"near-degenerate samples ({time.time() - t0:.1f}s): {rec['near_degenerate']}")
+        rec["cpu_baseline"] = cpu_baseline(w, None, args.cpu_seconds, log)
         log(f"cpu baseline: {rec['cpu_baseline']}")
     if args.headline_only:
         mesh.close()

@@ -72,10 +72,11 @@ typedef struct {
                              of its lanes are done, 1..64 (default 32) */
     int32_t chunk;        /* segments a wave claims per global atomic, 64..2^20
                              (default: about eight chunks per resident wave, 64..4096) */
-    int32_t stack_depth;  /* traversal-stack entries kept in LDS per lane; deeper entries go to
-                             device memory.  The whole stack (tree height + 1) stays in LDS by
-                             default and for any value at or above it; a smaller value raises
-                             occupancy. 1..255 */
+    int32_t stack_depth;  /* traversal-stack entries per lane of the main pass, kept in LDS
+                             (default 20 on the four-way walk, 17 for its boolean and counting
+                             walks, 32 on the binary walk); a walk that needs more is finished
+                             by the deep pass, whose stack continues in device memory.  A smaller
+                             value raises occupancy. 1..255 */
     int32_t branching;    /* 4 (default): traverse the four-way view of the binary tree of
                              Section 3.1 (every node with its grandchildren as children, child
                              boxes quantised outward to 8 bits per plane, one 64-byte record
@@ -100,6 +101,16 @@ typedef struct {
     float *ts;         /*               [n_r*capacity] their t; +inf padding */
     int32_t capacity;  /* K >= 1 slots per segment for RSI_ALL_HITS */
     int32_t reserved;
+    /* RSI_ALL_HITS, optional.  Segments with more than `capacity` crossings
+     * keep their full lists, ordered by (t, id), in a spill pool: the
+     * caller's (spill_ids / spill_ts, spill_cap entries each) when given,
+     * else the library's (read it with rsi_spill_info / rsi_spill_read).
+     * spill_off, when given, gets per segment the offset of its list in the
+     * pool, or -1 (count <= capacity, or no room left in the pool). */
+    int64_t *spill_off;  /*             [n_r] */
+    int32_t *spill_ids;  /*             [spill_cap] */
+    float *spill_ts;     /*             [spill_cap] */
+    int64_t spill_cap;
 } rsi_outputs;
 
 /* Build a BVH over the mesh (paper Section 2: Morton-ordered binary radix
@@ -107,11 +118,14 @@ typedef struct {
  *   V  device, float32 [n_v*3] vertex coordinates x,y,z (Section 2.5 layout)
  *   T  device, int32   [n_t*3] vertex indices per triangle, each in [0, n_v)
  *   opts host, may be NULL.
- * The handle keeps its own packed copy of the geometry; V and T may be freed
- * afterwards.  Blocks until the build has finished on `stream` (to validate
- * the indices and size the traversal stack).
- * Errors: RSI_E_INVALID for n_v < 0, n_t < 0, n_t >= 2^27, a NULL pointer with
- * a nonzero size or an index outside [0, n_v); RSI_E_NOMEM; RSI_E_HIP.
+ * The handle keeps its own packed copy of the geometry; V and T are read
+ * by the enqueued build and may be freed once it has run.  Asynchronous on
+ * `stream`: nothing is read back (queries need no tree height on the host).
+ * Errors: RSI_E_INVALID for n_v < 0, n_t < 0, n_t >= 2^27 or a NULL pointer
+ * with a nonzero size; RSI_E_NOMEM; RSI_E_HIP.  A triangle index outside
+ * [0, n_v) is found by the device and reported by rsi_query_stats
+ * (RSI_E_INVALID) at the next synchronising call; the build then reads
+ * vertex 0 in its place, so nothing outside V is touched.
  * n_t == 0 gives a handle whose queries report no crossing. */
 rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
                      const rsi_opts *opts, void *stream, rsi_handle *out);
@@ -119,7 +133,7 @@ rsi_status rsi_build(const float *V, int64_t n_v, const int32_t *T, int64_t n_t,
 /* Rebuild the tree of an existing handle for new geometry with the same
  * triangle count n_t (all build steps of rsi_build, reusing the handle's
  * device memory, so nothing is allocated).  V, T, n_v as for rsi_build;
- * blocks until done.  Errors as for rsi_build. */
+ * asynchronous on `stream`.  Errors as for rsi_build. */
 rsi_status rsi_rebuild(rsi_handle h, const float *V, int64_t n_v, const int32_t *T, void *stream);
 
 /* Recompute every bound and the packed geometry from new vertex positions
@@ -134,15 +148,22 @@ rsi_status rsi_refit(rsi_handle h, const float *V, void *stream);
  *   mode  bit mask of RSI_BOOL / RSI_FIRST_HIT / RSI_ALL_HITS (nonzero)
  *   out   host struct of device output pointers (see rsi_outputs)
  * RSI_BOOL alone stops each segment at its first crossing.  RSI_ALL_HITS keeps
- * up to `capacity` crossings per segment in `ids`/`ts`; a segment with more
- * is appended to an overflow list and traversed again into a library-owned
- * spill pool holding all its crossings (read it with rsi_spill_*).  With
- * RSI_ALL_HITS the call waits once on `stream` to size that pool; otherwise it
- * is asynchronous.  Reported t, u, v and P are re-solved in FP64 from the FP32
- * inputs; the crossing decisions are the FP32 test.
+ * the first `capacity` crossings by (t, id) of each segment in `ids`/`ts`
+ * and the exact count; a segment with more keeps its full list in the
+ * spill pool (see rsi_outputs), collected during the same walk (the
+ * collision buffer of Section 3.2: atomic append, overflow detection).  The
+ * library pool starts at max(2^20, n_r / 4) entries; when a query needs
+ * more, rsi_query_stats returns RSI_E_OVERFLOW (counts and every list that
+ * fitted stay exact), the pool grows to fit, and the caller queries again.
+ * Always asynchronous on `stream`.  Reported t, u, v and P are re-solved in
+ * FP64 from the FP32 inputs; the crossing decisions are the FP32 test.
+ * Memory kept with the handle, allocated on first use and grown with n_r:
+ * a retry queue (4 bytes per segment) and the deep pass's stack (a fixed
+ * grid); for RSI_ALL_HITS also 16 bytes per segment of overflow table, the
+ * arena and the library pool.
  * n_r == 0 is a no-op (output pointers are then not inspected).
  * Errors: RSI_E_INVALID (n_r < 0 or >= 2^30, mode 0 or unknown bits, missing output
- * pointer, capacity < 1), RSI_E_NOMEM, RSI_E_HIP. */
+ * pointer, capacity < 1, an incomplete caller pool), RSI_E_NOMEM, RSI_E_HIP. */
 rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
                      uint32_t mode, const rsi_outputs *out, void *stream);
 
@@ -158,9 +179,8 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
  *   g_t      device float32 [n_r]   upstream dL/dt      (NULL = zero)
  *   g_uv     device float32 [n_r*2] upstream dL/d(u, v) (NULL = zero)
  *   g_point  device float32 [n_r*3] upstream dL/dP      (NULL = zero)
- *   dV       device float32 [n_v*3]: ACCUMULATED with atomic adds (the
- *            caller zeroes it); summation order is not fixed, so the last
- *            bits vary between runs
+ *   dV       device float32 [n_v*3]: ACCUMULATED (dV += the gradient;
+ *            the caller zeroes it for a plain gradient)
  *   dS, dE   device float32 [n_r*3]: written (zero for misses); NULL skips
  * (t, u, v) and the 3x3 transposed solve are evaluated in FP64 per segment.
  * Batches of at least 65,536 segments and 4 per triangle keep about 24
@@ -173,20 +193,59 @@ rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, 
                                   const int32_t *tri, const float *g_t, const float *g_uv, const float *g_point,
                                   float *dV, float *dS, float *dE, void *stream);
 
-/* After an RSI_ALL_HITS query: number of overflowed segments and total
- * crossings held in the spill pool (host out-parameters). */
+/* After an RSI_ALL_HITS query (waits for it): entries of the overflow
+ * table and pool entries in use (host out-parameters). */
 rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossings);
 
-/* Copy the spill pool into caller device buffers:
- *   seg    int32 [n_segments]  segment index
+/* Copy the overflow table and the pool of the last RSI_ALL_HITS query into
+ * caller device buffers (waits for the query, then copies asynchronously on
+ * `stream`):
+ *   seg    int32 [n_segments]  segment index (batches: work item, i.e. the
+ *                              segment's position in the concatenation of
+ *                              the meshes' segment lists)
  *   offset int64 [n_segments]  first crossing of that segment in ids/ts
- *   count  int32 [n_segments]  its number of crossings
+ *   count  int32 [n_segments]  its number of crossings; -1 marks a void
+ *                              entry (a walk handed to the deep pass,
+ *                              which made a new entry), to be skipped
  *   ids    int32 [n_crossings] triangle ids, per segment ordered by (t, id)
  *   ts     float [n_crossings] their t
- * Asynchronous on `stream`.  Entries are grouped per segment; the order of
- * the segments themselves is unspecified. */
+ * Entries are grouped per segment; the order of the segments themselves is
+ * unspecified. */
 rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *count,
                           int32_t *ids, float *ts, void *stream);
+
+/* State of the last call on the handle, after waiting for it (the
+ * synchronising call that reports what the device found):
+ *   bad_index           the last build met a triangle index outside [0, n_v)
+ *                       (batches: outside its mesh's vertices)
+ *   build_inconsistent  the build's own consistency checks failed
+ *   walk_cut            a walk of the last query stopped at the node-visit
+ *                       bound (only a damaged tree does that)
+ *   stack_dropped       the deep pass dropped a stack entry (damaged tree)
+ *   overflow_full       the last all-hits query's pool or arena was too small
+ *   deep_segments       segments of the last query whose stack outgrew its
+ *                       LDS part and were walked by the deep pass
+ *   overflow_segments   all hits: segments with more crossings than slots
+ *   overflow_crossings  all hits: pool entries they needed (their crossings)
+ *   arena_records       all hits: crossings past the slots
+ *   pool_capacity       all hits: pool entries available to the last query
+ * Returns RSI_E_INVALID for bad_index / build_inconsistent, RSI_E_OVERFLOW
+ * for overflow_full (the library pool has then grown to fit: query again),
+ * else RSI_OK; `out` is filled in every case. */
+typedef struct {
+    int32_t bad_index;
+    int32_t build_inconsistent;
+    int32_t walk_cut;
+    int32_t stack_dropped;
+    int32_t overflow_full;
+    int32_t reserved;
+    int64_t deep_segments;
+    int64_t overflow_segments;
+    int64_t overflow_crossings;
+    int64_t arena_records;
+    int64_t pool_capacity;
+} rsi_stats;
+rsi_status rsi_query_stats(rsi_handle h, rsi_stats *out);
 
 /* Segment order (the paper's v2.2 step, Section 4.1: rays sorted so that
  * neighbouring threads take similar paths).  order (device int32[n_r]) gets
@@ -264,7 +323,8 @@ typedef struct {
 rsi_status rsi_set_counting(rsi_handle h, int enable);
 rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);
 
-/* Tree description for validation (host out-parameters / host buffers).
+/* Tree description for validation (host out-parameters / host buffers;
+ * waits for the handle's last work to read the heights).
  *   n_nodes: number of node records (n_t, the last one being the entry node
  *   whose left child is the root, as in the paper's Section 2), height: levels
  *   of internal nodes below the entry node, leaf_size: as built. */
@@ -280,7 +340,8 @@ rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out);
 
 /* Per-mesh layout of a handle: mesh `mesh` owns triangles, sorted leaves and
  * node records [tri_offset, tri_offset + n_t); its entry node is the last of
- * them.  Any out-pointer may be NULL. */
+ * them.  Any out-pointer may be NULL.  Reading the height waits for the
+ * handle's last work. */
 rsi_status rsi_get_mesh_info(rsi_handle h, int32_t mesh, int64_t *tri_offset, int64_t *n_t, int32_t *height);
 
 /* Copy the tree to host buffers (blocking):
@@ -305,25 +366,29 @@ rsi_status rsi_export_tree(rsi_handle h, float *boxes, int32_t *refs, int32_t *o
  * device pointers (vertex and triangle arrays as for rsi_build), n_v, n_t
  * host arrays of sizes.  The device pointers are kept: rsi_batch_rebuild and
  * captured rebuilds re-read the same buffers.  Triangle ids in outputs are
- * per mesh.  Blocks until built.  Errors as for rsi_build. */
+ * per mesh.  Asynchronous on `stream`.  Errors as for rsi_build. */
 rsi_status rsi_batch_create(int32_t n_meshes, const float *const *V, const int64_t *n_v, const int32_t *const *T,
                             const int64_t *n_t, const rsi_opts *opts, void *stream, rsi_handle *out);
 
 /* Rebuild every mesh of a batch from its (possibly updated) vertex and
- * triangle buffers; blocks until done. */
+ * triangle buffers; asynchronous on `stream`. */
 rsi_status rsi_batch_rebuild(rsi_handle h, void *stream);
 
 /* Query every mesh with its own segments in one launch.  S, E: host arrays of
  * n_meshes device pointers; n_r: host array of counts; outs: host array of
- * n_meshes rsi_outputs (hit / tri / t / uv / point as for rsi_query).  mode:
- * RSI_BOOL and/or RSI_FIRST_HIT.  Copies the tables (waits for that copy),
- * then runs asynchronously on `stream`. */
+ * n_meshes rsi_outputs (hit / tri / t / uv / point / count / ids / ts /
+ * spill_off as for rsi_query; one capacity for every mesh).  mode: a mask of
+ * RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS.  All hits use the library's spill
+ * pool (rsi_spill_*; its `seg` is then the work item).  Copies the tables
+ * (waits for that copy), then runs asynchronously on `stream`. */
 rsi_status rsi_batch_query(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
                            uint32_t mode, const rsi_outputs *outs, void *stream);
 
 /* Capture [rebuild of every mesh if `rebuild`] + the batched query with
  * these tables into a HIP graph held by the handle (replacing any previous
- * one).  All buffers named here must stay valid while the graph is used. */
+ * one).  All buffers named here must stay valid while the graph is used.
+ * A replay may follow any change of the vertex values: the traversal is
+ * sized from a bound on the tree height, not from the captured trees. */
 rsi_status rsi_batch_capture(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
                              uint32_t mode, const rsi_outputs *outs, int rebuild, void *stream);
 

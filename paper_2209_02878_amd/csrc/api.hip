@@ -47,19 +47,24 @@ void free_handle_memory(rsi_bvh *h)
 {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->compact_counts, h->nodes4, h->aux_E, h->aux_count, h->gstack, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys, h->order, h->nodes, h->tris,
-                    h->arrive, h->heights, h->climb, h->split_prefix, h->scalars, h->counters, h->ovf_seg, h->ovf_cnt,
-                    h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off, h->vert_off, h->mesh_bounds,
-                    h->mesh_height, h->mesh_root, h->mesh_entry, h->bt.seg_off, h->bt.S, h->bt.E, h->bt.hit,
-                    h->bt.tri, h->bt.t, h->bt.uv, h->bt.point, h->bt_graph.seg_off, h->bt_graph.S,
-                    h->bt_graph.E, h->bt_graph.hit, h->bt_graph.tri, h->bt_graph.t, h->bt_graph.uv,
-                    h->bt_graph.point};
+    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->adj_rec, h->adj_rec_v, h->tri_sum, h->inc_keys,
+                    h->inc_vals, h->compact_counts, h->nodes4, h->aux_E, h->aux_count,
+                    h->retry_q, h->retry_stack, h->arena, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys,
+                    h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb, h->split_prefix, h->scalars,
+                    h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off,
+                    h->vert_off, h->mesh_bounds, h->mesh_height, h->mesh_root, h->mesh_entry};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    rsi::BatchTables *tabs[] = {&h->bt, &h->bt_graph};
+    for (rsi::BatchTables *t : tabs) {
+        void *tp[] = {t->seg_off, t->S, t->E, t->hit, t->tri, t->t, t->uv, t->point, t->count, t->ids, t->ts,
+                      t->spill_off};
+        for (void *p : tp)
+            if (p) (void)hipFree(p);
+    }
     rsi::free_sort_scratch(h->sort);
     rsi::free_sort_scratch(h->seg_sort);
     if (h->h_scalars) (void)hipHostFree(h->h_scalars);
-    if (h->h_pub) (void)hipHostFree(h->h_pub);
 }
 
 void destroy_handle(rsi_bvh *h)
@@ -109,6 +114,10 @@ hipError_t alloc_tables(rsi::BatchTables &t, int32_t M)
     if (e == hipSuccess) e = dalloc(&t.t, M);
     if (e == hipSuccess) e = dalloc(&t.uv, M);
     if (e == hipSuccess) e = dalloc(&t.point, M);
+    if (e == hipSuccess) e = dalloc(&t.count, M);
+    if (e == hipSuccess) e = dalloc(&t.ids, M);
+    if (e == hipSuccess) e = dalloc(&t.ts, M);
+    if (e == hipSuccess) e = dalloc(&t.spill_off, M);
     return e;
 }
 
@@ -132,7 +141,14 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     }
     h->n_t = h->h_tri_off[M];
     h->n_v = h->h_vert_off[M];
-    h->h_height.assign(M, 0);
+    // A radix-tree node's split has a longer common key prefix than its
+    // parent's, and prefix lengths take at most 63 values for distinct
+    // 63-bit keys plus 27 for equal keys split by a (27-bit) index, so no
+    // path holds more than 90 internal nodes (nor more than n - 1).
+    for (int32_t m = 0; m < M; ++m) {
+        const int64_t hb = n_t[m] - 1 < 90 ? n_t[m] - 1 : 90;
+        if (hb > h->height_bound) h->height_bound = (int32_t)hb;
+    }
     if (h->n_t >= (int64_t(1) << rsi::kLeafFirstBits)) {
         delete h;
         return invalid("total triangle count must be below 2^27");
@@ -169,8 +185,6 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     if (e == hipSuccess && batch) e = alloc_tables(h->bt_graph, M);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&h->h_pub), sizeof(int32_t) * (2 + (size_t)M));
-    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&h->d_pub), h->h_pub, 0);
     if (e == hipSuccess && n > 0) e = rsi::ensure_sort_scratch(h->sort, n);
     if (e == hipSuccess)
         e = hipMemcpy(h->tri_off, h->h_tri_off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
@@ -186,33 +200,44 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     return RSI_OK;
 }
 
-// Wait for the build on `s`, then read back the index checks and the tree
-// heights (which size the traversal stack): one small kernel writes them into
-// pinned host memory, so the wait ends right after the last build kernel.
+// A build is stream-ordered: nothing is read back.  Index checks stay in
+// device flags that rsi_query_stats reports; the traversal needs no tree
+// height on the host (its deep pass is sized from a bound).
 rsi_status finish_build(rsi_bvh *h, hipStream_t s, const char *who)
 {
-    hipError_t e = hipSuccess;
-    if (h->n_t > 0) e = rsi::launch_publish(h, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, who);
-    if (h->n_t > 0) {
-        const int32_t bad = h->h_pub[0], bad_gather = h->h_pub[1];
-        if ((bad & 1) || (h->src_V && bad_gather)) return invalid("triangle index outside [0, n_v)");
-        if (bad) return invalid("inconsistent build state (report this)");
-        int32_t mx = 0;
-        for (int32_t m = 0; m < h->M; ++m) {
-            h->h_height[m] = h->h_pub[2 + m];
-            mx = h->h_pub[2 + m] > mx ? h->h_pub[2 + m] : mx;
-        }
-        h->height = mx;
+    h->last_stream = s;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RSI_OK : hip_fail(e, who);
+}
+
+// Wait for the handle's last work and read every mesh's tree height.
+bool read_heights(rsi_bvh *h, std::vector<int32_t> &hts)
+{
+    hts.assign(h->M, 0);
+    hipError_t e = hipStreamSynchronize(h->last_stream);
+    if (e == hipSuccess && h->n_t > 0)
+        e = hipMemcpy(hts.data(), h->mesh_height, sizeof(int32_t) * h->M, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        hip_fail(e, "tree heights");
+        return false;
     }
-    return RSI_OK;
+    return true;
+}
+
+// Wait for the handle's last enqueued work and copy its device scalars.
+hipError_t read_scalars(rsi_bvh *h)
+{
+    hipError_t e = hipStreamSynchronize(h->last_stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->h_scalars, h->scalars, sizeof(int32_t) * rsi::kNumScalars, hipMemcpyDeviceToHost);
+    return e;
 }
 
 // Single mesh: copy the indices and run the build kernels.
 hipError_t enqueue_build_single(rsi_bvh *h, const float *V, const int32_t *T, hipStream_t s)
 {
     hipError_t e = hipSuccess;
+    h->inc_valid = false;  // new triangles, new Morton order: the adjoint's incidence table is stale
     if (h->n_t > 0) e = hipMemcpyAsync(h->T, T, sizeof(int32_t) * 3 * h->n_t, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = rsi::launch_build(h, V, s);
     return e;
@@ -231,49 +256,19 @@ bool valid_mode(uint32_t mode)
     return mode != 0 && !(mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS | RSI_COUNT));
 }
 
-hipError_t ensure_ovf(rsi_bvh *h, int64_t n_r)
-{
-    if (h->ovf_cap >= n_r) return hipSuccess;
-    if (h->ovf_seg) (void)hipFree(h->ovf_seg);
-    if (h->ovf_cnt) (void)hipFree(h->ovf_cnt);
-    if (h->ovf_off) (void)hipFree(h->ovf_off);
-    h->ovf_seg = nullptr;
-    h->ovf_cnt = nullptr;
-    h->ovf_off = nullptr;
-    h->ovf_cap = 0;
-    hipError_t e = dalloc(&h->ovf_seg, n_r);
-    if (e == hipSuccess) e = dalloc(&h->ovf_cnt, n_r);
-    if (e == hipSuccess) e = dalloc(&h->ovf_off, n_r);
-    if (e == hipSuccess) h->ovf_cap = n_r;
-    return e;
-}
-
-hipError_t ensure_pool(rsi_bvh *h, int64_t n)
-{
-    if (h->pool_cap >= n) return hipSuccess;
-    if (h->pool_ids) (void)hipFree(h->pool_ids);
-    if (h->pool_ts) (void)hipFree(h->pool_ts);
-    h->pool_ids = nullptr;
-    h->pool_ts = nullptr;
-    h->pool_cap = 0;
-    const int64_t want = n + n / 4;
-    hipError_t e = dalloc(&h->pool_ids, want);
-    if (e == hipSuccess) e = dalloc(&h->pool_ts, want);
-    if (e == hipSuccess) h->pool_cap = want;
-    return e;
-}
-
 // Validate a batch query and write its tables; returns the total segment count.
 rsi_status set_batch_tables(rsi_bvh *h, rsi::BatchTables &bt, const float *const *S, const float *const *E,
                             const int64_t *n_r, uint32_t mode, const rsi_outputs *outs, hipStream_t s,
-                            int64_t *total)
+                            int64_t *total, int32_t *cap)
 {
     const int32_t M = h->M;
     if (!S || !E || !n_r || !outs) return invalid("rsi_batch_query: NULL table");
-    if (mode == 0 || (mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT)))
-        return invalid("rsi_batch_query: mode must be a nonzero mask of RSI_BOOL and RSI_FIRST_HIT");
+    if (mode == 0 || (mode & ~(uint32_t)(RSI_BOOL | RSI_FIRST_HIT | RSI_ALL_HITS)))
+        return invalid("rsi_batch_query: mode must be a nonzero mask of RSI_BOOL, RSI_FIRST_HIT and RSI_ALL_HITS");
+    constexpr int kTabs = 11;
     std::vector<int64_t> off(M + 1, 0);
-    std::vector<const void *> tab(7 * (size_t)M, nullptr);
+    std::vector<const void *> tab(kTabs * (size_t)M, nullptr);
+    int32_t K = 0;
     for (int32_t m = 0; m < M; ++m) {
         if (n_r[m] < 0) return invalid("rsi_batch_query: negative segment count");
         off[m + 1] = off[m] + n_r[m];
@@ -282,25 +277,45 @@ rsi_status set_batch_tables(rsi_bvh *h, rsi::BatchTables &bt, const float *const
             if ((mode & RSI_BOOL) && !outs[m].hit) return invalid("rsi_batch_query: RSI_BOOL needs hit");
             if ((mode & RSI_FIRST_HIT) && (!outs[m].tri || !outs[m].t || !outs[m].uv || !outs[m].point))
                 return invalid("rsi_batch_query: RSI_FIRST_HIT needs tri, t, uv, point");
+            if (mode & RSI_ALL_HITS) {
+                if (!outs[m].count || !outs[m].ids || !outs[m].ts)
+                    return invalid("rsi_batch_query: RSI_ALL_HITS needs count, ids, ts");
+                if (outs[m].capacity < 1 || (K && outs[m].capacity != K))
+                    return invalid("rsi_batch_query: RSI_ALL_HITS needs one capacity >= 1 for every mesh");
+                K = outs[m].capacity;
+            }
         }
-        tab[0 * M + m] = S[m];
-        tab[1 * M + m] = E[m];
-        tab[2 * M + m] = outs[m].hit;
-        tab[3 * M + m] = outs[m].tri;
-        tab[4 * M + m] = outs[m].t;
-        tab[5 * M + m] = outs[m].uv;
-        tab[6 * M + m] = outs[m].point;
+        const void *row[kTabs] = {S[m], E[m], outs[m].hit, outs[m].tri, outs[m].t, outs[m].uv, outs[m].point,
+                                  outs[m].count, outs[m].ids, outs[m].ts, outs[m].spill_off};
+        for (int k = 0; k < kTabs; ++k) tab[(size_t)k * M + m] = row[k];
     }
     if (off[M] >= (int64_t(1) << 30)) return invalid("rsi_batch_query: total segments must be below 2^30");
-    void *dst[7] = {bt.S, bt.E, bt.hit, bt.tri, bt.t, bt.uv, bt.point};
+    void *dst[kTabs] = {bt.S, bt.E, bt.hit, bt.tri, bt.t, bt.uv, bt.point, bt.count, bt.ids, bt.ts, bt.spill_off};
     hipError_t e = hipMemcpyAsync(bt.seg_off, off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice, s);
-    for (int k = 0; k < 7 && e == hipSuccess; ++k)
+    for (int k = 0; k < kTabs && e == hipSuccess; ++k)
         e = hipMemcpyAsync(dst[k], tab.data() + (size_t)k * M, sizeof(void *) * M, hipMemcpyHostToDevice, s);
     // the host vectors go out of scope on return: wait for the copies
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_query: tables");
     *total = off[M];
+    *cap = K ? K : 1;
     return RSI_OK;
+}
+
+// Device memory of a batched query (before any capture: nothing may be
+// allocated inside one).
+rsi_status prepare_batch_memory(rsi_bvh *h, int64_t total, uint32_t mode)
+{
+    const bool all = (mode & RSI_ALL_HITS) != 0;
+    hipError_t e = rsi::ensure_query_memory(h, total, all);
+    if (e == hipSuccess && all) {
+        const int64_t dflt = total / 4 > (1 << 20) ? total / 4 : (1 << 20);
+        e = rsi::ensure_pool(h, h->pool_want > dflt ? h->pool_want : dflt);
+        h->last_pool_ids = h->pool_ids;
+        h->last_pool_ts = h->pool_ts;
+        h->last_pool_cap = h->pool_cap;
+    }
+    return e == hipSuccess ? RSI_OK : hip_fail(e, "batched query: scratch");
 }
 
 }  // namespace
@@ -395,40 +410,38 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r, 
     if (n_r >= (int64_t(1) << 30)) return invalid("rsi_query: n_r must be below 2^30");
     hipStream_t s = (hipStream_t)stream;
     rsi::QueryOut o = {out->hit, out->tri, out->t, out->uv, out->point, out->count, out->ids, out->ts,
-                       out->capacity};
-    h->last_ovf_segs = 0;
-    h->last_ovf_total = 0;
+                       out->capacity, nullptr, nullptr, nullptr, 0};
+    h->last_stream = s;
     hipError_t e;
+    if (mode & RSI_ALL_HITS) {
+        o.spill_off = out->spill_off;
+        if (out->spill_ids || out->spill_ts || out->spill_cap) {
+            if (!out->spill_ids || !out->spill_ts || out->spill_cap < 1)
+                return invalid("rsi_query: a caller spill pool needs spill_ids, spill_ts and spill_cap >= 1");
+            o.pool_ids = out->spill_ids;
+            o.pool_ts = out->spill_ts;
+            o.pool_cap = out->spill_cap;
+        } else {
+            const int64_t dflt = n_r / 4 > (1 << 20) ? n_r / 4 : (1 << 20);
+            e = rsi::ensure_pool(h, h->pool_want > dflt ? h->pool_want : dflt);
+            if (e != hipSuccess) return hip_fail(e, "rsi_query: spill pool");
+            o.pool_ids = h->pool_ids;
+            o.pool_ts = h->pool_ts;
+            o.pool_cap = h->pool_cap;
+        }
+        h->last_pool_ids = o.pool_ids;
+        h->last_pool_ts = o.pool_ts;
+        h->last_pool_cap = o.pool_cap;
+    }
     if (h->n_t == 0) {
         e = rsi::launch_fill_miss(n_r, mode, o, s);
+        if (e == hipSuccess) e = rsi::launch_clear_query(h, s);
         return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_query");
     }
-    if (mode & RSI_ALL_HITS) {
-        e = ensure_ovf(h, n_r);
-        if (e != hipSuccess) return hip_fail(e, "rsi_query: overflow list");
-    }
-    e = rsi::ensure_gstack(h);
-    if (e != hipSuccess) return hip_fail(e, "rsi_query: stack");
+    e = rsi::ensure_query_memory(h, n_r, (mode & RSI_ALL_HITS) != 0);
+    if (e != hipSuccess) return hip_fail(e, "rsi_query: scratch");
     e = rsi::launch_query(h, S, E, n_r, mode, o, s);
     if (e != hipSuccess) return hip_fail(e, "rsi_query");
-    if (mode & RSI_ALL_HITS) {
-        // size the spill pool: one read-back of the overflow totals
-        e = hipMemcpyAsync(h->h_scalars + rsi::kOvfSegs, h->scalars + rsi::kOvfSegs, 3 * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "rsi_query: overflow read-back");
-        const int64_t nseg = h->h_scalars[rsi::kOvfSegs];
-        const uint64_t tot = (uint32_t)h->h_scalars[rsi::kOvfTotalLo] |
-                             ((uint64_t)(uint32_t)h->h_scalars[rsi::kOvfTotalHi] << 32);
-        h->last_ovf_segs = nseg;
-        h->last_ovf_total = (int64_t)tot;
-        if (nseg > 0) {
-            e = ensure_pool(h, (int64_t)tot);
-            if (e != hipSuccess) return hip_fail(e, "rsi_query: spill pool");
-            e = rsi::launch_spill(h, S, E, mode, o, s);
-            if (e != hipSuccess) return hip_fail(e, "rsi_query: spill pass");
-        }
-    }
     return RSI_OK;
 }
 
@@ -541,8 +554,13 @@ rsi_status rsi_spill_info(rsi_handle h, int64_t *n_segments, int64_t *n_crossing
 {
     set_error("");
     if (!h || !n_segments || !n_crossings) return invalid("rsi_spill_info: NULL argument");
-    *n_segments = h->last_ovf_segs;
-    *n_crossings = h->last_ovf_total;
+    hipError_t e = read_scalars(h);
+    if (e != hipSuccess) return hip_fail(e, "rsi_spill_info");
+    const int64_t ne = h->h_scalars[rsi::kOvfSegs];
+    const uint64_t tot = (uint32_t)h->h_scalars[rsi::kOvfTotalLo] |
+                         ((uint64_t)(uint32_t)h->h_scalars[rsi::kOvfTotalHi] << 32);
+    *n_segments = ne < h->ovf_cap ? ne : h->ovf_cap;
+    *n_crossings = (int64_t)tot < h->last_pool_cap ? (int64_t)tot : h->last_pool_cap;
     return RSI_OK;
 }
 
@@ -551,16 +569,55 @@ rsi_status rsi_spill_read(rsi_handle h, int32_t *seg, int64_t *offset, int32_t *
 {
     set_error("");
     if (!h) return invalid("rsi_spill_read: NULL handle");
-    const int64_t n = h->last_ovf_segs, m = h->last_ovf_total;
+    int64_t n = 0, m = 0;
+    rsi_status st = rsi_spill_info(h, &n, &m);
+    if (st != RSI_OK) return st;
     if (n == 0) return RSI_OK;
-    if (!seg || !offset || !count || !ids || !ts) return invalid("rsi_spill_read: NULL buffer");
+    if (!seg || !offset || !count || (m > 0 && (!ids || !ts))) return invalid("rsi_spill_read: NULL buffer");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(seg, h->ovf_seg, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(offset, h->ovf_off, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(count, h->ovf_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(ids, h->pool_ids, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(ts, h->pool_ts, sizeof(float) * m, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && m > 0)
+        e = hipMemcpyAsync(ids, h->last_pool_ids, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && m > 0)
+        e = hipMemcpyAsync(ts, h->last_pool_ts, sizeof(float) * m, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "rsi_spill_read");
+    return RSI_OK;
+}
+
+rsi_status rsi_query_stats(rsi_handle h, rsi_stats *out)
+{
+    set_error("");
+    if (!h || !out) return invalid("rsi_query_stats: NULL argument");
+    memset(out, 0, sizeof(*out));
+    hipError_t e = read_scalars(h);
+    if (e != hipSuccess) return hip_fail(e, "rsi_query_stats");
+    const int32_t *c = h->h_scalars;
+    auto u64 = [&](int lo, int hi) { return (int64_t)((uint32_t)c[lo] | ((uint64_t)(uint32_t)c[hi] << 32)); };
+    out->bad_index = (c[rsi::kBadIndex] & 1) || (h->src_V && c[rsi::kBadGather]) ? 1 : 0;
+    out->build_inconsistent = (c[rsi::kBadIndex] & 2) ? 1 : 0;
+    out->walk_cut = c[rsi::kWalkCut] != 0;
+    out->stack_dropped = c[rsi::kStackDropped] != 0;
+    out->deep_segments = c[rsi::kRetryN];
+    out->overflow_segments = c[rsi::kOvfSegs];
+    out->overflow_crossings = u64(rsi::kOvfTotalLo, rsi::kOvfTotalHi);
+    out->arena_records = u64(rsi::kArenaLo, rsi::kArenaHi);
+    out->pool_capacity = h->last_pool_cap;
+    out->overflow_full = (c[rsi::kOvfFull] != 0 || c[rsi::kRetryLost] != 0) ? 1 : 0;
+    if (out->overflow_full) {
+        // the next all-hits query gets a pool and an arena that hold this one
+        int64_t want = out->overflow_crossings > out->arena_records ? out->overflow_crossings : out->arena_records;
+        want += want / 4;
+        if (want > h->pool_want) h->pool_want = want;
+    }
+    if (out->bad_index) return invalid("triangle index outside [0, n_v)");
+    if (out->build_inconsistent) return invalid("inconsistent build state (report this)");
+    if (out->overflow_full) {
+        set_error("all-hits spill pool or arena too small for the last query (counts are exact; query again: "
+                  "the library pool has grown, a caller pool needs overflow_crossings entries)");
+        return RSI_E_OVERFLOW;
+    }
     return RSI_OK;
 }
 
@@ -601,16 +658,9 @@ rsi_status rsi_batch_rebuild(rsi_handle h, void *stream)
     if (!h) return invalid("rsi_batch_rebuild: NULL handle");
     if (!h->src_V) return invalid("rsi_batch_rebuild: not a batch handle");
     hipStream_t s = (hipStream_t)stream;
-    const int32_t before = h->height;
     hipError_t e = enqueue_build_batch(h, s);
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_rebuild");
-    rsi_status st = finish_build(h, s, "rsi_batch_rebuild");
-    if (st == RSI_OK && h->height > before && h->graph) {
-        // the captured launch sized its stack for the old trees
-        (void)hipGraphExecDestroy(h->graph);
-        h->graph = nullptr;
-    }
-    return st;
+    return finish_build(h, s, "rsi_batch_rebuild");
 }
 
 rsi_status rsi_batch_query(rsi_handle h, const float *const *S, const float *const *E, const int64_t *n_r,
@@ -621,11 +671,13 @@ rsi_status rsi_batch_query(rsi_handle h, const float *const *S, const float *con
     if (!h->src_V) return invalid("rsi_batch_query: not a batch handle");
     hipStream_t s = (hipStream_t)stream;
     int64_t total = 0;
-    rsi_status st = set_batch_tables(h, h->bt, S, E, n_r, mode, outs, s, &total);
+    int32_t cap = 1;
+    rsi_status st = set_batch_tables(h, h->bt, S, E, n_r, mode, outs, s, &total, &cap);
     if (st != RSI_OK) return st;
-    hipError_t e = rsi::ensure_gstack(h);
-    if (e != hipSuccess) return hip_fail(e, "rsi_batch_query: stack");
-    e = rsi::launch_batch_query(h, h->bt, total, mode, s);
+    st = prepare_batch_memory(h, total, mode);
+    if (st != RSI_OK) return st;
+    h->last_stream = s;
+    hipError_t e = rsi::launch_batch_query(h, h->bt, total, mode, cap, s);
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_query");
     return RSI_OK;
 }
@@ -645,10 +697,12 @@ rsi_status rsi_batch_capture(rsi_handle h, const float *const *S, const float *c
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
     }
-    rsi_status st = set_batch_tables(h, h->bt_graph, S, E, n_r, mode, outs, s, &total);
+    int32_t cap = 1;
+    rsi_status st = set_batch_tables(h, h->bt_graph, S, E, n_r, mode, outs, s, &total, &cap);
     if (st != RSI_OK) return st;
-    hipError_t e = rsi::ensure_gstack(h);  // no allocation may happen inside the capture
-    if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: stack");
+    st = prepare_batch_memory(h, total, mode);  // no allocation may happen inside the capture
+    if (st != RSI_OK) return st;
+    hipError_t e = hipSuccess;
     if (!h->capture_stream) e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: stream");
     hipGraph_t g = nullptr;
@@ -656,7 +710,7 @@ rsi_status rsi_batch_capture(rsi_handle h, const float *const *S, const float *c
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_capture: begin");
     hipError_t ek = hipSuccess;
     if (rebuild) ek = enqueue_build_batch(h, h->capture_stream);
-    if (ek == hipSuccess) ek = rsi::launch_batch_query(h, h->bt_graph, total, mode, h->capture_stream);
+    if (ek == hipSuccess) ek = rsi::launch_batch_query(h, h->bt_graph, total, mode, cap, h->capture_stream);
     e = hipStreamEndCapture(h->capture_stream, &g);
     if (ek != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -677,6 +731,7 @@ rsi_status rsi_batch_replay(rsi_handle h, void *stream)
     set_error("");
     if (!h) return invalid("rsi_batch_replay: NULL handle");
     if (!h->graph) return invalid("rsi_batch_replay: nothing captured");
+    h->last_stream = (hipStream_t)stream;
     hipError_t e = hipGraphLaunch(h->graph, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rsi_batch_replay");
     return RSI_OK;
@@ -859,9 +914,13 @@ rsi_status rsi_get_tree_info(rsi_handle h, rsi_tree_info *out)
     set_error("");
     if (!h || !out) return invalid("rsi_get_tree_info: NULL argument");
     memset(out, 0, sizeof(*out));
+    std::vector<int32_t> hts;
+    if (!read_heights(h, hts)) return RSI_E_HIP;
+    int32_t mx = 0;
+    for (int32_t x : hts) mx = x > mx ? x : mx;
     out->n_t = h->n_t;
     out->n_nodes = h->n_t;
-    out->height = h->height;
+    out->height = mx;
     out->leaf_size = h->leaf_size;
     out->entry = h->n_t > 0 ? (int32_t)(h->h_tri_off[1] - 1) : 0;
     out->n_meshes = h->M;
@@ -875,7 +934,11 @@ rsi_status rsi_get_mesh_info(rsi_handle h, int32_t mesh, int64_t *tri_offset, in
     if (mesh < 0 || mesh >= h->M) return invalid("rsi_get_mesh_info: mesh out of range");
     if (tri_offset) *tri_offset = h->h_tri_off[mesh];
     if (n_t) *n_t = h->h_tri_off[mesh + 1] - h->h_tri_off[mesh];
-    if (height) *height = h->h_height[mesh];
+    if (height) {
+        std::vector<int32_t> hts;
+        if (!read_heights(h, hts)) return RSI_E_HIP;
+        *height = hts[mesh];
+    }
     return RSI_OK;
 }
 

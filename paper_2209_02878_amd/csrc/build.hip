@@ -639,14 +639,6 @@ unsigned init_grid(const BuildArgs &a)
     return (unsigned)((n + 255) / 256);
 }
 
-// Copy the index flags and the tree heights into the pinned host block.
-__global__ void k_publish(const int32_t *__restrict__ scalars, const int32_t *__restrict__ mesh_height, int32_t M,
-                          int32_t *__restrict__ pub)
-{
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < M + 2; i += gridDim.x * blockDim.x)
-        pub[i] = i == 0 ? scalars[kBadIndex] : (i == 1 ? scalars[kBadGather] : mesh_height[i - 2]);
-}
-
 }  // namespace
 
 hipError_t launch_gather(rsi_bvh *h, hipStream_t s)
@@ -689,13 +681,6 @@ hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s)
     e = run_hierarchy(a, s);
     if (e != hipSuccess) return e;
     return launch_widen(h, s);
-}
-
-hipError_t launch_publish(rsi_bvh *h, hipStream_t s)
-{
-    const int32_t n = h->M + 2;
-    hipLaunchKernelGGL(k_publish, dim3((n + 255) / 256), dim3(256), 0, s, h->scalars, h->mesh_height, h->M, h->d_pub);
-    return hipGetLastError();
 }
 
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s)

@@ -11,10 +11,14 @@
 // avoids.
 //
 // A lane walks the tree from the entry node with a stack laid out
-// [depth][lane] in LDS so a wave's pushes and pops hit distinct banks; its
-// depth is sized from the tree height, so it cannot overflow, and entries
-// beyond the LDS part (the four-way walk keeps 20 there by default, 17 when
-// it holds the top copy below) go to a per-lane tail in device memory.
+// [depth][lane] in LDS so a wave's pushes and pops hit distinct banks.  The
+// main pass keeps the whole stack in LDS (20 entries per lane on the
+// four-way walk, 17 when it holds the top copy below; 32 on the binary
+// walk); a walk that would push past it stops, queues its segment, and a
+// deep pass (a small grid whose stacks continue in device memory up to a
+// bound on the tree height) walks those segments again from the root.  No
+// tree height is needed on the host, so builds, rebuilds and queries are
+// enqueued without waiting for the device.
 // Each node step loads one 64-byte record; the boolean and counting walks of
 // a single mesh read the records of the top three four-way levels from a
 // per-workgroup copy in LDS instead.
@@ -26,18 +30,26 @@
 // nearer touched child.  Pending leaves are tested once few lanes can still
 // take a node step, so the triangle test runs with most lanes active.  The
 // paper's bounded candidate list with resume (Section 3.2) is therefore not
-// needed: candidates are tested soon after they are found, and the bounded
-// buffers left are the stack and the all-hits slots, whose overflow is
-// detected and retried into a pool.
+// needed: candidates are tested soon after they are found.
 //
 // Modes
 //   bool only   stop at the first crossing (any-hit, Section 3.2)
 //   first hit   keep the crossing with the smallest (t, id); boxes that start
 //               beyond it are pruned
-//   all hits    count every crossing, keep the first K found in slots; the
-//               epilogue re-solves them in FP64, orders them by (t, id), and
-//               appends segments with more than K crossings to an overflow
-//               list for the spill pass
+//   all hits    count every crossing and keep the first K found (K slots per
+//               segment); every crossing after the K-th goes to an arena as
+//               an (overflow entry, rank, triangle) record, by one atomic
+//               bump of the arena's counter.  When its walk ends, a segment
+//               with more than K crossings reserves a range of the pool of
+//               full lists (a second atomic bump) and stores its first K
+//               there; two short passes then move the arena records into
+//               the ranges and re-solve, order and copy each list (its
+//               first K into the slots).  Nothing is walked twice and the
+//               host never waits; a pool or arena that is too small sets a
+//               flag (counts stay exact) that rsi_query_stats reports.
+//   count       count every crossing, no list
+// Segment ends are read, and results written, with nontemporal accesses:
+// they stream through once, and must not push the tree out of the L2.
 #include <hip/hip_runtime.h>
 #include <float.h>
 #include <math.h>
@@ -61,25 +73,28 @@ struct QArgs {
     const Node *nodes;
     const Node4 *nodes4;  // four-way view (branching 4), else null
     const Tri *tris;
+    int32_t n_tris;      // packed triangles (positions are checked against it before a re-solve)
     int32_t entry;
     const float *S;
     const float *E;
-    int64_t n_items;     // work items: segments, or overflow entries in the spill pass
+    int64_t n_items;     // work items of the main pass (segments, or (mesh, segment) pairs)
     QueryOut o;
-    // overflow list (all-hits)
+    // all hits: overflow table, arena, pool (QueryOut) and their capacities
     int32_t *ovf_seg;
     int32_t *ovf_cnt;
     int64_t *ovf_off;
     int64_t ovf_cap;
+    int4 *arena;
+    int64_t arena_cap;
     int32_t *scalars;
-    int32_t *pool_ids;
-    float *pool_ts;
     Counters *counters;
-    int32_t depth;       // stack entries per lane (tree height + 1)
-    int32_t lds_depth;   // of which the first lds_depth live in LDS, the rest in gstack
-    int32_t *gstack;     // [(depth - lds_depth) x resident threads], laid out [entry][thread]
+    int32_t depth;       // stack entries per lane: the LDS part (main pass) or the height bound (deep pass)
+    int32_t lds_depth;   // of which the first lds_depth live in LDS, the rest in gstack (deep pass)
+    int32_t *gstack;     // deep pass: [(depth - lds_depth) x threads of the grid], laid out [entry][thread]
     int64_t gstack_cap;  // entries in gstack
-    int32_t max_steps;   // node visits of one segment never exceed the node count
+    int32_t *retry_q;    // work items whose stack outgrew the main pass's LDS part
+    int64_t retry_cap;
+    int32_t max_steps;   // node records: a walk of a valid tree visits each at most once
     int32_t defer;       // test pending leaves once fewer lanes than this can step
     int32_t refill;      // fetch new segments once this many lanes are idle
     int32_t chunk;       // work items a wave claims per atomic on the global counter
@@ -88,6 +103,24 @@ struct QArgs {
     const int32_t *mesh_entry;
     BatchTables bt;
 };
+
+// Streaming accesses (segment ends in, results out).
+template <typename T>
+__device__ inline T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ inline void st_nt(T *p, T v) { __builtin_nontemporal_store(v, p); }
+typedef int32_t nt_i4 __attribute__((ext_vector_type(4)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ inline void st_nt4(int32_t *p, int32_t a, int32_t b, int32_t c, int32_t d)
+{
+    nt_i4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_i4 *>(p));
+}
+__device__ inline void st_nt4(float *p, float a, float b, float c, float d)
+{
+    nt_f4 v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
 
 __device__ inline void wave_add_u64(unsigned long long *dst, unsigned long long v)
 {
@@ -170,19 +203,26 @@ struct Lane {
     float best_t;
     int32_t best_id;
     int32_t best_pos;
-    int32_t count;     // crossings found (all hits)
-    int32_t spill_cap; // pool entries reserved for this segment (spill pass)
+    int32_t count;     // crossings found (all hits, count)
+    int32_t e;         // all hits: overflow-table entry, -1 while count <= K
+    int32_t item;      // work item (a segment, or a (mesh, segment) pair of a batch)
     int64_t seg_i;     // segment index (within its mesh for batched queries)
-    int64_t slot_base; // first slot of this segment (all hits) or pool offset (spill)
+    int64_t slot_base; // first slot of this segment (all hits)
     const float *sp;   // this segment's start and end (3 floats each)
     const float *ep;
     int32_t mesh;      // batched queries: the segment's mesh
-    int32_t hp0, hp1, hp2, hp3;  // all hits, capacity <= 4: the last four hit positions
+    int32_t hp0, hp1, hp2, hp3;  // all hits, capacity <= 4: the hit positions found so far
     bool found;
+    bool retry;        // the stack outgrew the pass's stack: the deep pass walks this segment again
 };
 
+template <bool BATCH>
+__device__ inline int32_t *slot_ids(const QArgs &a, const Lane &L) { return BATCH ? a.bt.ids[L.mesh] : a.o.ids; }
+template <bool BATCH>
+__device__ inline float *slot_ts(const QArgs &a, const Lane &L) { return BATCH ? a.bt.ts[L.mesh] : a.o.ts; }
+
 // Test the triangles of one leaf; returns true when the lane may stop.
-template <uint32_t MODE, bool SPILL, bool COUNT>
+template <uint32_t MODE, bool BATCH, bool COUNT>
 __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t &tests)
 {
     const int32_t first = leaf_first(ref);
@@ -210,82 +250,49 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
         if ((MODE & M_COUNT) && !(MODE & M_ALL)) ++L.count;
         if (MODE & M_ALL) {
             const int32_t c = L.count++;
-            if (SPILL) {
-                // the spill pass repeats the first pass's decisions; the
-                // bound only keeps a mismatch from writing past the segment
-                if (c < L.spill_cap) a.pool_ids[L.slot_base + c] = pos;
-            } else if (a.o.cap <= kRegSlots) {
-                // kept in registers until the segment is finished
-                L.hp3 = L.hp2;
-                L.hp2 = L.hp1;
-                L.hp1 = L.hp0;
-                L.hp0 = pos;
-            } else if (c < a.o.cap) {
-                a.o.ids[L.slot_base + c] = pos;
+            const int32_t K = a.o.cap;
+            if (c < K) {
+                if (K <= kRegSlots) {
+                    // kept in registers until the segment is finished
+                    L.hp3 = L.hp2;
+                    L.hp2 = L.hp1;
+                    L.hp1 = L.hp0;
+                    L.hp0 = pos;
+                } else {
+                    slot_ids<BATCH>(a, L)[L.slot_base + c] = pos;
+                }
+            } else {
+                // past the slots: an arena record (entry, rank, position)
+                if (c == K) L.e = atomicAdd(&a.scalars[kOvfSegs], 1);
+                const unsigned long long r =
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&a.scalars[kArenaLo]), 1ull);
+                if (L.e < a.ovf_cap && r < (unsigned long long)a.arena_cap)
+                    a.arena[r] = make_int4(L.e, c, pos, 0);
+                else
+                    atomicOr(&a.scalars[kOvfFull], 1);
             }
         }
     }
     return false;
 }
 
-// Orders entries [0, n) of a (t, id) list in place by (t, id); insertion sort
-// because lists are short.
-__device__ inline void sort_slots(int32_t *ids, float *ts, int n)
-{
-    for (int x = 1; x < n; ++x) {
-        const float kt = ts[x];
-        const int32_t ki = ids[x];
-        int y = x - 1;
-        while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
-            ts[y + 1] = ts[y];
-            ids[y + 1] = ids[y];
-            --y;
-        }
-        ts[y + 1] = kt;
-        ids[y + 1] = ki;
-    }
-}
-
-// Replace sorted positions by original ids and FP32 t by the FP64 re-solve.
-__device__ inline void refine_list(const QArgs &a, double sx, double sy, double sz, double ex, double ey,
-                                   double ez, int32_t *ids, float *ts, int n)
-{
-    for (int c = 0; c < n; ++c) {
-        float v[9];
-        int32_t id;
-        tri_load(a.tris, ids[c], v, id);
-        double t, u, w;
-        mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-        ids[c] = id;
-        ts[c] = (float)t;
-    }
-}
-
-// Write the results of a finished segment.
-template <uint32_t MODE, bool SPILL, bool BATCH>
+// Write the results of a finished segment (or queue it for the deep pass).
+template <uint32_t MODE, bool RETRY, bool BATCH>
 __device__ inline void finish(const QArgs &a, const Lane &L)
 {
-    const int64_t i = L.seg_i;
-    const float sx = L.sp[0], sy = L.sp[1], sz = L.sp[2];
-    const float ex = L.ep[0], ey = L.ep[1], ez = L.ep[2];
-    if (SPILL) {
-        const int n = L.count < L.spill_cap ? L.count : L.spill_cap;
-        int32_t *ids = a.pool_ids + L.slot_base;
-        float *ts = a.pool_ts + L.slot_base;
-        refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n);
-        sort_slots(ids, ts, n);
-        const int K = a.o.cap;
-        int32_t *sid = a.o.ids + i * (int64_t)K;
-        float *sts = a.o.ts + i * (int64_t)K;
-        for (int c = 0; c < K; ++c) {
-            sid[c] = c < n ? ids[c] : -1;
-            sts[c] = c < n ? ts[c] : INFINITY;
-        }
+    if (!RETRY && L.retry) {
+        const int32_t r = atomicAdd(&a.scalars[kRetryN], 1);
+        if (r < a.retry_cap) a.retry_q[r] = L.item;
+        else atomicOr(&a.scalars[kRetryLost], 1);
+        // the records this walk left in the arena are void: the deep pass
+        // takes a new overflow entry
+        if ((MODE & M_ALL) && L.e >= 0 && L.e < a.ovf_cap) a.ovf_cnt[L.e] = -1;
         return;
     }
+    const int64_t i = L.seg_i;
     if (MODE & M_BOOL) {
         uint8_t *hit = BATCH ? a.bt.hit[L.mesh] : a.o.hit;
-        hit[i] = L.found ? 1 : 0;
+        st_nt(hit + i, (uint8_t)(L.found ? 1 : 0));
     }
     if (MODE & M_FIRST) {
         int32_t *tri = BATCH ? a.bt.tri[L.mesh] : a.o.tri;
@@ -298,116 +305,168 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
             tri[i] = L.best_pos;
         } else if (L.best_pos >= 0) {
             // with all hits the walk keeps many registers anyway: re-solve here
+            const float sx = ld_nt(L.sp), sy = ld_nt(L.sp + 1), sz = ld_nt(L.sp + 2);
+            const float ex = ld_nt(L.ep), ey = ld_nt(L.ep + 1), ez = ld_nt(L.ep + 2);
             float v[9];
             int32_t id;
             tri_load(a.tris, L.best_pos, v, id);
             double t, u, w;
             mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-            tri[i] = id;
-            tt[i] = (float)t;
-            uv[2 * i] = (float)u;
-            uv[2 * i + 1] = (float)w;
-            pt[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
-            pt[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
-            pt[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
+            st_nt(tri + i, id);
+            st_nt(tt + i, (float)t);
+            st_nt(uv + 2 * i, (float)u);
+            st_nt(uv + 2 * i + 1, (float)w);
+            st_nt(pt + 3 * i, (float)((double)sx + t * ((double)ex - (double)sx)));
+            st_nt(pt + 3 * i + 1, (float)((double)sy + t * ((double)ey - (double)sy)));
+            st_nt(pt + 3 * i + 2, (float)((double)sz + t * ((double)ez - (double)sz)));
         } else {
-            tri[i] = -1;
-            tt[i] = INFINITY;
-            uv[2 * i] = 0.0f;
-            uv[2 * i + 1] = 0.0f;
-            pt[3 * i] = 0.0f;
-            pt[3 * i + 1] = 0.0f;
-            pt[3 * i + 2] = 0.0f;
+            st_nt(tri + i, -1);
+            st_nt(tt + i, INFINITY);
+            st_nt(uv + 2 * i, 0.0f);
+            st_nt(uv + 2 * i + 1, 0.0f);
+            st_nt(pt + 3 * i, 0.0f);
+            st_nt(pt + 3 * i + 1, 0.0f);
+            st_nt(pt + 3 * i + 2, 0.0f);
         }
     }
-    if ((MODE & M_COUNT) && !(MODE & M_ALL)) a.o.count[i] = L.count;
+    if ((MODE & M_COUNT) && !(MODE & M_ALL)) st_nt(a.o.count + i, L.count);
     if (MODE & M_ALL) {
         const int K = a.o.cap;
-        a.o.count[i] = L.count;
-        int32_t *ids = a.o.ids + L.slot_base;
-        float *ts = a.o.ts + L.slot_base;
-        const int n_in = L.count < K ? L.count : K;
-        if (K <= kRegSlots && L.count <= K) {
-            // the hits are in registers: re-solve, order by (t, id) with a
-            // sorting network (unused entries sort last) and store once
-            int32_t id[kRegSlots];
-            float t[kRegSlots];
-            const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
+        int32_t *cnt_out = BATCH ? a.bt.count[L.mesh] : a.o.count;
+        int64_t *soff = BATCH ? a.bt.spill_off[L.mesh] : a.o.spill_off;
+        st_nt(cnt_out + i, L.count);
+        int32_t *ids = slot_ids<BATCH>(a, L) + L.slot_base;
+        float *ts = slot_ts<BATCH>(a, L) + L.slot_base;
+        if (L.count <= K) {
+            const float sx = ld_nt(L.sp), sy = ld_nt(L.sp + 1), sz = ld_nt(L.sp + 2);
+            const float ex = ld_nt(L.ep), ey = ld_nt(L.ep + 1), ez = ld_nt(L.ep + 2);
+            if (K <= kRegSlots) {
+                // the hits are in registers: re-solve, order by (t, id) with a
+                // sorting network (unused entries sort last) and store once
+                int32_t id[kRegSlots];
+                float t[kRegSlots];
+                const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
 #pragma unroll
-            for (int k = 0; k < kRegSlots; ++k) {
-                id[k] = 0x7FFFFFFF;
-                t[k] = INFINITY;
-                if (k < L.count) {
+                for (int k = 0; k < kRegSlots; ++k) {
+                    id[k] = 0x7FFFFFFF;
+                    t[k] = INFINITY;
+                    if (k < L.count) {
+                        float v[9];
+                        int32_t tid;
+                        tri_load(a.tris, hp[k], v, tid);
+                        double tt, u, w;
+                        mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
+                        id[k] = tid;
+                        t[k] = (float)tt;
+                    }
+                }
+                auto cs = [&](int x, int y) {
+                    if (t[y] < t[x] || (t[y] == t[x] && id[y] < id[x])) {
+                        const float tf = t[x];
+                        t[x] = t[y];
+                        t[y] = tf;
+                        const int32_t tk = id[x];
+                        id[x] = id[y];
+                        id[y] = tk;
+                    }
+                };
+                cs(0, 1);
+                cs(2, 3);
+                cs(0, 2);
+                cs(1, 3);
+                cs(1, 2);
+#pragma unroll
+                for (int k = 0; k < kRegSlots; ++k)
+                    if (k >= L.count) id[k] = -1;
+                const bool vec = K == kRegSlots &&
+                                 ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
+                if (vec) {
+                    st_nt4(ids, id[0], id[1], id[2], id[3]);
+                    st_nt4(ts, t[0], t[1], t[2], t[3]);
+                } else {
+                    for (int c = 0; c < K; ++c) {
+                        st_nt(ids + c, id[c]);
+                        st_nt(ts + c, t[c]);
+                    }
+                }
+            } else {
+                for (int c = 0; c < L.count; ++c) {
                     float v[9];
                     int32_t tid;
-                    tri_load(a.tris, hp[k], v, tid);
+                    tri_load(a.tris, ids[c], v, tid);
                     double tt, u, w;
                     mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
-                    id[k] = tid;
-                    t[k] = (float)tt;
+                    ids[c] = tid;
+                    ts[c] = (float)tt;
+                }
+                // order by (t, id): insertion sort, lists are short
+                for (int x = 1; x < L.count; ++x) {
+                    const float kt = ts[x];
+                    const int32_t ki = ids[x];
+                    int y = x - 1;
+                    while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                        ts[y + 1] = ts[y];
+                        ids[y + 1] = ids[y];
+                        --y;
+                    }
+                    ts[y + 1] = kt;
+                    ids[y + 1] = ki;
+                }
+                for (int c = L.count; c < K; ++c) {
+                    st_nt(ids + c, -1);
+                    st_nt(ts + c, INFINITY);
                 }
             }
-            auto cs = [&](int x, int y) {
-                if (t[y] < t[x] || (t[y] == t[x] && id[y] < id[x])) {
-                    const float tf = t[x];
-                    t[x] = t[y];
-                    t[y] = tf;
-                    const int32_t tk = id[x];
-                    id[x] = id[y];
-                    id[y] = tk;
-                }
-            };
-            cs(0, 1);
-            cs(2, 3);
-            cs(0, 2);
-            cs(1, 3);
-            cs(1, 2);
+            if (soff) st_nt(soff + i, (int64_t)-1);
+        } else {
+            // more crossings than slots: reserve the full list's range in the
+            // pool and put the first K there; k_spill_place adds the arena
+            // records, k_spill_finish orders the list and fills the slots
+            int64_t off = -1;
+            if (L.e < a.ovf_cap) {
+                off = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&a.scalars[kOvfTotalLo]),
+                                         (unsigned long long)L.count);
+                a.ovf_seg[L.e] = L.item;
+                a.ovf_off[L.e] = off;
+                a.ovf_cnt[L.e] = L.count;
+                if (off + L.count <= a.o.pool_cap) {
+                    int32_t *q = a.o.pool_ids + off;
+                    if (K <= kRegSlots) {
+                        const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
 #pragma unroll
-            for (int k = 0; k < kRegSlots; ++k)
-                if (k >= L.count) id[k] = -1;
-            const bool vec = K == kRegSlots &&
-                             ((reinterpret_cast<uintptr_t>(a.o.ids) | reinterpret_cast<uintptr_t>(a.o.ts)) & 15) == 0;
-            if (vec) {
-                *reinterpret_cast<int4 *>(ids) = make_int4(id[0], id[1], id[2], id[3]);
-                *reinterpret_cast<float4 *>(ts) = make_float4(t[0], t[1], t[2], t[3]);
+                        for (int k = 0; k < kRegSlots; ++k)
+                            if (k < K) q[k] = hp[k];
+                    } else {
+                        for (int c = 0; c < K; ++c) q[c] = ids[c];
+                    }
+                } else {
+                    atomicOr(&a.scalars[kOvfFull], 1);
+                    off = -1;
+                }
             } else {
+                atomicOr(&a.scalars[kOvfFull], 1);
+            }
+            if (off < 0) {
+                // no room for the list: the slots say so (the count stays exact)
                 for (int c = 0; c < K; ++c) {
-                    ids[c] = id[c];
-                    ts[c] = t[c];
+                    ids[c] = -1;
+                    ts[c] = INFINITY;
                 }
             }
-        } else if (K <= kRegSlots) {
-            // more hits than slots: the spill pass writes the slots
-        } else if (L.count <= K) {
-            refine_list(a, sx, sy, sz, ex, ey, ez, ids, ts, n_in);
-            sort_slots(ids, ts, n_in);
-        }
-        if (K > kRegSlots) {
-            for (int c = n_in; c < K; ++c) {
-                ids[c] = -1;
-                ts[c] = INFINITY;
-            }
-        }
-        if (L.count > K) {
-            const int32_t e = atomicAdd(&a.scalars[kOvfSegs], 1);
-            const unsigned long long off = atomicAdd(
-                reinterpret_cast<unsigned long long *>(&a.scalars[kOvfTotalLo]), (unsigned long long)L.count);
-            if (e < a.ovf_cap) {
-                a.ovf_seg[e] = (int32_t)i;
-                a.ovf_cnt[e] = L.count;
-                a.ovf_off[e] = (int64_t)off;
-            }
+            if (soff) st_nt(soff + i, off);
         }
     }
 }
 
-// HYB: the stack may outgrow its LDS part (entries from lds_depth on live in
-// gstack); without it the whole stack is in LDS and the global path is not
-// compiled.  WIDE: walk the four-way view (Node4 records) instead of the
-// binary nodes; leaves and triangles are the same, so are the results.
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE>
+// RETRY: the deep pass.  Work items come from the retry queue (its length
+// is read on the device), and the stack continues past its LDS part into
+// device memory up to a bound on the tree height, so it never outgrows it
+// in a valid tree.  WIDE: walk the four-way view (Node4 records) instead of
+// the binary nodes; leaves and triangles are the same, so are the results.
+template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH, bool WIDE>
 __global__ __launch_bounds__(256) void k_query(QArgs a)
 {
+    constexpr bool HYB = RETRY;
     extern __shared__ int32_t lds_stack[];
     constexpr bool TOP = WIDE && !BATCH && top_copy(MODE);
     __shared__ uint4 top4[TOP ? 4 * kTopNodes : 4];
@@ -417,12 +476,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     }
     int32_t *const stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
-    int32_t *const work = &a.scalars[kWorkNext];
+    int32_t *const work = &a.scalars[RETRY ? kWorkRetry : kWorkNext];
     // stack entry k >= lds_depth lives at gstack[(k - lds_depth) * gstride + gtid]
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
     Lane L;
+    L.retry = false;
+    L.e = -1;
     // work items number below 2^30 (checked at the boundary), so item and
     // chunk arithmetic is 32-bit; the chunk bounds are wave-uniform
     int32_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
@@ -440,15 +501,22 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     // order in the binary walk, by child slot in the four-way walk
     int32_t leaf0 = 0, leaf1 = 0, leaf2 = 0, leaf3 = 0;
     // bound on a walk (a damaged tree can give wrong answers, never a hang):
-    // the wave counts its node-step rounds, each lane notes the round its
-    // segment started in, and every 64 rounds lanes past max_steps rounds stop
+    // each lane counts the node records it visits for its current segment; a
+    // walk of a valid tree visits every record at most once, so a count past
+    // the number of records can only come from a damaged tree.  Lanes check
+    // their count every 64 node-step rounds of the wave (behind a
+    // wave-uniform branch); a lane past the bound stops its walk and flags it.
     int32_t wround = 0;      // wave-uniform
-    int32_t start_round = 0;
+    int32_t vis = 0;
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
     unsigned long long w_blocked = 0, w_waiting = 0;               // wave-uniform
     int32_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
-    const int32_t n_items = (int32_t)a.n_items;
+    int32_t n_items = (int32_t)a.n_items;
+    if (RETRY) {
+        const int32_t q = a.scalars[kRetryN];
+        n_items = q < (int32_t)a.retry_cap ? q : (int32_t)a.retry_cap;
+    }
     bool exhausted = false;                 // the global counter has passed the last item
 
     for (;;) {
@@ -464,7 +532,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             ((int)__popcll(waiting) >= a.refill || ballot(item >= 0 && !done) == 0)) {
             if (COUNT) ++w_refill;
             if (done) {
-                finish<MODE, SPILL, BATCH>(a, L);
+                finish<MODE, RETRY, BATCH>(a, L);
                 item = -1;
             }
             const uint64_t idle = ballot(item == -1);
@@ -495,18 +563,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             if (item == -1) {
                 if (k >= 0) {
                     item = k;
-                    int32_t i = k;
+                    const int32_t it = RETRY ? a.retry_q[k] : k;
+                    int32_t i = it;
                     int32_t entry = (TOP && a.entry >= 0) ? kTopRef : a.entry;
-                    L.slot_base = (MODE & M_ALL) ? k * (int64_t)a.o.cap : 0;
-                    L.spill_cap = 0;
-                    if (SPILL) {
-                        i = a.ovf_seg[k];
-                        L.slot_base = a.ovf_off[k];
-                        L.spill_cap = a.ovf_cnt[k];
-                    }
                     if (BATCH) {
-                        const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
-                        i = (int32_t)(k - a.bt.seg_off[m]);
+                        const int32_t m = mesh_of(a.bt.seg_off, a.M, it);
+                        i = (int32_t)(it - a.bt.seg_off[m]);
                         L.mesh = m;
                         L.sp = a.bt.S[m] + 3 * (int64_t)i;
                         L.ep = a.bt.E[m] + 3 * (int64_t)i;
@@ -516,19 +578,24 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                         L.sp = a.S + 3 * (int64_t)i;
                         L.ep = a.E + 3 * (int64_t)i;
                     }
+                    L.item = it;
                     L.seg_i = i;
-                    L.seg = make_seg(L.sp[0], L.sp[1], L.sp[2], L.ep[0], L.ep[1], L.ep[2]);
+                    L.slot_base = (MODE & M_ALL) ? (int64_t)i * a.o.cap : 0;
+                    L.seg = make_seg(ld_nt(L.sp), ld_nt(L.sp + 1), ld_nt(L.sp + 2), ld_nt(L.ep), ld_nt(L.ep + 1),
+                                     ld_nt(L.ep + 2));
                     L.tlim = 1.0f;
                     L.best_t = INFINITY;
                     L.best_id = 0x7FFFFFFF;
                     L.best_pos = -1;
                     L.count = 0;
+                    L.e = -1;
                     L.found = false;
+                    L.retry = false;
                     node = entry;  // < 0 for an empty mesh: the segment misses
                     sp = 0;
                     sptr = stk;
-                    start_round = wround;
-                    if (COUNT) ++segs;
+                    vis = 0;
+                    if (COUNT && !RETRY) ++segs;
                 } else if (exhausted) {
                     item = -2;
                 }
@@ -536,16 +603,34 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         }
         if (ballot(item >= 0) == 0) break;
 
+        // a push that does not fit: in the main pass the walk stops and its
+        // segment goes to the deep pass; in the deep pass (a damaged tree
+        // only) the entry is dropped and flagged
+        auto overflow = [&]() {
+            if constexpr (RETRY) {
+                atomicOr(&a.scalars[kStackDropped], 1);
+            } else {
+                L.retry = true;
+            }
+        };
         auto push = [&](bool cond, int32_t child) {
             if constexpr (!HYB) {
-                if (cond && sptr < stk_end) {
-                    *sptr = child;
-                    sptr += stride;
+                if (cond) {
+                    if (sptr < stk_end) {
+                        *sptr = child;
+                        sptr += stride;
+                    } else {
+                        overflow();
+                    }
                 }
-            } else if (cond && sp < depth_off) {
-                if (sp < lds_off) stk[sp] = child;
-                else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = child;
-                sp += stride;
+            } else if (cond) {
+                if (sp < depth_off) {
+                    if (sp < lds_off) stk[sp] = child;
+                    else a.gstack[(int64_t)((sp - lds_off) / stride) * gstride + gtid] = child;
+                    sp += stride;
+                } else {
+                    overflow();
+                }
             }
         };
         auto pop = [&]() -> int32_t {
@@ -584,6 +669,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
             }
             if constexpr (WIDE) {
               if (want) {
+                ++vis;
                 uint4 P, Q, R;
                 int4 C;
                 if (TOP && node >= kTopRef) {
@@ -683,8 +769,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     push(p3, C.w);
                 }
                 node = near >= 0 ? near : pop();
+                if (!RETRY && L.retry) {
+                    // the stack is full: stop here, the deep pass takes over
+                    node = -1;
+                    leaf0 = leaf1 = leaf2 = leaf3 = 0;
+                }
               }
             } else if (want) {
+                ++vis;
                 const float4 *q = reinterpret_cast<const float4 *>(a.nodes + node);
                 const float4 q0 = q[0], q1 = q[1], q2 = q[2];
                 const int4 q3 = reinterpret_cast<const int4 *>(a.nodes + node)[3];
@@ -711,15 +803,20 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 const bool gl = hl && cl >= 0;
                 const bool gr = hr && cr >= 0;
                 // descend into the nearer internal child that was hit; push the
-                // other one when both were (a full stack, possible only in a
-                // damaged tree, drops it)
+                // other one when both were
                 const bool take_l = gl && (!gr || tl <= tr);
                 push(gl && gr, take_l ? cr : cl);
                 node = (gl || gr) ? (take_l ? cl : cr) : pop();
+                if (!RETRY && L.retry) {
+                    node = -1;
+                    leaf0 = leaf1 = leaf2 = 0;
+                }
             }
-            // the bound is checked every 64 rounds, behind a wave-uniform branch
             if (__builtin_expect((++wround & 63) == 0, 0)) {
-                if (wround - start_round >= a.max_steps) node = -1;
+                if (vis > a.max_steps) {
+                    node = -1;
+                    atomicOr(&a.scalars[kWalkCut], 1);
+                }
             }
         } while ((int)__popcll(w) >= a.defer);
 
@@ -732,7 +829,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 do {
                     const int32_t cur = leaf0 ? leaf0 : (leaf1 ? leaf1 : (leaf2 ? leaf2 : leaf3));
                     if (cur != 0) {
-                        const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, cur, tests);
+                        const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, cur, tests);
                         if (stop) {
                             leaf0 = leaf1 = leaf2 = leaf3 = 0;
                             node = -1;
@@ -749,7 +846,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 } while (ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
             } else do {
                 if (leaf0 != 0) {
-                    const bool stop = visit_leaf<MODE, SPILL, COUNT>(a, L, leaf0, tests);
+                    const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, leaf0, tests);
                     leaf0 = stop ? 0 : leaf1;
                     leaf1 = stop ? 0 : leaf2;
                     leaf2 = 0;
@@ -775,6 +872,117 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     }
 }
 
+// Segment and output arrays of work item `it` (a segment of a single mesh,
+// or a (mesh, segment) pair of a batch).
+template <bool BATCH>
+struct ItemView {
+    int64_t i;
+    const float *S, *E;
+    int32_t *ids;
+    float *ts;
+};
+template <bool BATCH>
+__device__ inline ItemView<BATCH> item_view(const QArgs &a, int64_t it)
+{
+    ItemView<BATCH> v;
+    if (BATCH) {
+        const int32_t m = mesh_of(a.bt.seg_off, a.M, it);
+        v.i = it - a.bt.seg_off[m];
+        v.S = a.bt.S[m];
+        v.E = a.bt.E[m];
+        v.ids = a.bt.ids[m];
+        v.ts = a.bt.ts[m];
+    } else {
+        v.i = it;
+        v.S = a.S;
+        v.E = a.E;
+        v.ids = a.o.ids;
+        v.ts = a.o.ts;
+    }
+    return v;
+}
+
+// All hits, after the walk: move every arena record (entry e, rank c,
+// sorted position) into slot c of its segment's reserved pool range.
+// Records of a void entry (a walk handed to the deep pass) are skipped.
+__global__ __launch_bounds__(256) void k_spill_place(QArgs a)
+{
+    const unsigned long long na = (uint32_t)a.scalars[kArenaLo] | ((unsigned long long)(uint32_t)a.scalars[kArenaHi] << 32);
+    const int64_t n = (int64_t)(na < (unsigned long long)a.arena_cap ? na : (unsigned long long)a.arena_cap);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+        const int4 rec = a.arena[r];
+        if (rec.x < 0 || rec.x >= a.ovf_cap) continue;
+        const int32_t cnt = a.ovf_cnt[rec.x];
+        if (cnt < 0 || rec.y >= cnt) continue;
+        const int64_t off = a.ovf_off[rec.x];
+        if (off < 0 || off + cnt > a.o.pool_cap) continue;
+        a.o.pool_ids[off + rec.y] = rec.z;
+    }
+}
+
+// All hits: one thread per overflowed segment re-solves its crossings in
+// FP64 (sorted positions become triangle ids), orders them by (t, id) in the
+// pool (shell sort, gaps 13, 4, 1, then insertion: lists are short) and
+// copies the first K into the segment's slots.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_spill_finish(QArgs a)
+{
+    const int32_t ne = a.scalars[kOvfSegs];
+    const int64_t n = ne < a.ovf_cap ? ne : a.ovf_cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int K = a.o.cap;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const int32_t cnt = a.ovf_cnt[e];
+        if (cnt < 0) continue;
+        const int64_t off = a.ovf_off[e];
+        if (off < 0 || off + cnt > a.o.pool_cap) continue;
+        const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
+        const float sx = v.S[3 * v.i], sy = v.S[3 * v.i + 1], sz = v.S[3 * v.i + 2];
+        const float ex = v.E[3 * v.i], ey = v.E[3 * v.i + 1], ez = v.E[3 * v.i + 2];
+        int32_t *ids = a.o.pool_ids + off;
+        float *ts = a.o.pool_ts + off;
+        for (int c = 0; c < cnt; ++c) {
+            // an entry no record reached (a full arena, reported) is never read through
+            const int32_t pos = ids[c];
+            if (pos < 0 || pos >= a.n_tris) {
+                ids[c] = 0x7FFFFFFF;
+                ts[c] = INFINITY;
+                continue;
+            }
+            float w[9];
+            int32_t id;
+            tri_load(a.tris, pos, w, id);
+            double t, u, vv;
+            mt_refine64(sx, sy, sz, ex, ey, ez, w, t, u, vv);
+            ids[c] = id;
+            ts[c] = (float)t;
+        }
+        const int gaps[3] = {13, 4, 1};
+        for (int g = 0; g < 3; ++g) {
+            const int gap = gaps[g];
+            for (int x = gap; x < cnt; ++x) {
+                const float kt = ts[x];
+                const int32_t ki = ids[x];
+                int y = x - gap;
+                while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                    ts[y + gap] = ts[y];
+                    ids[y + gap] = ids[y];
+                    y -= gap;
+                }
+                ts[y + gap] = kt;
+                ids[y + gap] = ki;
+            }
+        }
+        int32_t *sid = v.ids + v.i * (int64_t)K;
+        float *sts = v.ts + v.i * (int64_t)K;
+        for (int c = 0; c < K; ++c) {
+            sid[c] = ids[c];
+            sts[c] = ts[c];
+        }
+    }
+}
+
 __global__ void k_fill_miss(int64_t n_r, uint32_t mode, QueryOut o)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -792,6 +1000,7 @@ __global__ void k_fill_miss(int64_t n_r, uint32_t mode, QueryOut o)
             o.ids[i * (int64_t)o.cap + c] = -1;
             o.ts[i * (int64_t)o.cap + c] = INFINITY;
         }
+        if (o.spill_off) o.spill_off[i] = -1;
     }
 }
 
@@ -822,16 +1031,13 @@ __global__ void k_parity(const int32_t *__restrict__ count, int64_t n, uint8_t *
     if (i < n) inside[i] = (uint8_t)(count[i] & 1);
 }
 
-// Reset the work counter (and the overflow totals for a first all-hits pass)
-// with a kernel rather than a memset, so the sequence can be captured.
-__global__ void k_reset(int32_t *scalars, int reset_ovf, Counters *c)
+// Reset the per-query device scalars with a kernel rather than a memset, so
+// the sequence can be captured.
+__global__ void k_reset(int32_t *scalars, Counters *c)
 {
-    scalars[kWorkNext] = 0;
-    if (reset_ovf) {
-        scalars[kOvfSegs] = 0;
-        scalars[kOvfTotalLo] = 0;
-        scalars[kOvfTotalHi] = 0;
-    }
+    const int32_t zero[] = {kWorkNext, kWorkRetry, kRetryN, kRetryLost, kStackDropped, kWalkCut,
+                            kOvfSegs, kOvfTotalLo, kOvfTotalHi, kArenaLo, kArenaHi, kOvfFull};
+    for (int k = 0; k < (int)(sizeof(zero) / sizeof(zero[0])); ++k) scalars[zero[k]] = 0;
     if (c) {
         c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
         c->wave_loops = c->wave_node_steps = c->wave_leaf_phases = c->wave_refills = 0;
@@ -865,20 +1071,24 @@ __global__ __launch_bounds__(256) void k_refine_first(QArgs a)
         }
         const int32_t pos = tri[i];
         if (pos < 0) continue;
-        const float sx = S[3 * i], sy = S[3 * i + 1], sz = S[3 * i + 2];
-        const float ex = E[3 * i], ey = E[3 * i + 1], ez = E[3 * i + 2];
+        if (pos >= a.n_tris) {  // cannot come from a walk; never read through it
+            st_nt(tri + i, -1);
+            continue;
+        }
+        const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
+        const float ex = ld_nt(E + 3 * i), ey = ld_nt(E + 3 * i + 1), ez = ld_nt(E + 3 * i + 2);
         float v[9];
         int32_t id;
         tri_load(a.tris, pos, v, id);
         double t, u, w;
         mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-        tri[i] = id;
-        tt[i] = (float)t;
-        uv[2 * i] = (float)u;
-        uv[2 * i + 1] = (float)w;
-        pt[3 * i] = (float)((double)sx + t * ((double)ex - (double)sx));
-        pt[3 * i + 1] = (float)((double)sy + t * ((double)ey - (double)sy));
-        pt[3 * i + 2] = (float)((double)sz + t * ((double)ez - (double)sz));
+        st_nt(tri + i, id);
+        st_nt(tt + i, (float)t);
+        st_nt(uv + 2 * i, (float)u);
+        st_nt(uv + 2 * i + 1, (float)w);
+        st_nt(pt + 3 * i, (float)((double)sx + t * ((double)ex - (double)sx)));
+        st_nt(pt + 3 * i + 1, (float)((double)sy + t * ((double)ey - (double)sy)));
+        st_nt(pt + 3 * i + 2, (float)((double)sz + t * ((double)ez - (double)sz)));
     }
 }
 
@@ -890,65 +1100,84 @@ hipError_t launch_refine_first(const QArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH, bool HYB, bool WIDE>
+// Grid of the deep pass: a few workgroups per CU (the queue is short); its
+// device-memory stack holds one column per thread of this grid.
+constexpr int kRetryBlocksPerCU = 1;
+
+int device_cus()
+{
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    return n_cu > 0 ? n_cu : 1;
+}
+
+template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH, bool WIDE>
 hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    auto kern = k_query<MODE, SPILL, COUNT, BATCH, HYB, WIDE>;
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
-    if (e != hipSuccess) return e;
-    int dev = 0, n_cu = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    int64_t grid = (int64_t)per_cu * n_cu;
-    const int64_t need = (a.n_items + block - 1) / block;
-    if (grid > need) grid = need;
-    if (grid < 1) grid = 1;
-    // the global part of the stack must hold every resident thread's column
-    if (a.lds_depth < a.depth && (a.gstack == nullptr || grid * block * (int64_t)(a.depth - a.lds_depth) >
-                                                             a.gstack_cap))
-        return hipErrorInvalidValue;
+    auto kern = k_query<MODE, RETRY, COUNT, BATCH, WIDE>;
+    int64_t grid;
     QArgs b = a;
-    if (b.chunk <= 0) {
-        // about eight chunks per resident wave keeps the tail short while the
-        // global counter sees one atomic per chunk
-        const int64_t waves = grid * (block / 64);
-        int64_t c = (a.n_items + 8 * waves - 1) / (8 * waves);
-        c = (c + 63) / 64 * 64;
-        b.chunk = (int32_t)(c < 64 ? 64 : (c > 4096 ? 4096 : c));
+    if (RETRY) {
+        grid = (int64_t)kRetryBlocksPerCU * device_cus();
+        if (a.lds_depth < a.depth && (a.gstack == nullptr || grid * block * (int64_t)(a.depth - a.lds_depth) >
+                                                                 a.gstack_cap))
+            return hipErrorInvalidValue;
+        b.chunk = 64;
+    } else {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        grid = (int64_t)per_cu * device_cus();
+        const int64_t need = (a.n_items + block - 1) / block;
+        if (grid > need) grid = need;
+        if (grid < 1) grid = 1;
+        if (b.chunk <= 0) {
+            // about eight chunks per resident wave keeps the tail short while the
+            // global counter sees one atomic per chunk
+            const int64_t waves = grid * (block / 64);
+            int64_t c = (a.n_items + 8 * waves - 1) / (8 * waves);
+            c = (c + 63) / 64 * 64;
+            b.chunk = (int32_t)(c < 64 ? 64 : (c > 4096 ? 4096 : c));
+        }
     }
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, s, b);
     return hipGetLastError();
 }
 
-template <uint32_t MODE, bool SPILL, bool COUNT, bool BATCH = false>
+template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH = false>
 hipError_t launch_mode(const QArgs &a, int block, size_t lds, hipStream_t s)
 {
-    if (a.nodes4) {
-        if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true, true>(a, block, lds, s);
-        return launch_kernel<MODE, SPILL, COUNT, BATCH, false, true>(a, block, lds, s);
-    }
-    if (a.lds_depth < a.depth) return launch_kernel<MODE, SPILL, COUNT, BATCH, true, false>(a, block, lds, s);
-    return launch_kernel<MODE, SPILL, COUNT, BATCH, false, false>(a, block, lds, s);
+    if (a.nodes4) return launch_kernel<MODE, RETRY, COUNT, BATCH, true>(a, block, lds, s);
+    return launch_kernel<MODE, RETRY, COUNT, BATCH, false>(a, block, lds, s);
+}
+
+// The main pass, then the deep pass over the segments it queued.
+template <uint32_t MODE, bool COUNT, bool BATCH = false>
+hipError_t launch_passes(const QArgs &main, const QArgs &deep, int block, size_t lds, hipStream_t s)
+{
+    hipError_t e = launch_mode<MODE, false, COUNT, BATCH>(main, block, lds, s);
+    if (e == hipSuccess) e = launch_mode<MODE, true, COUNT, BATCH>(deep, block, lds, s);
+    return e;
 }
 
 template <bool COUNT>
-hipError_t dispatch(uint32_t mode, const QArgs &a, int block, size_t lds, hipStream_t s)
+hipError_t dispatch(uint32_t mode, const QArgs &a, const QArgs &d, int block, size_t lds, hipStream_t s)
 {
     // RSI_BOOL is derived for free whenever a full pass runs
     switch (mode) {
-    case M_BOOL: return launch_mode<M_BOOL, false, COUNT>(a, block, lds, s);
-    case M_FIRST: return launch_mode<M_FIRST, false, COUNT>(a, block, lds, s);
-    case M_FIRST | M_BOOL: return launch_mode<M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
-    case M_ALL: return launch_mode<M_ALL, false, COUNT>(a, block, lds, s);
-    case M_ALL | M_BOOL: return launch_mode<M_ALL | M_BOOL, false, COUNT>(a, block, lds, s);
-    case M_ALL | M_FIRST: return launch_mode<M_ALL | M_FIRST, false, COUNT>(a, block, lds, s);
-    case M_ALL | M_FIRST | M_BOOL: return launch_mode<M_ALL | M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
-    case M_COUNT: return launch_mode<M_COUNT, false, COUNT>(a, block, lds, s);
-    case M_COUNT | M_BOOL: return launch_mode<M_COUNT | M_BOOL, false, COUNT>(a, block, lds, s);
-    case M_COUNT | M_FIRST: return launch_mode<M_COUNT | M_FIRST, false, COUNT>(a, block, lds, s);
-    case M_COUNT | M_FIRST | M_BOOL: return launch_mode<M_COUNT | M_FIRST | M_BOOL, false, COUNT>(a, block, lds, s);
+    case M_BOOL: return launch_passes<M_BOOL, COUNT>(a, d, block, lds, s);
+    case M_FIRST: return launch_passes<M_FIRST, COUNT>(a, d, block, lds, s);
+    case M_FIRST | M_BOOL: return launch_passes<M_FIRST | M_BOOL, COUNT>(a, d, block, lds, s);
+    case M_ALL: return launch_passes<M_ALL, COUNT>(a, d, block, lds, s);
+    case M_ALL | M_BOOL: return launch_passes<M_ALL | M_BOOL, COUNT>(a, d, block, lds, s);
+    case M_ALL | M_FIRST: return launch_passes<M_ALL | M_FIRST, COUNT>(a, d, block, lds, s);
+    case M_ALL | M_FIRST | M_BOOL: return launch_passes<M_ALL | M_FIRST | M_BOOL, COUNT>(a, d, block, lds, s);
+    case M_COUNT: return launch_passes<M_COUNT, COUNT>(a, d, block, lds, s);
+    case M_COUNT | M_BOOL: return launch_passes<M_COUNT | M_BOOL, COUNT>(a, d, block, lds, s);
+    case M_COUNT | M_FIRST: return launch_passes<M_COUNT | M_FIRST, COUNT>(a, d, block, lds, s);
+    case M_COUNT | M_FIRST | M_BOOL: return launch_passes<M_COUNT | M_FIRST | M_BOOL, COUNT>(a, d, block, lds, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -962,26 +1191,25 @@ int fit_block(int want, int depth)
     return b;
 }
 
-// Traversal-stack entries a lane can need: one pushed sibling per binary
-// level (height + 1); in the four-way walk up to three per four-way level,
-// of which there are at most (height + 2) / 2 + 1.
-int full_depth(const rsi_bvh *h)
+// Traversal-stack entries a lane can need for a tree of the given height:
+// one pushed sibling per binary level (height + 1); in the four-way walk up
+// to three per four-way level, of which there are at most (height + 2) / 2 + 1.
+int stack_need(int height, int width)
 {
-    if (h->width_built == 4) return 3 * ((h->height + 2) / 2 + 1) + 1;
-    return h->height + 1;
+    if (width == 4) return 3 * ((height + 2) / 2 + 1) + 1;
+    return height + 1;
 }
 
-// LDS part of the stack: the whole stack unless a smaller cap is set; the
-// four-way walk keeps 20 entries in LDS by default (its worst-case depth is
-// about 1.5x the binary one while typical walks stay far below it; 20
-// entries of 128 lanes leave room for eight waves per SIMD), 17 when the
-// walk also holds the 1,344-byte copy of the top records (`top`).
+// LDS stack entries per lane of the main pass: the `stack_depth` option, or
+// 20 on the four-way walk (17 when the walk also holds the 1,344-byte copy
+// of the top records), 32 on the binary walk; never more than the bound.
 int lds_part(const rsi_bvh *h, bool top)
 {
-    const int depth = full_depth(h);
+    const int width = h->width_built;
+    const int bound = stack_need(h->height_bound, width);
     int cap = h->stack_cap;
-    if (cap <= 0 && h->width_built == 4) cap = top ? 17 : 20;
-    return (cap > 0 && cap < depth) ? cap : depth;
+    if (cap <= 0) cap = width == 4 ? (top ? 17 : 20) : 32;
+    return cap < bound ? cap : bound;
 }
 
 QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, const QueryOut &o)
@@ -990,6 +1218,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.nodes = h->nodes;
     a.nodes4 = h->width_built == 4 ? h->nodes4 : nullptr;
     a.tris = h->tris;
+    a.n_tris = (int32_t)h->n_t;
     a.entry = h->n_t > 0 ? (int32_t)(h->h_tri_off[1] - 1) : -1;
     a.S = S;
     a.E = E;
@@ -999,15 +1228,17 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.ovf_cnt = h->ovf_cnt;
     a.ovf_off = h->ovf_off;
     a.ovf_cap = h->ovf_cap;
+    a.arena = h->arena;
+    a.arena_cap = h->arena_cap;
     a.scalars = h->scalars;
-    a.pool_ids = h->pool_ids;
-    a.pool_ts = h->pool_ts;
     a.counters = h->counters;
-    a.depth = full_depth(h);
-    a.lds_depth = lds_part(h, false);  // launches that differ set their own
-    a.gstack = h->gstack;
-    a.gstack_cap = h->gstack_cap;
-    a.max_steps = (int32_t)(h->n_t + 1);
+    a.depth = 0;
+    a.lds_depth = 0;
+    a.gstack = h->retry_stack;
+    a.gstack_cap = h->retry_stack_cap;
+    a.retry_q = h->retry_q;
+    a.retry_cap = h->retry_cap;
+    a.max_steps = (int32_t)(h->n_t > 0 ? h->n_t : 1);
     a.defer = h->defer_lanes;
     a.refill = h->refill_lanes;
     a.chunk = h->chunk;
@@ -1015,6 +1246,27 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.mesh_entry = h->mesh_entry;
     a.bt = h->bt;
     return a;
+}
+
+// Arguments of the two passes: the main pass keeps its whole stack (ld
+// entries) in LDS; the deep pass has the same LDS part and continues in
+// device memory up to the height bound.
+void pass_args(const rsi_bvh *h, QArgs &main, QArgs &deep, int ld)
+{
+    main.depth = main.lds_depth = ld;
+    deep = main;
+    deep.depth = stack_need(h->height_bound, h->width_built);
+    deep.lds_depth = ld;
+    if (deep.depth < ld) deep.depth = ld;
+}
+
+hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
+{
+    const unsigned grid = (unsigned)(2 * device_cus());
+    hipLaunchKernelGGL(k_spill_place, dim3(grid), dim3(256), 0, s, a);
+    if (batch) hipLaunchKernelGGL(k_spill_finish<true>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_spill_finish<false>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1026,68 +1278,114 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
     const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
-    QArgs a = make_args(h, S, E, n_r, o);
-    a.lds_depth = ld;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, (mode & M_ALL) ? 1 : 0,
-                       h->counting ? h->counters : nullptr);
-    hipError_t e = h->counting ? dispatch<true>(mode, a, block, lds, s) : dispatch<false>(mode, a, block, lds, s);
+    QArgs a = make_args(h, S, E, n_r, o), d;
+    pass_args(h, a, d, ld);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, h->counting ? h->counters : nullptr);
+    hipError_t e = h->counting ? dispatch<true>(mode, a, d, block, lds, s) : dispatch<false>(mode, a, d, block, lds, s);
     if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<false>(a, s);
+    if (e == hipSuccess && (mode & M_ALL)) e = launch_all_hits_tail(a, false, s);
     return e;
 }
 
-hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mode, const QueryOut &o,
-                        hipStream_t s)
-{
-    (void)mode;
-    const int64_t n = h->last_ovf_segs;
-    if (n == 0) return hipSuccess;
-    const int ld = lds_part(h, false);
-    const int block = fit_block(h->block_size, ld);
-    const size_t lds = (size_t)block * ld * sizeof(int32_t);
-    QArgs a = make_args(h, S, E, n, o);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
-    return launch_mode<M_ALL, true, false>(a, block, lds, s);
-}
-
-hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s)
+hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, int32_t cap,
+                              hipStream_t s)
 {
     if (n_total == 0) return hipSuccess;
     const int ld = lds_part(h, false);
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QueryOut o = {};
-    QArgs a = make_args(h, nullptr, nullptr, n_total, o);
+    o.cap = cap;
+    o.pool_ids = h->pool_ids;
+    o.pool_ts = h->pool_ts;
+    o.pool_cap = h->pool_cap;
+    QArgs a = make_args(h, nullptr, nullptr, n_total, o), d;
     a.bt = bt;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, 0, nullptr);
+    pass_args(h, a, d, ld);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr);
     hipError_t e;
     switch (mode) {
-    case M_BOOL: e = launch_mode<M_BOOL, false, false, true>(a, block, lds, s); break;
-    case M_FIRST: e = launch_mode<M_FIRST, false, false, true>(a, block, lds, s); break;
-    case M_FIRST | M_BOOL: e = launch_mode<M_FIRST | M_BOOL, false, false, true>(a, block, lds, s); break;
+    case M_BOOL: e = launch_passes<M_BOOL, false, true>(a, d, block, lds, s); break;
+    case M_FIRST: e = launch_passes<M_FIRST, false, true>(a, d, block, lds, s); break;
+    case M_FIRST | M_BOOL: e = launch_passes<M_FIRST | M_BOOL, false, true>(a, d, block, lds, s); break;
+    case M_ALL: e = launch_passes<M_ALL, false, true>(a, d, block, lds, s); break;
+    case M_ALL | M_BOOL: e = launch_passes<M_ALL | M_BOOL, false, true>(a, d, block, lds, s); break;
+    case M_ALL | M_FIRST: e = launch_passes<M_ALL | M_FIRST, false, true>(a, d, block, lds, s); break;
+    case M_ALL | M_FIRST | M_BOOL: e = launch_passes<M_ALL | M_FIRST | M_BOOL, false, true>(a, d, block, lds, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<true>(a, s);
+    if (e == hipSuccess && (mode & M_ALL)) e = launch_all_hits_tail(a, true, s);
     return e;
 }
 
-hipError_t ensure_gstack(rsi_bvh *h)
+// A captured graph holds the addresses of the handle's scratch: before any
+// of it is reallocated, wait for the device and release the graph (a replay
+// then reports that nothing is captured).
+static hipError_t release_graph(rsi_bvh *h)
 {
-    const int depth = full_depth(h);
-    const int ld = lds_part(h, true);  // the smaller LDS part: the longer tail
-    if (ld >= depth) return hipSuccess;
-    int dev = 0, n_cu = 0, max_threads = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&max_threads, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev);
-    if (e != hipSuccess) return e;
-    // every thread the GPU can hold at once, times the entries beyond the LDS part
-    const int64_t need = (int64_t)n_cu * max_threads * (depth - ld);
-    if (h->gstack_cap >= need) return hipSuccess;
-    if (h->gstack) (void)hipFree(h->gstack);
-    h->gstack = nullptr;
-    h->gstack_cap = 0;
-    e = hipMalloc(reinterpret_cast<void **>(&h->gstack), sizeof(int32_t) * (size_t)need);
-    if (e == hipSuccess) h->gstack_cap = need;
+    if (!h->graph) return hipSuccess;
+    hipError_t e = hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    return e;
+}
+
+hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
+{
+    hipError_t e = hipSuccess;
+    auto grow = [&](auto **p, int64_t &cap, int64_t want, size_t elem) {
+        if (e != hipSuccess || cap >= want) return;
+        if ((e = release_graph(h)) != hipSuccess) return;
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        cap = 0;
+        e = hipMalloc(reinterpret_cast<void **>(p), elem * (size_t)(want > 0 ? want : 1));
+        if (e == hipSuccess) cap = want;
+    };
+    grow(&h->retry_q, h->retry_cap, n, sizeof(int32_t));
+    // deep-pass stack: every thread of its grid, entries past the LDS part
+    {
+        const int width = h->width_built;
+        const int ld_min = lds_part(h, width == 4);  // the smaller LDS part: the longer tail
+        const int need = stack_need(h->height_bound, width);
+        const int64_t want =
+            need > ld_min ? (int64_t)kRetryBlocksPerCU * device_cus() * h->block_size * (need - ld_min) : 1;
+        grow(&h->retry_stack, h->retry_stack_cap, want, sizeof(int32_t));
+    }
+    if (all_hits) {
+        // one entry per segment, plus room for the entries that walks handed
+        // to the deep pass leave void
+        const int64_t want = n + n / 8 + 1024;
+        if (h->ovf_cap < want) {
+            // the three arrays share one capacity: it holds only once all grew
+            int64_t c0 = 0, c1 = 0, c2 = 0;
+            h->ovf_cap = 0;
+            grow(&h->ovf_seg, c0, want, sizeof(int32_t));
+            grow(&h->ovf_cnt, c1, want, sizeof(int32_t));
+            grow(&h->ovf_off, c2, want, sizeof(int64_t));
+            if (e == hipSuccess) h->ovf_cap = want;
+        }
+        const int64_t arena_want = h->pool_want > (n / 4 > (1 << 20) ? n / 4 : (1 << 20)) ? h->pool_want
+                                   : (n / 4 > (1 << 20) ? n / 4 : (1 << 20));
+        grow(&h->arena, h->arena_cap, arena_want, sizeof(int4));
+    }
+    return e;
+}
+
+hipError_t ensure_pool(rsi_bvh *h, int64_t n)
+{
+    if (h->pool_cap >= n) return hipSuccess;
+    hipError_t g = release_graph(h);
+    if (g != hipSuccess) return g;
+    if (h->pool_ids) (void)hipFree(h->pool_ids);
+    if (h->pool_ts) (void)hipFree(h->pool_ts);
+    h->pool_ids = nullptr;
+    h->pool_ts = nullptr;
+    h->pool_cap = 0;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&h->pool_ids), sizeof(int32_t) * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&h->pool_ts), sizeof(float) * (size_t)n);
+    if (e == hipSuccess) h->pool_cap = n;
     return e;
 }
 
@@ -1103,6 +1401,12 @@ hipError_t launch_parity(const int32_t *count, int64_t n, uint8_t *inside, hipSt
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_parity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, count, n, inside);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_query(rsi_bvh *h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr);
     return hipGetLastError();
 }
 

@@ -16,11 +16,19 @@ namespace rsi {
 enum Scalar {
     kBadIndex = 6,     // nonzero if a triangle index was out of range (1) or the build state was inconsistent (2)
     kBadGather = 7,    // nonzero if a batch gather met a triangle index outside its mesh
-    kOvfSegs = 9,      // overflowed segments of the last all-hits pass
-    kOvfTotalLo = 10,  // 64-bit total crossings of those segments (lo, hi words)
+    kOvfSegs = 9,      // all hits: entries taken in the overflow table (segments with more crossings than slots)
+    kOvfTotalLo = 10,  // 64-bit total crossings of those segments: pool entries reserved (lo, hi words)
     kOvfTotalHi = 11,
-    kWorkNext = 12,    // next unclaimed work item of the running query kernel
+    kWorkNext = 12,    // next unclaimed work item of the running main query pass
+    kWalkCut = 13,     // walks stopped by the node-visit bound (damaged tree)
+    kArenaLo = 14,     // 64-bit count of arena records written during the walk (lo, hi words)
+    kArenaHi = 15,
     kSegBounds = 16,   // 6 ordered ints: bounding box of segment midpoints (segment order)
+    kRetryN = 22,      // segments whose stack outgrew its LDS part, queued for the deep pass
+    kWorkRetry = 23,   // next unclaimed item of the deep pass
+    kRetryLost = 24,   // retry queue full (cannot happen with a queue of one entry per segment)
+    kStackDropped = 25,  // pushes dropped by the deep pass (only a damaged tree is that deep)
+    kOvfFull = 26,     // the overflow table, arena or pool was too small: lists incomplete
     kNumScalars = 32
 };
 
@@ -37,7 +45,6 @@ struct SortScratch {
     uint64_t *keys_alt = nullptr;
     uint32_t *vals_alt = nullptr;
     uint32_t *hist = nullptr;
-    uint32_t *h_word = nullptr;  // pinned host word: a read-back of the sort
     int64_t cap = 0;
     int64_t hist_cap = 0;
 };
@@ -52,6 +59,10 @@ struct BatchTables {
     float **t = nullptr;
     float **uv = nullptr;
     float **point = nullptr;
+    int32_t **count = nullptr;
+    int32_t **ids = nullptr;
+    float **ts = nullptr;
+    int64_t **spill_off = nullptr;
 };
 
 }  // namespace rsi
@@ -67,11 +78,9 @@ struct rsi_bvh {
     int32_t defer_lanes = 32;
     int32_t refill_lanes = 32;
     int32_t chunk = 0;             // 0: sized per launch
-    int32_t stack_cap = 0;         // LDS part of the traversal stack (0: the whole stack)
-    int32_t height = 0;            // largest tree height over the meshes
+    int32_t stack_cap = 0;         // LDS stack entries per lane of the main pass (0: default)
     bool counting = false;
     std::vector<int64_t> h_tri_off, h_vert_off;  // host copies of the offsets
-    std::vector<int32_t> h_height;
 
     // mesh tables (device)
     int64_t *tri_off = nullptr;    // [M+1]
@@ -100,16 +109,32 @@ struct rsi_bvh {
     rsi::Counters *counters = nullptr;
     rsi::SortScratch sort;
 
-    // all-hits overflow (device)
-    int32_t *ovf_seg = nullptr;    // overflowed segment ids
-    int32_t *ovf_cnt = nullptr;    // their counts
-    int64_t *ovf_off = nullptr;    // their offsets into the pool
+    // all-hits lists beyond the slots (device): the overflow table (one
+    // entry per overflowed segment: work item, count, pool offset), the arena
+    // of (entry, rank, sorted position) records written during the walk, and
+    // the library's pool of full lists (used when the caller passes none)
+    int32_t *ovf_seg = nullptr;
+    int32_t *ovf_cnt = nullptr;
+    int64_t *ovf_off = nullptr;
     int64_t ovf_cap = 0;
+    int4 *arena = nullptr;
+    int64_t arena_cap = 0;
     int32_t *pool_ids = nullptr;
     float *pool_ts = nullptr;
     int64_t pool_cap = 0;
-    int64_t last_ovf_segs = 0;
-    int64_t last_ovf_total = 0;
+    int64_t pool_want = 0;         // pool entries the last overflowing query needed (grown to on the next query)
+    int32_t *last_pool_ids = nullptr;  // pool of the last all-hits query (the caller's or the library's)
+    float *last_pool_ts = nullptr;
+    int64_t last_pool_cap = 0;
+
+    // walks whose stack outgrew its LDS part: queue of work items and the
+    // device-memory stack of the deep pass (a small fixed grid)
+    int32_t *retry_q = nullptr;
+    int64_t retry_cap = 0;
+    int32_t *retry_stack = nullptr;
+    int64_t retry_stack_cap = 0;
+    int32_t height_bound = 0;      // bound on any tree height of the handle's meshes (sizes the deep pass)
+    hipStream_t last_stream = nullptr;  // stream of the last enqueued call (waited on by rsi_query_stats)
 
     // batched queries (device tables, sized for M meshes): `bt` serves the
     // eager calls, `bt_graph` belongs to the captured graph, so an eager call
@@ -125,17 +150,25 @@ struct rsi_bvh {
     int32_t width_built = 2;
     rsi::Node4 *nodes4 = nullptr;
 
-    // global part of the traversal stack when stack_cap is below the height
-    int32_t *gstack = nullptr;
-    int64_t gstack_cap = 0;
-
-    // segment order (and the adjoint's hit order): keys, values and sort
+    // segment order (and the adjoint's cell grouping): keys, values and sort
     // scratch sized for the segments
     uint64_t *seg_keys = nullptr;
     int64_t seg_key_cap = 0;
     uint32_t *adj_vals = nullptr;
     int64_t adj_val_cap = 0;
     rsi::SortScratch seg_sort;
+    // first-hit adjoint: per-segment records, per-triangle sums (FP64) and
+    // the vertex incidence table of the current topology
+    float4 *adj_rec = nullptr;
+    int64_t adj_rec_cap = 0;
+    float *adj_rec_v = nullptr;
+    int64_t adj_rec_v_cap = 0;
+    double *tri_sum = nullptr;
+    int64_t tri_sum_cap = 0;
+    uint64_t *inc_keys = nullptr;
+    uint32_t *inc_vals = nullptr;
+    int64_t inc_cap = 0;
+    bool inc_valid = false;
 
     // stream compaction: per-block counts and their scan (+ total)
     int32_t *compact_counts = nullptr;
@@ -148,10 +181,6 @@ struct rsi_bvh {
 
     // pinned host mirror of `scalars`
     int32_t *h_scalars = nullptr;
-    // pinned host block that k_publish fills after a build: the two index
-    // flags, then the M tree heights; d_pub is its device-side address
-    int32_t *h_pub = nullptr;
-    int32_t *d_pub = nullptr;
 };
 
 namespace rsi {
@@ -163,13 +192,15 @@ void set_error(const std::string &msg);
 hipError_t launch_gather(rsi_bvh *h, hipStream_t s);
 hipError_t launch_build(rsi_bvh *h, const float *V, hipStream_t s);
 hipError_t launch_refit(rsi_bvh *h, const float *V, hipStream_t s);
-hipError_t launch_publish(rsi_bvh *h, hipStream_t s);
 
-// sort.hip: stable LSD radix sort of 63-bit keys with 32-bit values, in
-// place; with mesh_off (M > 1) the mesh of each value is the most
-// significant digit
+// sort.hip: stable LSD radix sort of (key, value) pairs by key bits
+// [first_bit, key_bits), in place; with mesh_off (M > 1) the mesh of each
+// value is the most significant digit.  With kres and vres the result may
+// be left in the scratch buffers instead of being copied back: *kres, *vres
+// then name the arrays that hold it.
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &scratch,
-                            hipStream_t s, const int64_t *mesh_off = nullptr, int32_t M = 1);
+                            hipStream_t s, const int64_t *mesh_off = nullptr, int32_t M = 1, int first_bit = 0,
+                            uint64_t **kres = nullptr, uint32_t **vres = nullptr);
 hipError_t ensure_sort_scratch(SortScratch &scratch, int64_t n);
 void free_sort_scratch(SortScratch &scratch);
 
@@ -181,12 +212,16 @@ struct QueryOut {
     int32_t *count, *ids;
     float *ts;
     int32_t cap;
+    int64_t *spill_off;  // optional: per segment, offset of its full list in the pool (-1: none)
+    int32_t *pool_ids;   // pool of the full lists of overflowed segments (caller's or the library's)
+    float *pool_ts;
+    int64_t pool_cap;
 };
 hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
                         const QueryOut &o, hipStream_t s);
-hipError_t launch_spill(rsi_bvh *h, const float *S, const float *E, uint32_t mode, const QueryOut &o,
-                        hipStream_t s);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);
+// zero the per-query device scalars (a query that launches no walk)
+hipError_t launch_clear_query(rsi_bvh *h, hipStream_t s);
 hipError_t launch_widen(rsi_bvh *h, hipStream_t s);
 hipError_t launch_segment_order(rsi_bvh *h, const float *S, const float *E, int64_t n, int32_t *order,
                                 hipStream_t s);
@@ -197,9 +232,13 @@ hipError_t launch_compact(rsi_bvh *h, const uint8_t *hit, const float *S, const 
                           int32_t *tri_out, float *point_out, int64_t *n_out, hipStream_t s);
 hipError_t launch_inside_ends(const rsi_bvh *h, const float *P, int64_t n, float *E, hipStream_t s);
 hipError_t launch_parity(const int32_t *count, int64_t n, uint8_t *inside, hipStream_t s);
-hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, hipStream_t s);
-// size the global part of the traversal stack (call outside graph capture)
-hipError_t ensure_gstack(rsi_bvh *h);
+hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total, uint32_t mode, int32_t cap,
+                              hipStream_t s);
+// device memory of a query over n work items: retry queue, deep-pass stack
+// and, for all hits, the overflow table and arena (call outside capture)
+hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits);
+// size the library's pool of full lists for at least n entries
+hipError_t ensure_pool(rsi_bvh *h, int64_t n);
 
 // adjoint.hip
 hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, const float *E, int64_t n_r,

@@ -22,15 +22,19 @@
 #include <stdint.h>
 
 #include "rsi_host.h"
+#include "rsi_rank.h"
 
 namespace rsi {
 namespace {
 
-constexpr int kThreads = 256;
+using rank::kThreads;
+using rank::kRadix;
+using rank::kWaves;
+using rank::lanemask_lt;
+using rank::scan256;
+using rank::rank_tile;
 constexpr int kItems = 8;                // elements per thread in large sorts
 constexpr int kTile = kThreads * kItems;
-constexpr int kRadix = 256;
-constexpr int kWaves = kThreads / 64;
 constexpr int kFusedTiles = 64;  // up to this many tiles each workgroup scans the histograms itself
 
 // Digit of an element for one pass: 8 bits of the key, or (for batches)
@@ -144,33 +148,6 @@ __global__ __launch_bounds__(256) void k_part_apply(uint32_t *__restrict__ a, in
     for (int k = 0; k < 16; ++k) {
         if (base + k < n) a[base + k] = run;
         run += v[k];
-    }
-}
-
-__device__ inline uint64_t lanemask_lt()
-{
-    const uint32_t lane = __lane_id();
-    return lane ? (~0ull >> (64 - lane)) : 0ull;
-}
-
-// Exclusive scan of 256 per-digit values held one per thread, done by the
-// first wave (four digits per lane).
-__device__ inline void scan256(const uint32_t *in, uint32_t *out)
-{
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        uint32_t c0 = in[4 * tid], c1 = in[4 * tid + 1], c2 = in[4 * tid + 2], c3 = in[4 * tid + 3];
-        uint32_t s4 = c0 + c1 + c2 + c3;
-        uint32_t incl = s4;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t v = __shfl_up(incl, off, 64);
-            if ((int)__lane_id() >= off) incl += v;
-        }
-        uint32_t ex = incl - s4;
-        out[4 * tid] = ex;
-        out[4 * tid + 1] = ex + c0;
-        out[4 * tid + 2] = ex + c0 + c1;
-        out[4 * tid + 3] = ex + c0 + c1 + c2;
     }
 }
 
@@ -291,60 +268,6 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         vout[dst] = v;
         if (FUSED && hnext) atomicAdd(&hnext[(int64_t)dnext(k, v) * ntiles + dst / (kThreads * IPT)], 1u);
     }
-}
-
-// Stable rank of one tile held in registers (item r of thread x is tile
-// element r * kThreads + x; `valid` marks live elements): on return pos[r]
-// is the item's position in the tile ordered by digit (ties in tile order),
-// run[d] the tile's count of digit d and start[d] its exclusive scan.
-// `wcnt` is LDS scratch of IPT * kWaves * kRadix words.
-template <int IPT>
-__device__ inline void rank_tile(const uint32_t (&dig)[IPT], const bool (&valid)[IPT], uint32_t (&pos)[IPT],
-                                 uint32_t *wcnt, uint32_t *run, uint32_t *start)
-{
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcnt[(r * kWaves + w) * kRadix + tid] = 0;
-    __syncthreads();
-    // per round: the lanes of this wave holding the same digit (8 ballots);
-    // the lowest of them records the group size
-    uint32_t below[IPT];
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t d = dig[r];
-        uint64_t peers = __ballot(valid[r]);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        below[r] = (uint32_t)__popcll(peers & lt);
-        if (valid[r] && below[r] == 0) wcnt[(r * kWaves + wave) * kRadix + d] = (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    // digit tid: exclusive prefix over (round, wave) in tile order
-    {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int r = 0; r < IPT; ++r)
-#pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = wcnt[(r * kWaves + w) * kRadix + tid];
-                wcnt[(r * kWaves + w) * kRadix + tid] = acc;
-                acc += c;
-            }
-        run[tid] = acc;
-    }
-    __syncthreads();
-    scan256(run, start);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) pos[r] = start[dig[r]] + wcnt[(r * kWaves + wave) * kRadix + dig[r]] + below[r];
 }
 
 // A bucket of at most IPT * kThreads elements: all low passes in LDS.
@@ -499,20 +422,6 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(uint64_t *__restrict__
         sort_bucket_global(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, gcount, gbase);
 }
 
-// Largest bucket of a scanned top-digit table (one workgroup of 256).
-__global__ __launch_bounds__(kThreads) void k_bucket_max(const uint32_t *__restrict__ hist, int ntiles, int64_t n,
-                                                         uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t m[kWaves];
-    const int d = threadIdx.x;
-    const uint32_t end = d + 1 < kRadix ? hist[(int64_t)(d + 1) * ntiles] : (uint32_t)n;
-    uint32_t size = end - hist[(int64_t)d * ntiles];
-    for (int off = 32; off > 0; off >>= 1) size = max(size, (uint32_t)__shfl_xor(size, off, 64));
-    if (__lane_id() == 0) m[d >> 6] = size;
-    __syncthreads();
-    if (d == 0) out[0] = max(max(m[0], m[1]), max(m[2], m[3]));
-}
-
 __global__ void k_copy_pairs(const uint64_t *__restrict__ ks, const uint32_t *__restrict__ vs,
                              uint64_t *__restrict__ kd, uint32_t *__restrict__ vd, int64_t n)
 {
@@ -541,8 +450,7 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
     const int64_t ntiles = (n + kTile - 1) / kTile;
     // fused path: three rotating histograms; else one table plus the
     // partial sums of the three-launch scan
-    // (plus one word for the largest bucket of a bucket sort)
-    const int64_t hn = 1 + (ntiles <= kFusedTiles ? 3 * kFusedTiles * kRadix
+    const int64_t hn = (ntiles <= kFusedTiles ? 3 * kFusedTiles * kRadix
                                                   : ntiles * kRadix + (ntiles * kRadix + kScanChunk - 1) / kScanChunk);
     if (hn > sc.hist_cap) {
         if (sc.hist) (void)hipFree(sc.hist);
@@ -551,7 +459,6 @@ hipError_t ensure_sort_scratch(SortScratch &sc, int64_t n)
         if ((e = hipMalloc(&sc.hist, sizeof(uint32_t) * hn)) != hipSuccess) return e;
         sc.hist_cap = hn;
     }
-    if (!sc.h_word) e = hipHostMalloc(reinterpret_cast<void **>(&sc.h_word), sizeof(uint32_t));
     return e;
 }
 
@@ -560,7 +467,6 @@ void free_sort_scratch(SortScratch &sc)
     if (sc.keys_alt) (void)hipFree(sc.keys_alt);
     if (sc.vals_alt) (void)hipFree(sc.vals_alt);
     if (sc.hist) (void)hipFree(sc.hist);
-    if (sc.h_word) (void)hipHostFree(sc.h_word);
     sc = SortScratch();
 }
 
@@ -600,14 +506,17 @@ static void scan_table(uint32_t *hist, int64_t hsz, hipStream_t s)
     }
 }
 
-// Largest top-digit bucket for which large inputs take the bucket sort
-// (beyond it one workgroup would carry too much of the work).
+// Inputs up to kRadix * kBucketLarge keys take the bucket sort (an average
+// bucket of at most kBucketLarge keys per workgroup).
 constexpr uint32_t kBucketLarge = 16384;
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, SortScratch &sc,
-                            hipStream_t s, const int64_t *mesh_off, int32_t M)
+                            hipStream_t s, const int64_t *mesh_off, int32_t M, int first_bit, uint64_t **kres,
+                            uint32_t **vres)
 {
-    if (n <= 1) return hipSuccess;
+    if (kres) *kres = keys;
+    if (vres) *vres = vals;
+    if (n <= 1 || key_bits <= first_bit) return hipSuccess;
     hipError_t e = ensure_sort_scratch(sc, n);
     if (e != hipSuccess) return e;
     const int ntiles = (int)((n + kTile - 1) / kTile);
@@ -615,7 +524,7 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     // digits, so each mesh's elements end up contiguous in key order
     Digit passes[16];
     int np = 0;
-    for (int p = 0; p < (key_bits + 7) / 8; ++p) passes[np++] = Digit{nullptr, 0, 8 * p};
+    for (int b = first_bit; b < key_bits; b += 8) passes[np++] = Digit{nullptr, 0, b};
     if (mesh_off && M > 1) {
         passes[np++] = Digit{mesh_off, M, 0};
         if (M > 256) passes[np++] = Digit{mesh_off, M, 8};
@@ -626,12 +535,14 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
     // Key digits by buckets: one stable pass on the top 8 bits groups the
     // elements into 256 buckets, then one workgroup per bucket sorts it by
     // the lower digits (k_bucket_sort), so three or four launches replace
-    // one or more per digit.  Small inputs always take this path; larger
-    // ones when their largest bucket stays within kBucketLarge (read back
-    // after the top digit's histogram; not while a graph is being
-    // captured, when the digit passes below run instead).
+    // one or more per digit.  Inputs up to kRadix * kBucketLarge keys take
+    // this path without looking at the data (nothing is read back, so the
+    // call stays stream-ordered and can be captured): buckets up to
+    // kBucketLds keys sort in LDS, a larger one streams through device
+    // memory inside its workgroup, which is slower but only meets meshes
+    // whose triangles crowd into a few of the top-level Morton cells.
     int p0 = 0;  // first pass still to run
-    if (key_bits > 8) {
+    if (key_bits > 8 && first_bit == 0) {
         const int top = key_bits - 8;
         const Digit dtop{nullptr, 0, top};
         const int nlow = (top + 7) / 8;
@@ -644,26 +555,14 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
                                0, nlow);
             p0 = (key_bits + 7) / 8;
         } else if (n <= (int64_t)kRadix * kBucketLarge) {  // else even the average bucket is too large
-            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-            hipError_t ce = hipStreamIsCapturing(s, &cs);
-            if (ce != hipSuccess) return ce;
-            if (cs == hipStreamCaptureStatusNone) {
-                hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist,
-                                   ntiles, nullptr);
-                scan_table(sc.hist, hsz, s);
-                uint32_t *dmax = sc.hist + sc.hist_cap - 1;
-                hipLaunchKernelGGL(k_bucket_max, dim3(1), dim3(kThreads), 0, s, sc.hist, ntiles, n, dmax);
-                hipError_t me = hipMemcpyAsync(sc.h_word, dmax, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-                if (me == hipSuccess) me = hipStreamSynchronize(s);
-                if (me != hipSuccess) return me;
-                if (*sc.h_word <= (uint32_t)kBucketLarge) {
-                    hipLaunchKernelGGL((k_scatter<false, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb,
-                                       vb, n, dtop, sc.hist, ntiles, dtop, nullptr, nullptr);
-                    hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist,
-                                       ntiles, n, 1, nlow);
-                    p0 = (key_bits + 7) / 8;
-                }
-            }
+            hipLaunchKernelGGL(k_hist<kItems>, dim3(ntiles), dim3(kThreads), 0, s, ka, va, n, dtop, sc.hist, ntiles,
+                               nullptr);
+            scan_table(sc.hist, hsz, s);
+            hipLaunchKernelGGL((k_scatter<false, kItems>), dim3(ntiles), dim3(kThreads), 0, s, ka, va, kb, vb, n,
+                               dtop, sc.hist, ntiles, dtop, nullptr, nullptr);
+            hipLaunchKernelGGL(k_bucket_sort, dim3(kRadix), dim3(kThreads), 0, s, kb, vb, ka, va, sc.hist, ntiles, n,
+                               1, nlow);
+            p0 = (key_bits + 7) / 8;
         }
     }
     if (p0 == np) return hipGetLastError();
@@ -687,6 +586,11 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int key_b
             uint64_t *tk = ka; ka = kb; kb = tk;
             uint32_t *tv = va; va = vb; vb = tv;
         }
+    }
+    if (kres && vres) {  // the caller takes the result where it is
+        *kres = ka;
+        *vres = va;
+        return hipGetLastError();
     }
     if (ka != keys) {
         const int blk = 256;

@@ -24,7 +24,7 @@ MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS, "co
 
 EXPORTED = [
     "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_compact", "rsi_segment_order", "rsi_gather_segments", "rsi_inside", "rsi_first_hit_backward",
-    "rsi_spill_info", "rsi_spill_read",
+    "rsi_spill_info", "rsi_spill_read", "rsi_query_stats",
     "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_get_mesh_info", "rsi_export_tree",
     "rsi_batch_create", "rsi_batch_rebuild", "rsi_batch_query", "rsi_batch_capture", "rsi_batch_replay",
     "rsi_set_opts", "rsi_get_opts", "rsi_tune",
@@ -56,7 +56,17 @@ class rsi_outputs(ctypes.Structure):
     _fields_ = [("hit", ctypes.c_void_p), ("tri", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("uv", ctypes.c_void_p), ("point", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("ids", ctypes.c_void_p), ("ts", ctypes.c_void_p), ("capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("spill_off", ctypes.c_void_p), ("spill_ids", ctypes.c_void_p),
+                ("spill_ts", ctypes.c_void_p), ("spill_cap", ctypes.c_int64)]
+
+
+class rsi_stats(ctypes.Structure):
+    _fields_ = [("bad_index", ctypes.c_int32), ("build_inconsistent", ctypes.c_int32),
+                ("walk_cut", ctypes.c_int32), ("stack_dropped", ctypes.c_int32),
+                ("overflow_full", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("deep_segments", ctypes.c_int64), ("overflow_segments", ctypes.c_int64),
+                ("overflow_crossings", ctypes.c_int64), ("arena_records", ctypes.c_int64),
+                ("pool_capacity", ctypes.c_int64)]
 
 
 class rsi_counters(ctypes.Structure):
@@ -97,6 +107,7 @@ def lib():
     L.rsi_first_hit_backward.argtypes = [H, P, P, P, i64, P, P, P, P, P, P, P, P]
     L.rsi_spill_info.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.rsi_spill_read.argtypes = [H, P, P, P, P, P, P]
+    L.rsi_query_stats.argtypes = [H, ctypes.POINTER(rsi_stats)]
     L.rsi_set_counting.argtypes = [H, ctypes.c_int]
     L.rsi_get_counters.argtypes = [H, ctypes.POINTER(rsi_counters)]
     L.rsi_get_tree_info.argtypes = [H, ctypes.POINTER(rsi_tree_info)]
@@ -241,6 +252,36 @@ def rsi_spill_read(h, seg, offset, count, ids, ts, stream=None):
                                 _stream(stream)))
 
 
+def rsi_query_stats(h, check=True):
+    """Wait for the handle's last call and return its device-side state as a
+    dict (rsi_stats); with check=True a failing status raises RsiError."""
+    st = rsi_stats()
+    status = lib().rsi_query_stats(h, ctypes.byref(st))
+    if check:
+        _check(status)
+    d = {name: getattr(st, name) for name, _ in rsi_stats._fields_ if name != "reserved"}
+    d["status"] = status
+    return d
+
+
+def read_spill(h, stream=None, device=None):
+    """The overflow table and pool of the last all-hits query as tensors,
+    void entries (walks handed to the deep pass) dropped."""
+    nseg, ntot = rsi_spill_info(h)
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    sp = {"seg": torch.empty(nseg, dtype=torch.int32, device=dev),
+          "offset": torch.empty(nseg, dtype=torch.int64, device=dev),
+          "count": torch.empty(nseg, dtype=torch.int32, device=dev),
+          "ids": torch.empty(ntot, dtype=torch.int32, device=dev),
+          "ts": torch.empty(ntot, dtype=torch.float32, device=dev)}
+    if nseg:
+        rsi_spill_read(h, sp["seg"], sp["offset"], sp["count"], sp["ids"], sp["ts"], stream)
+        keep = sp["count"] >= 0
+        for k in ("seg", "offset", "count"):
+            sp[k] = sp[k][keep]
+    return sp
+
+
 def rsi_set_counting(h, enable: bool):
     _check(lib().rsi_set_counting(h, 1 if enable else 0))
 
@@ -329,18 +370,40 @@ class Mesh:
     """A BVH over a triangle mesh on the current HIP device."""
 
     def __init__(self, V, T, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0,
-                 chunk=0, stack_depth=0, branching=0):
+                 chunk=0, stack_depth=0, branching=0, check=True):
+        self.handle = None
         self.V = V
         self.T = T
         self.n_t = T.shape[0]
+        self.n_v = V.shape[0]
         self.handle = rsi_build(V, T, leaf_size, block_size, stream, defer_lanes, refill_lanes, chunk,
                                 stack_depth, branching)
+        if check:
+            # the build is asynchronous: wait once here so that bad triangle
+            # indices raise at construction
+            try:
+                rsi_query_stats(self.handle)
+            except RsiError:
+                self.close()
+                raise
+
+    def _check_v(self, V):
+        if V.shape[0] != self.n_v:
+            raise ValueError(f"V has {V.shape[0]} vertices; the mesh was built with {self.n_v}")
 
     def rebuild(self, V, T, stream=None):
+        if T.shape[0] != self.n_t:
+            raise ValueError(f"T has {T.shape[0]} triangles; the mesh was built with {self.n_t}")
         rsi_rebuild(self.handle, V, T, stream)
+        self.n_v = V.shape[0]
 
     def refit(self, V, stream=None):
+        self._check_v(V)
         rsi_refit(self.handle, V, stream)
+
+    def stats(self, check=True):
+        """Wait for the last call and return its device-side state (rsi_stats)."""
+        return rsi_query_stats(self.handle, check)
 
     def alloc_outputs(self, n_r, mode, capacity=4, device=None):
         mode = parse_mode(mode)
@@ -362,29 +425,32 @@ class Mesh:
 
     @staticmethod
     def outputs_struct(out, capacity=4):
+        sp_ids, sp_ts = out.get("spill_ids"), out.get("spill_ts")
         return rsi_outputs(_ptr(out.get("hit")), _ptr(out.get("tri")), _ptr(out.get("t")),
                            _ptr(out.get("uv")), _ptr(out.get("point")), _ptr(out.get("count")),
-                           _ptr(out.get("ids")), _ptr(out.get("ts")), capacity, 0)
+                           _ptr(out.get("ids")), _ptr(out.get("ts")), capacity, 0, _ptr(out.get("spill_off")),
+                           _ptr(sp_ids), _ptr(sp_ts), 0 if sp_ids is None else sp_ids.numel())
 
     def query_into(self, S, E, mode, out, capacity=4, stream=None):
         rsi_query(self.handle, S, E, parse_mode(mode), self.outputs_struct(out, capacity), stream)
         return out
 
     def query(self, S, E, mode="bool", capacity=4, stream=None):
+        """Allocate outputs and query.  With all hits, wait for the query:
+        if the library's spill pool was too small (RSI_E_OVERFLOW), query
+        again (the pool has grown to fit), then read the overflowed
+        segments' full lists into out["spill"]."""
         mode = parse_mode(mode)
         out = self.alloc_outputs(S.shape[0], mode, capacity, S.device)
         self.query_into(S, E, mode, out, capacity, stream)
         if mode & RSI_ALL_HITS:
-            nseg, ntot = rsi_spill_info(self.handle)
-            if nseg:
-                dev = S.device
-                sp = {"seg": torch.empty(nseg, dtype=torch.int32, device=dev),
-                      "offset": torch.empty(nseg, dtype=torch.int64, device=dev),
-                      "count": torch.empty(nseg, dtype=torch.int32, device=dev),
-                      "ids": torch.empty(ntot, dtype=torch.int32, device=dev),
-                      "ts": torch.empty(ntot, dtype=torch.float32, device=dev)}
-                rsi_spill_read(self.handle, sp["seg"], sp["offset"], sp["count"], sp["ids"], sp["ts"], stream)
-                out["spill"] = sp
+            st = rsi_query_stats(self.handle, check=False)
+            if st["status"] == RSI_E_OVERFLOW:
+                self.query_into(S, E, mode, out, capacity, stream)
+                st = rsi_query_stats(self.handle, check=False)
+            _check(st["status"])
+            if st["overflow_segments"]:
+                out["spill"] = read_spill(self.handle, stream, S.device)
         return out
 
     def barycentric(self, S, E, stream=None):
@@ -431,6 +497,7 @@ class Mesh:
         return out
 
     def first_hit_backward(self, V, S, E, tri, g_t=None, g_uv=None, g_point=None, stream=None):
+        self._check_v(V)
         return rsi_first_hit_backward(self.handle, V, S, E, tri, g_t, g_uv, g_point, stream=stream)
 
     def set_counting(self, enable=True):
@@ -485,7 +552,8 @@ class Batch:
     optional HIP graph of rebuild + query replayed with one launch."""
 
     def __init__(self, meshes, leaf_size=0, block_size=0, stream=None, defer_lanes=0, refill_lanes=0, chunk=0,
-                 stack_depth=0, branching=0):
+                 stack_depth=0, branching=0, check=True):
+        self.handle = None
         self.meshes = [(_dev_f32(V, "V"), _dev_i32(T, "T")) for V, T in meshes]
         M = len(self.meshes)
         self._V = _ptr_array([V for V, _ in self.meshes])
@@ -500,6 +568,13 @@ class Batch:
         self.handle = h
         self._keep = None
         self._graph_keep = None
+        if check:
+            # the build is asynchronous: wait once so bad indices raise here
+            try:
+                rsi_query_stats(self.handle)
+            except RsiError:
+                self.close()
+                raise
 
     @property
     def n_meshes(self):
@@ -508,12 +583,16 @@ class Batch:
     def rebuild(self, stream=None):
         _check(lib().rsi_batch_rebuild(self.handle, _stream(stream)))
 
-    def alloc_outputs(self, segments, mode):
+    def alloc_outputs(self, segments, mode, capacity=4):
         mode = parse_mode(mode)
         outs = []
         for S, _ in segments:
             n = S.shape[0]
             d = {}
+            if mode & RSI_ALL_HITS:
+                d["count"] = torch.empty(n, dtype=torch.int32, device=S.device)
+                d["ids"] = torch.empty(n, capacity, dtype=torch.int32, device=S.device)
+                d["ts"] = torch.empty(n, capacity, dtype=torch.float32, device=S.device)
             if mode & RSI_BOOL:
                 d["hit"] = torch.empty(n, dtype=torch.uint8, device=S.device)
             if mode & RSI_FIRST_HIT:
@@ -531,7 +610,8 @@ class Batch:
         S = _ptr_array([s for s, _ in segs])
         E = _ptr_array([e for _, e in segs])
         n = (ctypes.c_int64 * self.n_meshes)(*[s.shape[0] for s, _ in segs])
-        o = (rsi_outputs * self.n_meshes)(*[Mesh.outputs_struct(d, 1) for d in outs])
+        cap = lambda d: d["ids"].shape[1] if "ids" in d else 1
+        o = (rsi_outputs * self.n_meshes)(*[Mesh.outputs_struct(d, cap(d)) for d in outs])
         setattr(self, keep, (segs, outs, S, E, n, o))  # buffers the launch (or graph) refers to
         c = lambda x: ctypes.cast(x, ctypes.c_void_p)
         return c(S), c(E), c(n), parse_mode(mode), c(o)
@@ -541,9 +621,26 @@ class Batch:
         _check(lib().rsi_batch_query(self.handle, S, E, n, m, o, _stream(stream)))
         return outs
 
-    def query(self, segments, mode="bool", stream=None):
-        outs = self.alloc_outputs(segments, mode)
-        return self.query_into(segments, mode, outs, stream)
+    def query(self, segments, mode="bool", capacity=4, stream=None):
+        """Allocate outputs and run one batched query.  With all hits, wait
+        for it, query again if the spill pool was too small, and return the
+        overflowed work items' full lists as outs[0]["spill"] (its `seg` is
+        the work item: the offset of the mesh's segments plus the index)."""
+        m = parse_mode(mode)
+        outs = self.alloc_outputs(segments, m, capacity)
+        self.query_into(segments, m, outs, stream)
+        if m & RSI_ALL_HITS:
+            st = rsi_query_stats(self.handle, check=False)
+            if st["status"] == RSI_E_OVERFLOW:
+                self.query_into(segments, m, outs, stream)
+                st = rsi_query_stats(self.handle, check=False)
+            _check(st["status"])
+            if st["overflow_segments"]:
+                outs[0]["spill"] = read_spill(self.handle, stream, segments[0][0].device)
+        return outs
+
+    def stats(self, check=True):
+        return rsi_query_stats(self.handle, check)
 
     def capture(self, segments, mode, outs, rebuild=True, stream=None):
         # the graph keeps its own tables on the device; keep its buffers alive here
@@ -596,6 +693,7 @@ class FirstHit(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, V, S, E, mesh):
+        mesh._check_v(V)
         V = V.detach().contiguous()
         S = S.detach().contiguous()
         E = E.detach().contiguous()

@@ -23,8 +23,8 @@ DEFAULT_CACHE = os.environ.get("RSI_TUNE_CACHE", os.path.join(os.path.expanduser
 # staged search: each stage varies some options on top of the best so far
 STAGES = [
     [{"branching": w, "block_size": b} for w in (2, 4) for b in (64, 128, 256)],
-    # stack_depth 255 keeps the whole stack in LDS (it is capped at the walk's worst-case depth)
-    [{"stack_depth": s} for s in (255, 8, 12, 16, 20, 24)],
+    # LDS stack entries per lane of the main pass (deeper walks go to the deep pass)
+    [{"stack_depth": s} for s in (8, 12, 16, 20, 24, 32)],
     [{"defer_lanes": d, "refill_lanes": r} for d in (16, 32, 48) for r in (16, 32, 48)],
     [{"leaf_size": leaf} for leaf in (1, 2, 4)],
 ]

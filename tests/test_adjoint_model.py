@@ -1,0 +1,98 @@
+"""CPU model of the first-hit adjoint's data flow (no GPU): the order in
+which the device groups and sums the vertex contributions, restated in numpy
+and checked against the FP64 oracle's gradient.
+
+The device kernels (adjoint.hip) solve every segment in input order, group
+the (hit triangle's Morton position, segment) pairs by cells of 1,024
+positions with a stable pass, let each 256-position group walk its cell's
+pairs tile by tile (1,024 pairs), rank the tile's own pairs stably by
+position, sum each triangle's records in that order in FP64, and finally sum
+the (triangle, corner) terms of each vertex from a table sorted by vertex.
+No atomic operation is involved, so the only ways to lose a contribution
+would be a wrong grouping or a wrong range; this model walks exactly those
+ranges (including cells that span several tiles, empty cells, misses and
+groups past the last triangle) and must reproduce the oracle's gradient.
+"""
+import numpy as np
+
+import oracle
+from paper_2209_02878_amd import workloads as wl
+
+CELL_BITS, GROUP_BITS, TILE = 10, 8, 1024
+
+
+def _model(V, T, S, E, tri, g_p, rank):
+    n_t, n_r = T.shape[0], S.shape[0]
+    # k_adj_solve: per segment, lambda and (u, v) (here in FP64; the device
+    # stores them in FP32), the key (sorted position or n_t)
+    keys = np.full(n_r, n_t, np.int64)
+    rec = np.zeros((n_r, 5))
+    for i in range(n_r):
+        j = tri[i]
+        if j < 0:
+            continue
+        v0, v1, v2 = (V[T[j, c]].astype(np.float64) for c in range(3))
+        s, e = S[i].astype(np.float64), E[i].astype(np.float64)
+        d = e - s
+        M = np.stack([-d, v1 - v0, v2 - v0], 1)
+        if np.linalg.det(M) == 0:
+            continue
+        t, u, v = np.linalg.solve(M, s - v0)
+        tb = g_p[i] @ d
+        lam = np.linalg.solve(M.T, np.array([tb, 0.0, 0.0]))
+        rec[i] = [*lam, u, v]
+        keys[i] = rank[j]
+    # stable grouping by cell
+    order = np.argsort(keys >> CELL_BITS, kind="stable")
+    sk = keys[order]
+    n_groups = (n_t + (1 << GROUP_BITS) - 1) >> GROUP_BITS
+    n_cells = (n_groups + 3) // 4
+    tri_sum = np.zeros((n_t, 3, 3))
+    for group in range(4 * n_cells):
+        g = group >> 2
+        lo = np.searchsorted(sk >> CELL_BITS, g, side="left")
+        hi = np.searchsorted(sk >> CELL_BITS, g + 1, side="left")
+        acc = np.zeros((1 << GROUP_BITS, 3, 3))
+        for c0 in range(lo, hi, TILE):
+            ks = sk[c0:min(c0 + TILE, hi)]
+            segs = order[c0:min(c0 + TILE, hi)]
+            sel = (ks < n_t) & ((ks >> GROUP_BITS) == group)
+            # stable rank by position within the tile, then per-triangle order
+            local = ks[sel] & 0xFF
+            for p in np.argsort(local, kind="stable"):
+                lam, u, v = rec[segs[sel][p], :3], rec[segs[sel][p], 3], rec[segs[sel][p], 4]
+                w = np.array([-(1.0 - u - v), -u, -v])
+                acc[local[p]] += w[:, None] * lam[None, :]
+        base = group << GROUP_BITS
+        m = min(1 << GROUP_BITS, max(0, n_t - base))
+        tri_sum[base:base + m] = acc[:m]
+    # vertex incidence table sorted by vertex (stable): (vertex, 3 * position + corner)
+    inc_v = T.reshape(-1)
+    inc_tc = 3 * np.repeat(rank, 3) + np.tile(np.arange(3), n_t)
+    o = np.argsort(inc_v, kind="stable")
+    dV = np.zeros((V.shape[0], 3))
+    for v, tc in zip(inc_v[o], inc_tc[o]):
+        dV[v] += tri_sum[tc // 3, tc % 3]
+    return dV
+
+
+def test_adjoint_grouping_model_matches_oracle_gradient():
+    # 2,888 triangles: three cells, the last one partly filled; segments in
+    # random order, some missing the mesh; cells span several tiles
+    V, T = wl.noise_heightfield(39, 11, 0.2)
+    n_t = T.shape[0]
+    rng = np.random.default_rng(4)
+    S, E = wl.segments_near_vertical(rng, 6000)
+    S[:300, :2] += 2.0  # misses
+    E[:300, :2] += 2.0
+    ref = oracle.query(V, T, S, E)
+    tri = ref["first_tri"]
+    assert (tri < 0).sum() >= 300 and (tri >= 0).sum() > 5000
+    # any permutation serves as the Morton order of the triangles
+    rank = rng.permutation(n_t).astype(np.int64)
+    g_p = np.zeros((S.shape[0], 3))
+    g_p[:, 2] = rng.standard_normal(S.shape[0])
+    dV = _model(V, T, S, E, tri, g_p, rank)
+    rV, _, _ = oracle.first_hit_grad(V, T, S, E, tri, ref["first_tuv"], g_p=g_p)
+    assert np.abs(dV - rV).max() <= 1e-9 * np.abs(rV).max()
+    assert np.count_nonzero(rV) > 0
