@@ -183,10 +183,13 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
  *            the caller zeroes it for a plain gradient)
  *   dS, dE   device float32 [n_r*3]: written (zero for misses); NULL skips
  * (t, u, v) and the 3x3 transposed solve are evaluated in FP64 per segment.
- * Batches of at least 65,536 segments and 4 per triangle keep about 24
- * bytes per segment with the handle (sort keys and values and the sort's
- * scratch; allocated on first use, grown for a larger batch, freed by
- * rsi_free) to sum the hits of equal triangles before the atomic adds.
+ * The vertex gradient is summed without atomic operations in a fixed order
+ * (per triangle in FP64, then per vertex), so repeated calls give the same
+ * bits.  Memory kept with the handle and released by rsi_destroy (allocated
+ * on first use, grown for a larger batch): about 56 bytes per segment
+ * (records, sort pairs and the sort's scratch), 72 bytes per triangle and a
+ * vertex incidence table of 36 bytes per triangle (rebuilt after
+ * rsi_build / rsi_rebuild, kept across rsi_refit).
  * Asynchronous on `stream`.  Errors: RSI_E_INVALID (NULL pointers, n_r out
  * of range), RSI_E_NOMEM, RSI_E_HIP. */
 rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,

@@ -186,6 +186,9 @@ rsi_status alloc_handle(int32_t M, const int64_t *n_v, const int64_t *n_t, const
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void **>(&h->h_scalars), sizeof(int32_t) * rsi::kNumScalars);
     if (e == hipSuccess && n > 0) e = rsi::ensure_sort_scratch(h->sort, n);
+    // device flags and counters start clear (a fresh handle reports nothing)
+    if (e == hipSuccess) e = hipMemset(h->scalars, 0, sizeof(int32_t) * rsi::kNumScalars);
+    if (e == hipSuccess) e = hipMemset(h->counters, 0, sizeof(rsi::Counters));
     if (e == hipSuccess)
         e = hipMemcpy(h->tri_off, h->h_tri_off.data(), sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess)

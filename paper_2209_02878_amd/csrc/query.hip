@@ -206,8 +206,7 @@ struct Lane {
     int32_t count;     // crossings found (all hits, count)
     int32_t e;         // all hits: overflow-table entry, -1 while count <= K
     int32_t item;      // work item (a segment, or a (mesh, segment) pair of a batch)
-    int64_t seg_i;     // segment index (within its mesh for batched queries)
-    int64_t slot_base; // first slot of this segment (all hits)
+    int32_t seg_i;     // segment index (within its mesh for batched queries; below 2^30)
     const float *sp;   // this segment's start and end (3 floats each)
     const float *ep;
     int32_t mesh;      // batched queries: the segment's mesh
@@ -259,7 +258,7 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
                     L.hp1 = L.hp0;
                     L.hp0 = pos;
                 } else {
-                    slot_ids<BATCH>(a, L)[L.slot_base + c] = pos;
+                    slot_ids<BATCH>(a, L)[(int64_t)L.seg_i * K + c] = pos;
                 }
             } else {
                 // past the slots: an arena record (entry, rank, position)
@@ -299,26 +298,10 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         float *tt = BATCH ? a.bt.t[L.mesh] : a.o.t;
         float *uv = BATCH ? a.bt.uv[L.mesh] : a.o.uv;
         float *pt = BATCH ? a.bt.point[L.mesh] : a.o.point;
-        if (L.best_pos >= 0 && !(MODE & M_ALL)) {
+        if (L.best_pos >= 0) {
             // the hit's sorted position; k_refine_first re-solves it and
             // writes the id, t, (u, v) and the point
             tri[i] = L.best_pos;
-        } else if (L.best_pos >= 0) {
-            // with all hits the walk keeps many registers anyway: re-solve here
-            const float sx = ld_nt(L.sp), sy = ld_nt(L.sp + 1), sz = ld_nt(L.sp + 2);
-            const float ex = ld_nt(L.ep), ey = ld_nt(L.ep + 1), ez = ld_nt(L.ep + 2);
-            float v[9];
-            int32_t id;
-            tri_load(a.tris, L.best_pos, v, id);
-            double t, u, w;
-            mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-            st_nt(tri + i, id);
-            st_nt(tt + i, (float)t);
-            st_nt(uv + 2 * i, (float)u);
-            st_nt(uv + 2 * i + 1, (float)w);
-            st_nt(pt + 3 * i, (float)((double)sx + t * ((double)ex - (double)sx)));
-            st_nt(pt + 3 * i + 1, (float)((double)sy + t * ((double)ey - (double)sy)));
-            st_nt(pt + 3 * i + 2, (float)((double)sz + t * ((double)ez - (double)sz)));
         } else {
             st_nt(tri + i, -1);
             st_nt(tt + i, INFINITY);
@@ -335,87 +318,30 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         int32_t *cnt_out = BATCH ? a.bt.count[L.mesh] : a.o.count;
         int64_t *soff = BATCH ? a.bt.spill_off[L.mesh] : a.o.spill_off;
         st_nt(cnt_out + i, L.count);
-        int32_t *ids = slot_ids<BATCH>(a, L) + L.slot_base;
-        float *ts = slot_ts<BATCH>(a, L) + L.slot_base;
-        if (L.count <= K) {
-            const float sx = ld_nt(L.sp), sy = ld_nt(L.sp + 1), sz = ld_nt(L.sp + 2);
-            const float ex = ld_nt(L.ep), ey = ld_nt(L.ep + 1), ez = ld_nt(L.ep + 2);
+        int32_t *ids = slot_ids<BATCH>(a, L) + i * K;
+        float *ts = slot_ts<BATCH>(a, L) + i * K;
+        if (L.count == 0) {
+            for (int c = 0; c < K; ++c) {
+                st_nt(ids + c, -1);
+                st_nt(ts + c, INFINITY);
+            }
+            if (soff) st_nt(soff + i, (int64_t)-1);
+        } else if (L.count <= K) {
+            // the hits' sorted positions (after the walk, k_refine_slots
+            // re-solves them, orders them by (t, id) and writes ids and t):
+            // kept in registers up to four, else already in the slots
             if (K <= kRegSlots) {
-                // the hits are in registers: re-solve, order by (t, id) with a
-                // sorting network (unused entries sort last) and store once
-                int32_t id[kRegSlots];
-                float t[kRegSlots];
                 const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
-#pragma unroll
-                for (int k = 0; k < kRegSlots; ++k) {
-                    id[k] = 0x7FFFFFFF;
-                    t[k] = INFINITY;
-                    if (k < L.count) {
-                        float v[9];
-                        int32_t tid;
-                        tri_load(a.tris, hp[k], v, tid);
-                        double tt, u, w;
-                        mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
-                        id[k] = tid;
-                        t[k] = (float)tt;
-                    }
-                }
-                auto cs = [&](int x, int y) {
-                    if (t[y] < t[x] || (t[y] == t[x] && id[y] < id[x])) {
-                        const float tf = t[x];
-                        t[x] = t[y];
-                        t[y] = tf;
-                        const int32_t tk = id[x];
-                        id[x] = id[y];
-                        id[y] = tk;
-                    }
-                };
-                cs(0, 1);
-                cs(2, 3);
-                cs(0, 2);
-                cs(1, 3);
-                cs(1, 2);
-#pragma unroll
-                for (int k = 0; k < kRegSlots; ++k)
-                    if (k >= L.count) id[k] = -1;
-                const bool vec = K == kRegSlots &&
-                                 ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
+                const bool vec = K == kRegSlots && (reinterpret_cast<uintptr_t>(ids) & 15) == 0;
                 if (vec) {
-                    st_nt4(ids, id[0], id[1], id[2], id[3]);
-                    st_nt4(ts, t[0], t[1], t[2], t[3]);
+                    st_nt4(ids, hp[0], L.count > 1 ? hp[1] : -1, L.count > 2 ? hp[2] : -1, L.count > 3 ? hp[3] : -1);
                 } else {
-                    for (int c = 0; c < K; ++c) {
-                        st_nt(ids + c, id[c]);
-                        st_nt(ts + c, t[c]);
-                    }
+#pragma unroll
+                    for (int c = 0; c < kRegSlots; ++c)
+                        if (c < K) ids[c] = c < L.count ? hp[c] : -1;
                 }
             } else {
-                for (int c = 0; c < L.count; ++c) {
-                    float v[9];
-                    int32_t tid;
-                    tri_load(a.tris, ids[c], v, tid);
-                    double tt, u, w;
-                    mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
-                    ids[c] = tid;
-                    ts[c] = (float)tt;
-                }
-                // order by (t, id): insertion sort, lists are short
-                for (int x = 1; x < L.count; ++x) {
-                    const float kt = ts[x];
-                    const int32_t ki = ids[x];
-                    int y = x - 1;
-                    while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
-                        ts[y + 1] = ts[y];
-                        ids[y + 1] = ids[y];
-                        --y;
-                    }
-                    ts[y + 1] = kt;
-                    ids[y + 1] = ki;
-                }
-                for (int c = L.count; c < K; ++c) {
-                    st_nt(ids + c, -1);
-                    st_nt(ts + c, INFINITY);
-                }
+                for (int c = L.count; c < K; ++c) ids[c] = -1;
             }
             if (soff) st_nt(soff + i, (int64_t)-1);
         } else {
@@ -580,7 +506,6 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                     }
                     L.item = it;
                     L.seg_i = i;
-                    L.slot_base = (MODE & M_ALL) ? (int64_t)i * a.o.cap : 0;
                     L.seg = make_seg(ld_nt(L.sp), ld_nt(L.sp + 1), ld_nt(L.sp + 2), ld_nt(L.ep), ld_nt(L.ep + 1),
                                      ld_nt(L.ep + 2));
                     L.tlim = 1.0f;
@@ -983,6 +908,122 @@ __global__ __launch_bounds__(256) void k_spill_finish(QArgs a)
     }
 }
 
+// All hits, after the walk: every segment with 1..K crossings has their
+// sorted positions in its first slots (the rest -1).  Re-solve them in FP64
+// (positions become triangle ids), order by (t, id) and write ids and t.
+// Segments with no crossing were completed by the walk; those with more
+// than K by k_spill_finish.  Kept out of the walk, whose register count
+// (hence waves per SIMD) the FP64 solves would otherwise set.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int K = a.o.cap;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_items; k += stride) {
+        int64_t i = k;
+        const float *S = a.S, *E = a.E;
+        const int32_t *cnt = a.o.count;
+        int32_t *ids = a.o.ids;
+        float *ts = a.o.ts;
+        if (BATCH) {
+            const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
+            i = k - a.bt.seg_off[m];
+            S = a.bt.S[m];
+            E = a.bt.E[m];
+            cnt = a.bt.count[m];
+            ids = a.bt.ids[m];
+            ts = a.bt.ts[m];
+        }
+        const int32_t n = cnt[i];
+        if (n < 1 || n > K) continue;
+        ids += i * (int64_t)K;
+        ts += i * (int64_t)K;
+        const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
+        const float ex = ld_nt(E + 3 * i), ey = ld_nt(E + 3 * i + 1), ez = ld_nt(E + 3 * i + 2);
+        if (K <= kRegSlots) {
+            int32_t id[kRegSlots];
+            float t[kRegSlots];
+#pragma unroll
+            for (int c = 0; c < kRegSlots; ++c) {
+                id[c] = 0x7FFFFFFF;
+                t[c] = INFINITY;
+                const int32_t pos = c < n ? ids[c] : -1;
+                if (pos >= 0 && pos < a.n_tris) {
+                    float v[9];
+                    int32_t tid;
+                    tri_load(a.tris, pos, v, tid);
+                    double tt, u, w;
+                    mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
+                    id[c] = tid;
+                    t[c] = (float)tt;
+                }
+            }
+            // five-comparator network (unused entries sort last)
+            auto cs = [&](int x, int y) {
+                if (t[y] < t[x] || (t[y] == t[x] && id[y] < id[x])) {
+                    const float tf = t[x];
+                    t[x] = t[y];
+                    t[y] = tf;
+                    const int32_t tk = id[x];
+                    id[x] = id[y];
+                    id[y] = tk;
+                }
+            };
+            cs(0, 1);
+            cs(2, 3);
+            cs(0, 2);
+            cs(1, 3);
+            cs(1, 2);
+#pragma unroll
+            for (int c = 0; c < kRegSlots; ++c)
+                if (c >= n) id[c] = -1;
+            const bool vec = K == kRegSlots &&
+                             ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
+            if (vec) {
+                st_nt4(ids, id[0], id[1], id[2], id[3]);
+                st_nt4(ts, t[0], t[1], t[2], t[3]);
+            } else {
+                for (int c = 0; c < K; ++c) {
+                    st_nt(ids + c, id[c]);
+                    st_nt(ts + c, t[c]);
+                }
+            }
+        } else {
+            for (int c = 0; c < n; ++c) {
+                const int32_t pos = ids[c];
+                if (pos < 0 || pos >= a.n_tris) {
+                    ids[c] = 0x7FFFFFFF;
+                    ts[c] = INFINITY;
+                    continue;
+                }
+                float v[9];
+                int32_t tid;
+                tri_load(a.tris, pos, v, tid);
+                double tt, u, w;
+                mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
+                ids[c] = tid;
+                ts[c] = (float)tt;
+            }
+            for (int x = 1; x < n; ++x) {  // insertion sort by (t, id): lists are short
+                const float kt = ts[x];
+                const int32_t ki = ids[x];
+                int y = x - 1;
+                while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                    ts[y + 1] = ts[y];
+                    ids[y + 1] = ids[y];
+                    --y;
+                }
+                ts[y + 1] = kt;
+                ids[y + 1] = ki;
+            }
+            for (int c = n; c < K; ++c) {
+                ids[c] = -1;
+                ts[c] = INFINITY;
+            }
+        }
+    }
+}
+
 __global__ void k_fill_miss(int64_t n_r, uint32_t mode, QueryOut o)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1262,6 +1303,10 @@ void pass_args(const rsi_bvh *h, QArgs &main, QArgs &deep, int ld)
 
 hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
 {
+    const int64_t blocks = (a.n_items + 255) / 256;
+    const unsigned rgrid = (unsigned)(blocks < 8192 ? blocks : 8192);
+    if (batch) hipLaunchKernelGGL(k_refine_slots<true>, dim3(rgrid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_refine_slots<false>, dim3(rgrid), dim3(256), 0, s, a);
     const unsigned grid = (unsigned)(2 * device_cus());
     hipLaunchKernelGGL(k_spill_place, dim3(grid), dim3(256), 0, s, a);
     if (batch) hipLaunchKernelGGL(k_spill_finish<true>, dim3(grid), dim3(256), 0, s, a);
@@ -1271,18 +1316,38 @@ hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
 
 }  // namespace
 
+int64_t deep_stack_entries(const rsi_bvh *h, uint32_t mode)
+{
+    const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
+    const int block = fit_block(h->block_size, ld);
+    const int need = stack_need(h->height_bound, h->width_built);
+    return need > ld ? (int64_t)kRetryBlocksPerCU * device_cus() * block * (need - ld) : 0;
+}
+
 hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
                         const QueryOut &o, hipStream_t s)
+{
+    const QueryScratch sc = {h->retry_q, h->retry_cap, h->retry_stack, h->retry_stack_cap};
+    return launch_query_scratch(h, S, E, n_r, mode, o, sc, s);
+}
+
+hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
+                                const QueryOut &o, const QueryScratch &sc, hipStream_t s)
 {
     if (n_r == 0) return hipSuccess;
     const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
     const int block = fit_block(h->block_size, ld);
     const size_t lds = (size_t)block * ld * sizeof(int32_t);
     QArgs a = make_args(h, S, E, n_r, o), d;
+    a.retry_q = sc.retry_q;
+    a.retry_cap = sc.retry_cap;
+    a.gstack = sc.gstack;
+    a.gstack_cap = sc.gstack_cap;
+    if (a.retry_cap < n_r) return hipErrorInvalidValue;
     pass_args(h, a, d, ld);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, h->counting ? h->counters : nullptr);
     hipError_t e = h->counting ? dispatch<true>(mode, a, d, block, lds, s) : dispatch<false>(mode, a, d, block, lds, s);
-    if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<false>(a, s);
+    if (e == hipSuccess && (mode & M_FIRST)) e = launch_refine_first<false>(a, s);
     if (e == hipSuccess && (mode & M_ALL)) e = launch_all_hits_tail(a, false, s);
     return e;
 }
@@ -1314,7 +1379,7 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
     case M_ALL | M_FIRST | M_BOOL: e = launch_passes<M_ALL | M_FIRST | M_BOOL, false, true>(a, d, block, lds, s); break;
     default: return hipErrorInvalidValue;
     }
-    if (e == hipSuccess && (mode & M_FIRST) && !(mode & M_ALL)) e = launch_refine_first<true>(a, s);
+    if (e == hipSuccess && (mode & M_FIRST)) e = launch_refine_first<true>(a, s);
     if (e == hipSuccess && (mode & M_ALL)) e = launch_all_hits_tail(a, true, s);
     return e;
 }

@@ -93,16 +93,18 @@ struct Seg {
 
 __device__ inline float guarded_rcp(float d)
 {
-    // Components below 1e-30 in magnitude (zero included) use +-1e-30, so
-    // every slab parameter is finite or +-inf and never NaN.  A capped
-    // reciprocal keeps the box decision exact while every nonzero coordinate
-    // difference is at least 1e-30 (coordinates of magnitude >= ~1e-23, or
-    // zero): then |(plane - o) * 1e30| >= 1 lies outside [0, 1] on the same
-    // side as the exact parameter.  (plane == o with d == 0 is a segment
+    // Components below the smallest normal FP32 value 2^-126 in magnitude
+    // (zero included) use +-2^-126, so the reciprocal is finite (at most
+    // 2^126) and every slab parameter is finite or +-inf, never NaN.  The
+    // capped reciprocal keeps the box decision exact while every nonzero
+    // coordinate difference is a normal number: then |(plane - o) * 2^126|
+    // >= 1 lies outside [0, 1] on the same side as the exact parameter.
+    // Only differences in the subnormal range (coordinates below about
+    // 2^-102) fall short of that.  (plane == o with d == 0 is a segment
     // lying in a box face, which meets the triangles inside only on their
     // boundary.)  The hardware reciprocal is within 1 ulp, which the slack
     // of slab_hit covers.
-    const float tiny = 1e-30f;
+    const float tiny = 0x1p-126f;
     const float g = fabsf(d) < tiny ? copysignf(tiny, d) : d;
     return __builtin_amdgcn_rcpf(g);
 }

@@ -219,6 +219,18 @@ struct QueryOut {
 };
 hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
                         const QueryOut &o, hipStream_t s);
+// The deep pass's queue (one entry per segment) and device-memory stack.
+struct QueryScratch {
+    int32_t *retry_q;
+    int64_t retry_cap;
+    int32_t *gstack;
+    int64_t gstack_cap;
+};
+// launch_query with the deep pass's memory given by the caller
+hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
+                                const QueryOut &o, const QueryScratch &sc, hipStream_t s);
+// stack entries (int32) the deep pass of a query in `mode` needs
+int64_t deep_stack_entries(const rsi_bvh *h, uint32_t mode);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);
 // zero the per-query device scalars (a query that launches no walk)
 hipError_t launch_clear_query(rsi_bvh *h, hipStream_t s);
