@@ -136,163 +136,175 @@ def degenerate_fraction(w, n_pick, seed):
     return {"sample": int(idx.size), "near_degenerate": n, "fraction": round(n / idx.size, 6)}
 
 
-def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2):
-    """The other configurations, reported beside the headline."""
+EXTRA_SECTIONS = ("c1", "c2var", "c3", "c4", "c5")
+
+
+def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2, sections=EXTRA_SECTIONS):
+    """The other configurations, reported beside the headline: c1 the
+    1,922-triangle heightfield; c2var the headline workload on the binary walk
+    and with Morton-ordered segments; c3 the 499,280-triangle closed sphere
+    (all hits + first hit, boolean, inside test); c4 the differentiable first
+    hit on 199,712 triangles; c5 the 64-mesh batch."""
     out = {}
     med = lambda xs: float(np.median(xs))
 
-    # the 1,922-triangle heightfield, 100k segments, boolean
-    w = wl.config1()
-    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
-    m = rsi.Mesh(V, T)
-    o = m.alloc_outputs(w.n_r, "bool")
-    q = time_events(lambda: m.query_into(S, E, "bool", o), 20)
-    out["heightfield_1922tri_100kseg_bool"] = {"query_ms": round(med(q), 4),
-                                               "msegments_per_s": round(w.n_r / med(q) / 1e3, 2)}
-    log(f"1,922-triangle heightfield: bool {med(q):.4f} ms")
-    m.close()
+    if "c1" in sections:
+        # the 1,922-triangle heightfield, 100k segments, boolean
+        w = wl.config1()
+        V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
+        m = rsi.Mesh(V, T)
+        o = m.alloc_outputs(w.n_r, "bool")
+        q = time_events(lambda: m.query_into(S, E, "bool", o), 20)
+        out["heightfield_1922tri_100kseg_bool"] = {"query_ms": round(med(q), 4),
+                                                   "msegments_per_s": round(w.n_r / med(q) / 1e3, 2)}
+        log(f"1,922-triangle heightfield: bool {med(q):.4f} ms")
+        m.close()
 
-    # the headline mesh and segments: the binary walk, and Morton-ordered segments
-    m = rsi.Mesh(V2, T2)
-    ob = m.alloc_outputs(w2.n_r, "bool")
-    oa = m.alloc_outputs(w2.n_r, "all", capacity=4)
-    m.set_opts(branching=2)
-    b2 = time_events(lambda: m.rebuild(V2, T2), 10)
-    q2 = time_events(lambda: m.query_into(S2, E2, "bool", ob), 10)
-    a2 = time_events(lambda: m.query_into(S2, E2, "all", oa, capacity=4), 5)
-    out["heightfield_29768tri_10Mseg_binary_walk"] = {
-        "rebuild_ms": round(med(b2), 4), "query_bool_ms": round(med(q2), 4),
-        "query_all_hits_k4_ms": round(med(a2), 4)}
-    log(f"binary walk: rebuild {med(b2):.3f} ms, bool {med(q2):.3f} ms, all-hits {med(a2):.3f} ms")
-    m.set_opts(branching=4)
-    order = torch.empty(w2.n_r, dtype=torch.int32, device=dev)
-    So, Eo = torch.empty_like(S2), torch.empty_like(E2)
-    oc = time_events(lambda: (rsi.rsi_segment_order(m.handle, S2, E2, order),
-                              rsi.rsi_gather_segments(m.handle, S2, E2, order, So, Eo)), 5)
-    qo = time_events(lambda: m.query_into(So, Eo, "bool", ob), 10)
-    ao = time_events(lambda: m.query_into(So, Eo, "all", oa, capacity=4), 5)
-    out["heightfield_29768tri_10Mseg_morton_ordered"] = {
-        "order_and_gather_ms": round(med(oc), 4), "query_bool_ms": round(med(qo), 4),
-        "query_all_hits_k4_ms": round(med(ao), 4)}
-    log(f"ordered segments: order+gather {med(oc):.3f} ms, bool {med(qo):.3f} ms, all-hits {med(ao):.3f} ms")
-    m.close()
-    del ob, oa, order, So, Eo
+    if "c2var" in sections:
+        # the headline mesh and segments: the binary walk, and Morton-ordered segments
+        m = rsi.Mesh(V2, T2)
+        ob = m.alloc_outputs(w2.n_r, "bool")
+        oa = m.alloc_outputs(w2.n_r, "all", capacity=4)
+        m.set_opts(branching=2)
+        b2 = time_events(lambda: m.rebuild(V2, T2), 10)
+        q2 = time_events(lambda: m.query_into(S2, E2, "bool", ob), 10)
+        a2 = time_events(lambda: m.query_into(S2, E2, "all", oa, capacity=4), 5)
+        out["heightfield_29768tri_10Mseg_binary_walk"] = {
+            "rebuild_ms": round(med(b2), 4), "query_bool_ms": round(med(q2), 4),
+            "query_all_hits_k4_ms": round(med(a2), 4)}
+        log(f"binary walk: rebuild {med(b2):.3f} ms, bool {med(q2):.3f} ms, all-hits {med(a2):.3f} ms")
+        m.set_opts(branching=4)
+        order = torch.empty(w2.n_r, dtype=torch.int32, device=dev)
+        So, Eo = torch.empty_like(S2), torch.empty_like(E2)
+        oc = time_events(lambda: (rsi.rsi_segment_order(m.handle, S2, E2, order),
+                                  rsi.rsi_gather_segments(m.handle, S2, E2, order, So, Eo)), 5)
+        qo = time_events(lambda: m.query_into(So, Eo, "bool", ob), 10)
+        ao = time_events(lambda: m.query_into(So, Eo, "all", oa, capacity=4), 5)
+        out["heightfield_29768tri_10Mseg_morton_ordered"] = {
+            "order_and_gather_ms": round(med(oc), 4), "query_bool_ms": round(med(qo), 4),
+            "query_all_hits_k4_ms": round(med(ao), 4)}
+        log(f"ordered segments: order+gather {med(oc):.3f} ms, bool {med(qo):.3f} ms, all-hits {med(ao):.3f} ms")
+        m.close()
+        del ob, oa, order, So, Eo
 
-    # closed 499,280-triangle sphere: all crossings (capacity 4) + first hit
-    t0 = time.time()
-    w = wl.config3()
-    log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
-    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
-    m = rsi.Mesh(V, T)
-    o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
-    b = time_events(lambda: m.rebuild(V, T), 5)
-    q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
-    st = m.stats()
-    ob = m.alloc_outputs(w.n_r, "bool")
-    qb = time_events(lambda: m.query_into(S, E, "bool", ob), 5)
-    out["sphere_499280tri_10Mseg_all_first_k4"] = {
-        "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
-        "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "query_bool_ms": round(med(qb), 4),
-        "overflowed_segments": int(st["overflow_segments"]), "spilled_crossings": int(st["overflow_crossings"]),
-        "deep_pass_segments": int(st["deep_segments"])}
-    log(f"sphere all|first: query {med(q):.3f} ms, bool {med(qb):.3f} ms, build {med(b):.3f} ms, stats {st}")
-    # odd-parity inside test of 10M points against the same closed surface
-    P = torch.from_numpy(wl.inside_points(w.V, w.n_r, wl.seed_for(6, 1))).to(dev)
-    ins = torch.empty(w.n_r, dtype=torch.uint8, device=dev)
-    cnt = torch.empty(w.n_r, dtype=torch.int32, device=dev)
-    ends = torch.empty(w.n_r, 3, dtype=torch.float32, device=dev)
-    qi = time_events(lambda: rsi.rsi_inside(m.handle, P, ins, cnt, ends), 5)
-    out["sphere_499280tri_10Mpoint_inside"] = {
-        "ms": round(med(qi), 4), "mpoints_per_s": round(w.n_r / med(qi) / 1e3, 2),
-        "inside_fraction": round(float(ins.float().mean().item()), 5)}
-    log(f"inside test: {med(qi):.3f} ms for {w.n_r} points")
-    m.close()
-    del V, T, S, E, o, ob, P, ins, cnt, ends
-
-    # differentiable first hit: 199,712-triangle heightfield, 4M segments
-    w = wl.config4()
-    Vg, _ = wl.config4_target()
-    V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
-    n = 317
-    gz = torch.from_numpy(Vg[:, 2].astype(np.float32)).to(dev)
-    X = torch.clamp(S[:, 0] * (n - 1), 0, n - 1 - 1e-6)
-    Y = torch.clamp(S[:, 1] * (n - 1), 0, n - 1 - 1e-6)
-    i, j = X.long(), Y.long()
-    a, c = X - i, Y - j
-    k = j * n + i
-    target = (gz[k] * (1 - a) * (1 - c) + gz[k + 1] * a * (1 - c) + gz[k + n] * (1 - a) * c
-              + gz[k + n + 1] * a * c)
-    m = rsi.Mesh(V, T)
-    Vp = V.clone().requires_grad_(True)
-
-    def fwd():
-        with torch.no_grad():
-            _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
-            return ((P[:, 2] - target) ** 2).sum()
-
-    def fwd_bwd():
-        Vp.grad = None
-        _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
-        loss = ((P[:, 2] - target) ** 2).sum()
-        loss.backward()
-
-    f = time_events(fwd, 10)
-    fb = time_events(fwd_bwd, 10)
-    out["heightfield_199712tri_4Mseg_first_hit_grad"] = {
-        "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
-        "backward_ms": round(med(fb) - med(f), 4),
-        "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
-        "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
-        "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
-    log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms")
-    m.close()
-    del V, T, S, E, Vp
-
-    # 64 meshes: one captured graph (rebuild all + one batched query) per mode,
-    # with options chosen by the autotuner on this batch, against 64
-    # sequential plain calls (rebuild + query per mesh)
-    from paper_2209_02878_amd import tune
-    t0 = time.time()
-    ws = wl.config5()
-    log(f"64-mesh batch generated in {time.time() - t0:.1f}s: {sum(x.n_t for x in ws)} triangles, "
-        f"{sum(x.n_r for x in ws)} segments")
-    meshes = [(torch.from_numpy(x.V).to(dev), torch.from_numpy(x.T).to(dev)) for x in ws]
-    segs = [(torch.from_numpy(x.S).to(dev), torch.from_numpy(x.E).to(dev)) for x in ws]
-    singles = [rsi.Mesh(Vm, Tm) for Vm, Tm in meshes]
-    ntot = sum(x.n_r for x in ws)
-    bt = rsi.Batch(meshes)
-    for mode in ("bool", "first"):
+    if "c3" in sections:
+        # closed 499,280-triangle sphere: all crossings (capacity 4) + first hit
         t0 = time.time()
-        opts = tune.autotune(bt, segs, mode=mode, kind="batch64", n_t=sum(x.n_t for x in ws), n_r=ntot,
-                             cache_path=None)
-        t_tune = time.time() - t0
+        w = wl.config3()
+        log(f"workload {w.name} generated in {time.time() - t0:.1f}s")
+        V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
+        m = rsi.Mesh(V, T)
+        o = m.alloc_outputs(w.n_r, "all|first", capacity=4)
+        b = time_events(lambda: m.rebuild(V, T), 5)
+        q = time_events(lambda: m.query_into(S, E, "all|first", o, capacity=4), 5)
+        st = m.stats()
+        ob = m.alloc_outputs(w.n_r, "bool")
+        qb = time_events(lambda: m.query_into(S, E, "bool", ob), 5)
+        out["sphere_499280tri_10Mseg_all_first_k4"] = {
+            "build_ms": round(med(b), 4), "query_ms": round(med(q), 4),
+            "msegments_per_s": round(w.n_r / med(q) / 1e3, 2), "query_bool_ms": round(med(qb), 4),
+            "overflowed_segments": int(st["overflow_segments"]), "spilled_crossings": int(st["overflow_crossings"]),
+            "deep_pass_segments": int(st["deep_segments"])}
+        log(f"sphere all|first: query {med(q):.3f} ms, bool {med(qb):.3f} ms, build {med(b):.3f} ms, stats {st}")
+        # odd-parity inside test of 10M points against the same closed surface
+        P = torch.from_numpy(wl.inside_points(w.V, w.n_r, wl.seed_for(6, 1))).to(dev)
+        ins = torch.empty(w.n_r, dtype=torch.uint8, device=dev)
+        cnt = torch.empty(w.n_r, dtype=torch.int32, device=dev)
+        ends = torch.empty(w.n_r, 3, dtype=torch.float32, device=dev)
+        qi = time_events(lambda: rsi.rsi_inside(m.handle, P, ins, cnt, ends), 5)
+        out["sphere_499280tri_10Mpoint_inside"] = {
+            "ms": round(med(qi), 4), "mpoints_per_s": round(w.n_r / med(qi) / 1e3, 2),
+            "inside_fraction": round(float(ins.float().mean().item()), 5)}
+        log(f"inside test: {med(qi):.3f} ms for {w.n_r} points")
+        m.close()
+        del V, T, S, E, o, ob, P, ins, cnt, ends
+
+    if "c4" in sections:
+        # differentiable first hit: 199,712-triangle heightfield, 4M segments
+        w = wl.config4()
+        Vg, _ = wl.config4_target()
+        V, T, S, E = (torch.from_numpy(x).to(dev) for x in (w.V, w.T, w.S, w.E))
+        n = 317
+        gz = torch.from_numpy(Vg[:, 2].astype(np.float32)).to(dev)
+        X = torch.clamp(S[:, 0] * (n - 1), 0, n - 1 - 1e-6)
+        Y = torch.clamp(S[:, 1] * (n - 1), 0, n - 1 - 1e-6)
+        i, j = X.long(), Y.long()
+        a, c = X - i, Y - j
+        k = j * n + i
+        target = (gz[k] * (1 - a) * (1 - c) + gz[k + 1] * a * (1 - c) + gz[k + n] * (1 - a) * c
+                  + gz[k + n + 1] * a * c)
+        m = rsi.Mesh(V, T)
+        Vp = V.clone().requires_grad_(True)
+
+        def fwd():
+            with torch.no_grad():
+                _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
+                return ((P[:, 2] - target) ** 2).sum()
+
+        def fwd_bwd():
+            Vp.grad = None
+            _, _, P, _ = rsi.FirstHit.apply(Vp, S, E, m)
+            loss = ((P[:, 2] - target) ** 2).sum()
+            loss.backward()
+
+        f = time_events(fwd, 10)
+        fb = time_events(fwd_bwd, 10)
+        out["heightfield_199712tri_4Mseg_first_hit_grad"] = {
+            "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
+            "backward_ms": round(med(fb) - med(f), 4),
+            "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
+            "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
+            "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
+        log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms")
+        m.close()
+        del V, T, S, E, Vp
+
+    if "c5" in sections:
+        # 64 meshes: one captured graph (rebuild all + one batched query) per mode,
+        # with options chosen by the autotuner on this batch, against 64
+        # sequential plain calls (rebuild + query per mesh)
+        from paper_2209_02878_amd import tune
+        t0 = time.time()
+        ws = wl.config5()
+        log(f"64-mesh batch generated in {time.time() - t0:.1f}s: {sum(x.n_t for x in ws)} triangles, "
+            f"{sum(x.n_r for x in ws)} segments")
+        meshes = [(torch.from_numpy(x.V).to(dev), torch.from_numpy(x.T).to(dev)) for x in ws]
+        segs = [(torch.from_numpy(x.S).to(dev), torch.from_numpy(x.E).to(dev)) for x in ws]
+        singles = [rsi.Mesh(Vm, Tm) for Vm, Tm in meshes]
+        ntot = sum(x.n_r for x in ws)
+        bt = rsi.Batch(meshes)
+        for mode in ("bool", "first"):
+            t0 = time.time()
+            opts = tune.autotune(bt, segs, mode=mode, kind="batch64", n_t=sum(x.n_t for x in ws), n_r=ntot,
+                                 cache_path=None)
+            t_tune = time.time() - t0
+            for sm in singles:
+                sm.set_opts(**opts)  # a new leaf size applies at the rebuild of each sequential step
+            souts = [sm.alloc_outputs(Sm.shape[0], mode) for sm, (Sm, _) in zip(singles, segs)]
+
+            def sequential():
+                for sm, (Vm, Tm), (Sm, Em), so in zip(singles, meshes, segs, souts):
+                    sm.rebuild(Vm, Tm)
+                    sm.query_into(Sm, Em, mode, so)
+
+            bouts = bt.alloc_outputs(segs, mode)
+            bt.capture(segs, mode, bouts, rebuild=True)
+            seq = time_events(sequential, 3)
+            rep = time_events(bt.replay, 10)
+            torch.cuda.synchronize()
+            same = all(torch.equal(bo[key], so[key]) for bo, so in zip(bouts, souts) for key in so)
+            out[f"batch_64_meshes_{mode}"] = {
+                "n_t": int(sum(x.n_t for x in ws)), "n_r": int(ntot), "tuned_options": opts,
+                "autotune_s": round(t_tune, 2),
+                "graph_replay_ms": round(med(rep), 4), "sequential_64_calls_ms": round(med(seq), 4),
+                "graph_msegments_per_s": round(ntot / med(rep) / 1e3, 2),
+                "speedup_vs_sequential": round(med(seq) / med(rep), 3), "identical_to_sequential": bool(same)}
+            log(f"batch {mode}: tuned {opts} in {t_tune:.1f}s; graph {med(rep):.3f} ms vs sequential "
+                f"{med(seq):.3f} ms, identical={same}")
+            del bouts, souts
+        bt.close()
         for sm in singles:
-            sm.set_opts(**opts)  # a new leaf size applies at the rebuild of each sequential step
-        souts = [sm.alloc_outputs(Sm.shape[0], mode) for sm, (Sm, _) in zip(singles, segs)]
-
-        def sequential():
-            for sm, (Vm, Tm), (Sm, Em), so in zip(singles, meshes, segs, souts):
-                sm.rebuild(Vm, Tm)
-                sm.query_into(Sm, Em, mode, so)
-
-        bouts = bt.alloc_outputs(segs, mode)
-        bt.capture(segs, mode, bouts, rebuild=True)
-        seq = time_events(sequential, 3)
-        rep = time_events(bt.replay, 10)
-        torch.cuda.synchronize()
-        same = all(torch.equal(bo[key], so[key]) for bo, so in zip(bouts, souts) for key in so)
-        out[f"batch_64_meshes_{mode}"] = {
-            "n_t": int(sum(x.n_t for x in ws)), "n_r": int(ntot), "tuned_options": opts,
-            "autotune_s": round(t_tune, 2),
-            "graph_replay_ms": round(med(rep), 4), "sequential_64_calls_ms": round(med(seq), 4),
-            "graph_msegments_per_s": round(ntot / med(rep) / 1e3, 2),
-            "speedup_vs_sequential": round(med(seq) / med(rep), 3), "identical_to_sequential": bool(same)}
-        log(f"batch {mode}: tuned {opts} in {t_tune:.1f}s; graph {med(rep):.3f} ms vs sequential "
-            f"{med(seq):.3f} ms, identical={same}")
-        del bouts, souts
-    bt.close()
-    for sm in singles:
-        sm.close()
+            sm.close()
     return out
 
 
@@ -347,6 +359,9 @@ def main():
                     help="only the 29,768-triangle step (for profiler runs)")
     ap.add_argument("--branching", type=int, default=0, choices=(0, 2, 4),
                     help="walk for the headline step: 4 = quantised four-way view (the default), 2 = binary tree")
+    ap.add_argument("--extra", default=None,
+                    help="comma list of the other workloads to run: " + ", ".join(EXTRA_SECTIONS) +
+                         " (with --headline-only: none unless given)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device copy (known traffic for HBM counter scaling)")
     args = ap.parse_args()
@@ -487,9 +502,16 @@ def main():
         rec["copy_calibration_bytes"] = 2 * x.numel() * 4
         del x, y
 
-    if not args.headline_only:
+    if args.extra is None:
+        sections = [] if args.headline_only else list(EXTRA_SECTIONS)
+    else:
+        sections = [x for x in args.extra.split(",") if x]
+    unknown = set(sections) - set(EXTRA_SECTIONS)
+    if unknown:
+        raise SystemExit(f"unknown --extra sections: {sorted(unknown)}")
+    if sections:
         mesh.close()
-        rec["extra"] = extra_workloads(torch, rsi, wl, dev, time_events, w, V, T, S, E)
+        rec["extra"] = extra_workloads(torch, rsi, wl, dev, time_events, w, V, T, S, E, set(sections))
 
     if not args.no_cpu_baseline:
         # near-degenerate segments per workload (oracle classifier on samples)
@@ -504,7 +526,7 @@ def main():
         log(f"near-degenerate samples ({time.time() - t0:.1f}s): {rec['near_degenerate']}")
         rec["cpu_baseline"] = cpu_baseline(w, None, args.cpu_seconds, log)
         log(f"cpu baseline: {rec['cpu_baseline']}")
-    if args.headline_only:
+    if not sections:
         mesh.close()
     print(json.dumps(rec), flush=True)
 

@@ -138,9 +138,10 @@ rsi_status rsi_rebuild(rsi_handle h, const float *V, int64_t n_v, const int32_t 
 
 /* Recompute every bound and the packed geometry from new vertex positions
  * with the same triangles and the same tree topology (the bottom-up pass of
- * Section 3.1 with its arrival counters).  V: device float32 [n_v*3].
- * Asynchronous on `stream`. */
-rsi_status rsi_refit(rsi_handle h, const float *V, void *stream);
+ * Section 3.1 with its arrival counters).  V: device float32 [n_v*3], n_v
+ * the vertex count of the last build or rebuild (RSI_E_INVALID otherwise:
+ * the triangles index that many vertices).  Asynchronous on `stream`. */
+rsi_status rsi_refit(rsi_handle h, const float *V, int64_t n_v, void *stream);
 
 /* Test n_r segments (paper Section 1; traversal of Section 3.2, kernel of
  * Section 3.3).
@@ -172,7 +173,9 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
  * S + t (E - S) = v0 + u (v1 - v0) + v (v2 - v0): the differentiable form of
  * the paper's `barycentric` output (Section 2.4).
  *   V        device float32 [n_v*3]: the vertices the handle was built or
- *            refit with (read-only)
+ *            refit with (read-only); n_v must be the vertex count of the
+ *            last build or rebuild (RSI_E_INVALID otherwise), since dV has
+ *            that many rows and every triangle index is below it
  *   S, E     device float32 [n_r*3]: the segments of the forward query
  *   tri      device int32 [n_r]: first-hit triangle ids from the forward
  *            query (-1 = miss, contributes nothing)
@@ -192,9 +195,9 @@ rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
  * rsi_build / rsi_rebuild, kept across rsi_refit).
  * Asynchronous on `stream`.  Errors: RSI_E_INVALID (NULL pointers, n_r out
  * of range), RSI_E_NOMEM, RSI_E_HIP. */
-rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,
-                                  const int32_t *tri, const float *g_t, const float *g_uv, const float *g_point,
-                                  float *dV, float *dS, float *dE, void *stream);
+rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, int64_t n_v, const float *S, const float *E,
+                                  int64_t n_r, const int32_t *tri, const float *g_t, const float *g_uv,
+                                  const float *g_point, float *dV, float *dS, float *dE, void *stream);
 
 /* After an RSI_ALL_HITS query (waits for it): entries of the overflow
  * table and pool entries in use (host out-parameters). */

@@ -16,7 +16,8 @@
 // around the vertex.  It is formed without any atomic operation, in a fixed
 // order, so every call gives the same bits:
 //   k_adj_solve   one lane per segment, in input order (coalesced): the
-//                 solve, dS and dE, and a record of (lambda, u, v) with the
+//                 solve, dS and dE, and a record of lambda and the three
+//                 corner weights (1 - u - v, u, v) with the
 //                 sort pair (Morton position of the hit triangle, segment)
 //   (sort.hip)    one stable pass per 8 bits of the cell index (position >>
 //                 10): the pairs of each cell of 1,024 consecutive
@@ -66,8 +67,8 @@ struct AdjArgs {
     float *dV;
     float *dS;
     float *dE;
-    float4 *rec;          // per segment: lambda.x, lambda.y, lambda.z, u
-    float *rec_v;         // per segment: v
+    float4 *rec;          // per segment: lambda.x, lambda.y, lambda.z, 1 - u - v
+    float2 *rec_v;        // per segment: u, v
     uint64_t *keys;       // per segment: sorted position of the hit triangle, n_t when none
     uint32_t *vals;       // per segment: its index
     double *tri_sum;      // per sorted triangle: 3 corners x 3 axes
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
     if (i >= a.n_r) return;
     double gs[3] = {0.0, 0.0, 0.0}, ge[3] = {0.0, 0.0, 0.0};
     float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float rv = 0.0f;
+    float2 rv = make_float2(0.0f, 0.0f);
     uint64_t key = (uint64_t)a.n_t;
     const int32_t j = a.tri[i];
     if (j >= 0 && j < a.n_t) {
@@ -129,8 +130,11 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
                 ge[0] = t * w.x;
                 ge[1] = t * w.y;
                 ge[2] = t * w.z;
-                r = make_float4((float)lam.x, (float)lam.y, (float)lam.z, (float)u);
-                rv = (float)v;
+                // the three corner weights are rounded separately from their
+                // FP64 values: 1 - u - v formed later from rounded u and v
+                // would lose its relative accuracy near the edge v1 v2
+                r = make_float4((float)lam.x, (float)lam.y, (float)lam.z, (float)(1.0 - u - v));
+                rv = make_float2((float)u, (float)v);
                 key = (uint64_t)a.rank[j];
             }
         }
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_tri(AdjArgs a, const uint64_t 
     __shared__ uint32_t wcnt[kTriItems * kWaves * kRadix];
     __shared__ uint32_t run[kRadix], start[kRadix];
     __shared__ float4 srec[kTriTile];
-    __shared__ float srv[kTriTile];
+    __shared__ float2 srv[kTriTile];
     __shared__ int64_t range[2];
     const int tid = threadIdx.x;
     const int64_t g = blockIdx.x / kGroupsPerCell;
@@ -208,8 +212,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_tri(AdjArgs a, const uint64_t 
         const uint32_t b = start[tid], e = b + run[tid];
         for (uint32_t p = b; p < e; ++p) {
             const float4 rr = srec[p];
-            const double u = rr.w, v = srv[p];
-            const double w[3] = {-(1.0 - u - v), -u, -v};
+            const float2 uv = srv[p];
+            const double w[3] = {-(double)rr.w, -(double)uv.x, -(double)uv.y};
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 acc[3 * c] += w[c] * (double)rr.x;

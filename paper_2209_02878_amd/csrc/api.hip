@@ -378,11 +378,12 @@ rsi_status rsi_rebuild(rsi_handle h, const float *V, int64_t n_v, const int32_t 
     return finish_build(h, s, "rsi_rebuild");
 }
 
-rsi_status rsi_refit(rsi_handle h, const float *V, void *stream)
+rsi_status rsi_refit(rsi_handle h, const float *V, int64_t n_v, void *stream)
 {
     set_error("");
     if (!h) return invalid("rsi_refit: NULL handle");
     if (h->M != 1) return invalid("rsi_refit: batch handle");
+    if (n_v != h->n_v) return invalid("rsi_refit: n_v differs from the vertex count of the last build");
     if (h->n_t > 0 && !V) return invalid("rsi_refit: NULL vertices");
     hipError_t e = rsi::launch_refit(h, V, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rsi_refit");
@@ -536,13 +537,15 @@ rsi_status rsi_compact(rsi_handle h, const uint8_t *hit, const int32_t *tri, con
     return e == hipSuccess ? RSI_OK : hip_fail(e, "rsi_compact");
 }
 
-rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, const float *S, const float *E, int64_t n_r,
-                                  const int32_t *tri, const float *g_t, const float *g_uv, const float *g_point,
-                                  float *dV, float *dS, float *dE, void *stream)
+rsi_status rsi_first_hit_backward(rsi_handle h, const float *V, int64_t n_v, const float *S, const float *E,
+                                  int64_t n_r, const int32_t *tri, const float *g_t, const float *g_uv,
+                                  const float *g_point, float *dV, float *dS, float *dE, void *stream)
 {
     set_error("");
     if (!h) return invalid("rsi_first_hit_backward: NULL handle");
     if (h->M != 1) return invalid("rsi_first_hit_backward: batch handle");
+    if (n_v != h->n_v)
+        return invalid("rsi_first_hit_backward: n_v differs from the vertex count of the last build");
     if (n_r < 0 || n_r >= (int64_t(1) << 30)) return invalid("rsi_first_hit_backward: n_r must be in [0, 2^30)");
     if (n_r == 0) return RSI_OK;
     if (!S || !E || !tri) return invalid("rsi_first_hit_backward: NULL S, E or tri");

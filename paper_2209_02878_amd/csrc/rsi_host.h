@@ -161,7 +161,7 @@ struct rsi_bvh {
     // the vertex incidence table of the current topology
     float4 *adj_rec = nullptr;
     int64_t adj_rec_cap = 0;
-    float *adj_rec_v = nullptr;
+    float2 *adj_rec_v = nullptr;
     int64_t adj_rec_v_cap = 0;
     double *tri_sum = nullptr;
     int64_t tri_sum_cap = 0;

@@ -98,13 +98,13 @@ def lib():
     H = ctypes.c_void_p
     L.rsi_build.argtypes = [P, i64, P, i64, ctypes.POINTER(rsi_opts), P, ctypes.POINTER(H)]
     L.rsi_rebuild.argtypes = [H, P, i64, P, P]
-    L.rsi_refit.argtypes = [H, P, P]
+    L.rsi_refit.argtypes = [H, P, i64, P]
     L.rsi_query.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
     L.rsi_inside.argtypes = [H, P, i64, P, P, P, P]
     L.rsi_segment_order.argtypes = [H, P, P, i64, P, P]
     L.rsi_gather_segments.argtypes = [H, P, P, P, i64, P, P, P]
     L.rsi_compact.argtypes = [H, P, P, P, P, P, P, i64, P, P, P, P, ctypes.POINTER(i64), P]
-    L.rsi_first_hit_backward.argtypes = [H, P, P, P, i64, P, P, P, P, P, P, P, P]
+    L.rsi_first_hit_backward.argtypes = [H, P, i64, P, P, i64, P, P, P, P, P, P, P, P]
     L.rsi_spill_info.argtypes = [H, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.rsi_spill_read.argtypes = [H, P, P, P, P, P, P]
     L.rsi_query_stats.argtypes = [H, ctypes.POINTER(rsi_stats)]
@@ -186,7 +186,7 @@ def rsi_rebuild(h, V, T, stream=None):
 
 def rsi_refit(h, V, stream=None):
     V = _dev_f32(V, "V")
-    _check(lib().rsi_refit(h, _ptr(V), _stream(stream)))
+    _check(lib().rsi_refit(h, _ptr(V), V.shape[0], _stream(stream)))
 
 
 def rsi_query(h, S, E, mode, out: rsi_outputs, stream=None):
@@ -215,7 +215,7 @@ def rsi_first_hit_backward(h, V, S, E, tri, g_t=None, g_uv=None, g_point=None, d
         dS = torch.empty_like(S)
     if dE is None:
         dE = torch.empty_like(E)
-    _check(lib().rsi_first_hit_backward(h, _ptr(V), _ptr(S), _ptr(E), n, _ptr(tri), _ptr(g_t), _ptr(g_uv),
+    _check(lib().rsi_first_hit_backward(h, _ptr(V), V.shape[0], _ptr(S), _ptr(E), n, _ptr(tri), _ptr(g_t), _ptr(g_uv),
                                         _ptr(g_point), _ptr(dV), _ptr(dS), _ptr(dE), _stream(stream)))
     return dV, dS, dE
 

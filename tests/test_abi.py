@@ -48,8 +48,8 @@ def test_status_strings_without_device():
 
 def test_null_handle_is_rejected_without_device():
     L = _lib_or_skip()
-    L.rsi_refit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    assert L.rsi_refit(None, None, None) == rsi.RSI_E_INVALID
+    L.rsi_refit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert L.rsi_refit(None, None, 0, None) == rsi.RSI_E_INVALID
     L.rsi_last_error.restype = ctypes.c_char_p
     assert b"NULL handle" in L.rsi_last_error()
     out = ctypes.c_void_p()

@@ -21,12 +21,16 @@ from paper_2209_02878_amd import workloads as wl
 CELL_BITS, GROUP_BITS, TILE = 10, 8, 1024
 
 
-def _model(V, T, S, E, tri, g_p, rank):
+def _model(V, T, S, E, tri, g_p, rank, corner0="fp64"):
+    """dV as the device forms it.  The record holds lambda and the corner
+    weights rounded to FP32; corner0="fp64" rounds 1 - u - v from its FP64
+    value (the device's record), corner0="from_uv" forms it from the rounded
+    u and v instead (shown below to lose accuracy near the edge v1 v2)."""
     n_t, n_r = T.shape[0], S.shape[0]
-    # k_adj_solve: per segment, lambda and (u, v) (here in FP64; the device
-    # stores them in FP32), the key (sorted position or n_t)
+    # k_adj_solve: per segment, lambda and the corner weights (FP32), the
+    # key (sorted position or n_t)
     keys = np.full(n_r, n_t, np.int64)
-    rec = np.zeros((n_r, 5))
+    rec = np.zeros((n_r, 6))
     for i in range(n_r):
         j = tri[i]
         if j < 0:
@@ -40,7 +44,9 @@ def _model(V, T, S, E, tri, g_p, rank):
         t, u, v = np.linalg.solve(M, s - v0)
         tb = g_p[i] @ d
         lam = np.linalg.solve(M.T, np.array([tb, 0.0, 0.0]))
-        rec[i] = [*lam, u, v]
+        f = lambda x: float(np.float32(x))
+        w0 = f(1.0 - u - v) if corner0 == "fp64" else 1.0 - f(u) - f(v)
+        rec[i] = [f(lam[0]), f(lam[1]), f(lam[2]), w0, f(u), f(v)]
         keys[i] = rank[j]
     # stable grouping by cell
     order = np.argsort(keys >> CELL_BITS, kind="stable")
@@ -60,8 +66,8 @@ def _model(V, T, S, E, tri, g_p, rank):
             # stable rank by position within the tile, then per-triangle order
             local = ks[sel] & 0xFF
             for p in np.argsort(local, kind="stable"):
-                lam, u, v = rec[segs[sel][p], :3], rec[segs[sel][p], 3], rec[segs[sel][p], 4]
-                w = np.array([-(1.0 - u - v), -u, -v])
+                r = rec[segs[sel][p]]
+                lam, w = r[:3], -r[3:6]
                 acc[local[p]] += w[:, None] * lam[None, :]
         base = group << GROUP_BITS
         m = min(1 << GROUP_BITS, max(0, n_t - base))
@@ -93,6 +99,40 @@ def test_adjoint_grouping_model_matches_oracle_gradient():
     g_p = np.zeros((S.shape[0], 3))
     g_p[:, 2] = rng.standard_normal(S.shape[0])
     dV = _model(V, T, S, E, tri, g_p, rank)
-    rV, _, _ = oracle.first_hit_grad(V, T, S, E, tri, ref["first_tuv"], g_p=g_p)
-    assert np.abs(dV - rV).max() <= 1e-9 * np.abs(rV).max()
+    rV, _, _, rabs = oracle.first_hit_grad(V, T, S, E, tri, ref["first_tuv"], g_p=g_p, with_abs=True)
+    # the device's bar: within 1e-5 of the sum of absolute contributions
+    assert np.all(np.abs(dV - rV) <= 1e-5 * rabs + 1e-30)
+    assert np.abs(dV - rV).max() <= 1e-6 * np.abs(rV).max()
     assert np.count_nonzero(rV) > 0
+
+
+def test_corner_weight_rounding_near_an_edge():
+    """Hits close to the edge v1 v2 give vertex v0 only small weights
+    1 - u - v.  Formed from u and v already rounded to FP32, that weight keeps
+    an absolute error of a few 1e-8, which is then a large share of the small
+    sum of |contributions| at v0 and breaks the per-element bar; rounded from
+    its FP64 value it keeps FP32 relative accuracy and meets it."""
+    V = np.array([[0.1, 0.2, 0.0], [1.3, 0.1, 0.05], [0.15, 1.1, -0.03]], np.float32)
+    T = np.array([[0, 1, 2]], np.int32)
+    rng = np.random.default_rng(9)
+    n = 8
+    # vertical segments through points with 1 - u - v in [1e-5, 1e-4]
+    w0 = rng.uniform(1e-5, 1e-4, n)
+    u = rng.uniform(0.2, 0.8, n) * (1.0 - w0)
+    v = 1.0 - w0 - u
+    Vd = V.astype(np.float64)
+    xy = (w0[:, None] * Vd[0] + u[:, None] * Vd[1] + v[:, None] * Vd[2])[:, :2]
+    S = np.concatenate([xy, np.full((n, 1), 1.0)], 1).astype(np.float32)
+    E = np.concatenate([xy, np.full((n, 1), -1.0)], 1).astype(np.float32)
+    ref = oracle.query(V, T, S, E)
+    tri = ref["first_tri"]
+    assert np.all(tri == 0)
+    g_p = np.zeros((n, 3))
+    g_p[:, 2] = 1.0
+    rV, _, _, rabs = oracle.first_hit_grad(V, T, S, E, tri, ref["first_tuv"], g_p=g_p, with_abs=True)
+    rank = np.zeros(1, np.int64)
+    good = _model(V, T, S, E, tri, g_p, rank, corner0="fp64")
+    bad = _model(V, T, S, E, tri, g_p, rank, corner0="from_uv")
+    ratio = lambda d: np.max(np.abs(d - rV) / (rabs + 1e-30))
+    assert ratio(good) <= 1e-6
+    assert ratio(bad) > 1e-5

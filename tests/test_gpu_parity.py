@@ -216,6 +216,13 @@ def test_invalid_arguments():
         m.query_into(S, S, 8, {})
     with pytest.raises(rsi.RsiError):
         m.query_into(S, S, rsi.RSI_BOOL, {})
+    # refit and the adjoint take vertex arrays of the built size only
+    V4 = _t(np.zeros((4, 3), np.float32))
+    with pytest.raises(rsi.RsiError, match="n_v"):
+        rsi.rsi_refit(m.handle, V4)
+    tri = torch.zeros(4, dtype=torch.int32, device=DEV)
+    with pytest.raises(rsi.RsiError, match="n_v"):
+        rsi.rsi_first_hit_backward(m.handle, V4, S, S, tri)
     m.close()
 
 
