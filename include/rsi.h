@@ -168,6 +168,33 @@ rsi_status rsi_refit(rsi_handle h, const float *V, int64_t n_v, void *stream);
 rsi_status rsi_query(rsi_handle h, const float *S, const float *E, int64_t n_r,
                      uint32_t mode, const rsi_outputs *out, void *stream);
 
+/* rsi_query for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * handle, inputs and outputs are the caller's, as for rsi_query; the
+ * library's own scratch (the deep pass's queue and stack) comes from one
+ * fixed 32 MiB device array per GPU, held from the first call on that GPU
+ * until the process ends.  No allocation of any kind is made, and nothing
+ * is waited for.
+ *   mode  nonzero mask of RSI_BOOL, RSI_FIRST_HIT, RSI_COUNT (RSI_ALL_HITS
+ *         needs memory that grows with the crossings and is rejected)
+ *   S, E, n_r, out as for rsi_query (only the arrays of `mode` are used)
+ * The array holds the deep pass's stack (its size depends on block_size and
+ * the stack options; about 16 MB at the defaults on 256 CUs) and a queue
+ * of one entry per segment; a query with more segments than the queue
+ * holds (about 4.3 million at the defaults) runs as consecutive parts of
+ * that many segments each, with the same kernels and results as rsi_query.
+ * rsi_query_stats then reports the last part's deep-pass count and the
+ * flags of every part.
+ * Every call on a GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other handles, other threads) race and must be
+ * ordered by the caller.  Its contents need no clearing between calls.
+ * Errors: as rsi_query, plus RSI_E_INVALID when the current device is not
+ * the handle's, for a batch handle, or when the options' deep-pass stack
+ * leaves no room in the array (a block_size of 256 with the deepest stack
+ * bound comes close; use a smaller block_size or rsi_query). */
+rsi_status rsi_query_noalloc(rsi_handle h, const float *S, const float *E, int64_t n_r, uint32_t mode,
+                             const rsi_outputs *out, void *stream);
+
 /* Gradient of the first hit (t, u, v, P of RSI_FIRST_HIT) with respect to
  * the vertices and both segment ends, by the adjoint of the crossing system
  * S + t (E - S) = v0 + u (v1 - v0) + v (v2 - v0): the differentiable form of

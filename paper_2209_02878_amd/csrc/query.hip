@@ -1074,12 +1074,16 @@ __global__ void k_parity(const int32_t *__restrict__ count, int64_t n, uint8_t *
 
 // Reset the per-query device scalars with a kernel rather than a memset, so
 // the sequence can be captured.
-__global__ void k_reset(int32_t *scalars, Counters *c)
+// Zero the per-query scalars.  keep != 0 (a later part of a query split
+// into parts) keeps the flags of damaged-tree walks and the work counters,
+// so they describe every part.
+__global__ void k_reset(int32_t *scalars, Counters *c, int keep)
 {
-    const int32_t zero[] = {kWorkNext, kWorkRetry, kRetryN, kRetryLost, kStackDropped, kWalkCut,
-                            kOvfSegs, kOvfTotalLo, kOvfTotalHi, kArenaLo, kArenaHi, kOvfFull};
-    for (int k = 0; k < (int)(sizeof(zero) / sizeof(zero[0])); ++k) scalars[zero[k]] = 0;
-    if (c) {
+    const int32_t zero[] = {kWorkNext, kWorkRetry, kRetryN, kOvfSegs, kOvfTotalLo, kOvfTotalHi, kArenaLo,
+                            kArenaHi, kOvfFull, kRetryLost, kStackDropped, kWalkCut};
+    const int n = (int)(sizeof(zero) / sizeof(zero[0])) - (keep ? 3 : 0);
+    for (int k = 0; k < n; ++k) scalars[zero[k]] = 0;
+    if (c && !keep) {
         c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
         c->wave_loops = c->wave_node_steps = c->wave_leaf_phases = c->wave_refills = 0;
         c->lanes_blocked = c->lanes_waiting = 0;
@@ -1328,11 +1332,11 @@ hipError_t launch_query(rsi_bvh *h, const float *S, const float *E, int64_t n_r,
                         const QueryOut &o, hipStream_t s)
 {
     const QueryScratch sc = {h->retry_q, h->retry_cap, h->retry_stack, h->retry_stack_cap};
-    return launch_query_scratch(h, S, E, n_r, mode, o, sc, s);
+    return launch_query_scratch(h, S, E, n_r, mode, o, sc, false, s);
 }
 
 hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
-                                const QueryOut &o, const QueryScratch &sc, hipStream_t s)
+                                const QueryOut &o, const QueryScratch &sc, bool keep_flags, hipStream_t s)
 {
     if (n_r == 0) return hipSuccess;
     const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
@@ -1345,7 +1349,8 @@ hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int6
     a.gstack_cap = sc.gstack_cap;
     if (a.retry_cap < n_r) return hipErrorInvalidValue;
     pass_args(h, a, d, ld);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, h->counting ? h->counters : nullptr);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, h->counting ? h->counters : nullptr,
+                       keep_flags ? 1 : 0);
     hipError_t e = h->counting ? dispatch<true>(mode, a, d, block, lds, s) : dispatch<false>(mode, a, d, block, lds, s);
     if (e == hipSuccess && (mode & M_FIRST)) e = launch_refine_first<false>(a, s);
     if (e == hipSuccess && (mode & M_ALL)) e = launch_all_hits_tail(a, false, s);
@@ -1367,7 +1372,7 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
     QArgs a = make_args(h, nullptr, nullptr, n_total, o), d;
     a.bt = bt;
     pass_args(h, a, d, ld);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr, 0);
     hipError_t e;
     switch (mode) {
     case M_BOOL: e = launch_passes<M_BOOL, false, true>(a, d, block, lds, s); break;
@@ -1471,7 +1476,7 @@ hipError_t launch_parity(const int32_t *count, int64_t n, uint8_t *inside, hipSt
 
 hipError_t launch_clear_query(rsi_bvh *h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, h->scalars, nullptr, 0);
     return hipGetLastError();
 }
 

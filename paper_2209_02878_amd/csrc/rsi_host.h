@@ -226,9 +226,11 @@ struct QueryScratch {
     int32_t *gstack;
     int64_t gstack_cap;
 };
-// launch_query with the deep pass's memory given by the caller
+// launch_query with the deep pass's memory given by the caller; keep_flags
+// (a later part of a query split into parts) keeps the damaged-tree flags
+// and work counters of the earlier parts
 hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int64_t n_r, uint32_t mode,
-                                const QueryOut &o, const QueryScratch &sc, hipStream_t s);
+                                const QueryOut &o, const QueryScratch &sc, bool keep_flags, hipStream_t s);
 // stack entries (int32) the deep pass of a query in `mode` needs
 int64_t deep_stack_entries(const rsi_bvh *h, uint32_t mode);
 hipError_t launch_fill_miss(int64_t n_r, uint32_t mode, const QueryOut &o, hipStream_t s);

@@ -23,7 +23,7 @@ RSI_BOOL, RSI_FIRST_HIT, RSI_ALL_HITS, RSI_COUNT = 1, 2, 4, 8
 MODE_NAMES = {"bool": RSI_BOOL, "first": RSI_FIRST_HIT, "all": RSI_ALL_HITS, "count": RSI_COUNT}
 
 EXPORTED = [
-    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_compact", "rsi_segment_order", "rsi_gather_segments", "rsi_inside", "rsi_first_hit_backward",
+    "rsi_build", "rsi_rebuild", "rsi_refit", "rsi_query", "rsi_query_noalloc", "rsi_compact", "rsi_segment_order", "rsi_gather_segments", "rsi_inside", "rsi_first_hit_backward",
     "rsi_spill_info", "rsi_spill_read", "rsi_query_stats",
     "rsi_set_counting", "rsi_get_counters", "rsi_get_tree_info", "rsi_get_mesh_info", "rsi_export_tree",
     "rsi_batch_create", "rsi_batch_rebuild", "rsi_batch_query", "rsi_batch_capture", "rsi_batch_replay",
@@ -100,6 +100,7 @@ def lib():
     L.rsi_rebuild.argtypes = [H, P, i64, P, P]
     L.rsi_refit.argtypes = [H, P, i64, P]
     L.rsi_query.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
+    L.rsi_query_noalloc.argtypes = [H, P, P, i64, u32, ctypes.POINTER(rsi_outputs), P]
     L.rsi_inside.argtypes = [H, P, i64, P, P, P, P]
     L.rsi_segment_order.argtypes = [H, P, P, i64, P, P]
     L.rsi_gather_segments.argtypes = [H, P, P, P, i64, P, P, P]
@@ -195,6 +196,16 @@ def rsi_query(h, S, E, mode, out: rsi_outputs, stream=None):
     if S.shape != E.shape:
         raise ValueError("S and E must have the same shape")
     _check(lib().rsi_query(h, _ptr(S), _ptr(E), S.shape[0], mode, ctypes.byref(out), _stream(stream)))
+
+
+def rsi_query_noalloc(h, S, E, mode, out: rsi_outputs, stream=None):
+    """rsi_query without any device allocation (boolean, first-hit and count
+    modes); the library's scratch is a fixed array per GPU."""
+    S = _dev_f32(S, "S")
+    E = _dev_f32(E, "E")
+    if S.shape != E.shape:
+        raise ValueError("S and E must have the same shape")
+    _check(lib().rsi_query_noalloc(h, _ptr(S), _ptr(E), S.shape[0], mode, ctypes.byref(out), _stream(stream)))
 
 
 def rsi_first_hit_backward(h, V, S, E, tri, g_t=None, g_uv=None, g_point=None, dV=None, dS=None, dE=None,
@@ -433,6 +444,11 @@ class Mesh:
 
     def query_into(self, S, E, mode, out, capacity=4, stream=None):
         rsi_query(self.handle, S, E, parse_mode(mode), self.outputs_struct(out, capacity), stream)
+        return out
+
+    def query_noalloc_into(self, S, E, mode, out, stream=None):
+        """rsi_query_noalloc into caller-allocated outputs (see alloc_outputs)."""
+        rsi_query_noalloc(self.handle, S, E, parse_mode(mode), self.outputs_struct(out), stream)
         return out
 
     def query(self, S, E, mode="bool", capacity=4, stream=None):
