@@ -606,14 +606,16 @@ rsi_status rsi_query_stats(rsi_handle h, rsi_stats *out)
     out->walk_cut = c[rsi::kWalkCut] != 0;
     out->stack_dropped = c[rsi::kStackDropped] != 0;
     out->deep_segments = c[rsi::kRetryN];
-    out->overflow_segments = c[rsi::kOvfSegs];
+    out->overflow_segments = c[rsi::kOvfUsed];
     out->overflow_crossings = u64(rsi::kOvfTotalLo, rsi::kOvfTotalHi);
-    out->arena_records = u64(rsi::kArenaLo, rsi::kArenaHi);
+    out->arena_records = c[rsi::kArenaUsed];
+    // records handed out (in blocks; the arena must hold them all)
+    const int64_t arena_claimed = u64(rsi::kArenaLo, rsi::kArenaHi);
     out->pool_capacity = h->last_pool_cap;
     out->overflow_full = (c[rsi::kOvfFull] != 0 || c[rsi::kRetryLost] != 0) ? 1 : 0;
     if (out->overflow_full) {
         // the next all-hits query gets a pool and an arena that hold this one
-        int64_t want = out->overflow_crossings > out->arena_records ? out->overflow_crossings : out->arena_records;
+        int64_t want = out->overflow_crossings > arena_claimed ? out->overflow_crossings : arena_claimed;
         want += want / 4;
         if (want > h->pool_want) h->pool_want = want;
     }

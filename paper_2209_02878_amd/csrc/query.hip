@@ -193,6 +193,12 @@ __device__ inline void load_top(const Node4 *__restrict__ nodes4, int32_t entry,
     top[4 * l + 3] = make_uint4((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w);
 }
 
+// All hits: overflow-table entries and arena records are handed to lanes in
+// blocks, so the counters see one atomic per block instead of one per entry
+// or crossing (one address serialises them across the whole GPU).
+constexpr int32_t kEntBlock = 4;
+constexpr int32_t kArenaBlock = 8;
+
 // Per-lane query state for the segment it currently owns.
 // All-hits capacities up to this many keep the hit list in registers.
 constexpr int kRegSlots = 4;
@@ -211,6 +217,12 @@ struct Lane {
     const float *ep;
     int32_t mesh;      // batched queries: the segment's mesh
     int32_t hp0, hp1, hp2, hp3;  // all hits, capacity <= 4: the hit positions found so far
+    // all hits: the lane's next overflow-table entry and arena record, taken
+    // from blocks of kEntBlock / kArenaBlock claimed with one atomic each
+    // (a cursor at a multiple of the block size has used its block up);
+    // kept across the lane's segments, unused tails voided when it exits
+    int32_t ent_cur;
+    int32_t arn_cur;
     bool found;
     bool retry;        // the stack outgrew the pass's stack: the deep pass walks this segment again
 };
@@ -262,10 +274,13 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
                 }
             } else {
                 // past the slots: an arena record (entry, rank, position)
-                if (c == K) L.e = atomicAdd(&a.scalars[kOvfSegs], 1);
-                const unsigned long long r =
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&a.scalars[kArenaLo]), 1ull);
-                if (L.e < a.ovf_cap && r < (unsigned long long)a.arena_cap)
+                if (c == K) {
+                    if ((L.ent_cur & (kEntBlock - 1)) == 0) L.ent_cur = atomicAdd(&a.scalars[kOvfSegs], kEntBlock);
+                    L.e = L.ent_cur++;
+                }
+                if ((L.arn_cur & (kArenaBlock - 1)) == 0) L.arn_cur = atomicAdd(&a.scalars[kArenaLo], kArenaBlock);
+                const int32_t r = L.arn_cur++;
+                if (L.e < a.ovf_cap && r >= 0 && r < a.arena_cap)
                     a.arena[r] = make_int4(L.e, c, pos, 0);
                 else
                     atomicOr(&a.scalars[kOvfFull], 1);
@@ -298,19 +313,13 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         float *tt = BATCH ? a.bt.t[L.mesh] : a.o.t;
         float *uv = BATCH ? a.bt.uv[L.mesh] : a.o.uv;
         float *pt = BATCH ? a.bt.point[L.mesh] : a.o.point;
-        if (L.best_pos >= 0) {
-            // the hit's sorted position; k_refine_first re-solves it and
-            // writes the id, t, (u, v) and the point
-            tri[i] = L.best_pos;
-        } else {
-            st_nt(tri + i, -1);
-            st_nt(tt + i, INFINITY);
-            st_nt(uv + 2 * i, 0.0f);
-            st_nt(uv + 2 * i + 1, 0.0f);
-            st_nt(pt + 3 * i, 0.0f);
-            st_nt(pt + 3 * i + 1, 0.0f);
-            st_nt(pt + 3 * i + 2, 0.0f);
-        }
+        // the hit's sorted position, or -1: k_refine_first (in segment
+        // order, so its stores fill whole lines) re-solves a hit and writes
+        // the id, t, (u, v) and the point, or writes the miss values
+        (void)tt;
+        (void)uv;
+        (void)pt;
+        tri[i] = L.best_pos >= 0 ? L.best_pos : -1;
     }
     if ((MODE & M_COUNT) && !(MODE & M_ALL)) st_nt(a.o.count + i, L.count);
     if (MODE & M_ALL) {
@@ -320,16 +329,13 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         st_nt(cnt_out + i, L.count);
         int32_t *ids = slot_ids<BATCH>(a, L) + i * K;
         float *ts = slot_ts<BATCH>(a, L) + i * K;
-        if (L.count == 0) {
-            for (int c = 0; c < K; ++c) {
-                st_nt(ids + c, -1);
-                st_nt(ts + c, INFINITY);
-            }
-            if (soff) st_nt(soff + i, (int64_t)-1);
-        } else if (L.count <= K) {
-            // the hits' sorted positions (after the walk, k_refine_slots
-            // re-solves them, orders them by (t, id) and writes ids and t):
-            // kept in registers up to four, else already in the slots
+        // A segment with at most K crossings writes only its hits' sorted
+        // positions (kept in registers up to four, else already in the
+        // slots): k_refine_slots, running in segment order, re-solves them,
+        // orders them by (t, id), pads the slots and writes the spill
+        // offset, with stores that fill whole lines.  Stores from here land
+        // wherever the finishing lanes' segments lie, each a partial line.
+        if (L.count >= 1 && L.count <= K) {
             if (K <= kRegSlots) {
                 const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
                 const bool vec = K == kRegSlots && (reinterpret_cast<uintptr_t>(ids) & 15) == 0;
@@ -338,13 +344,10 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
                 } else {
 #pragma unroll
                     for (int c = 0; c < kRegSlots; ++c)
-                        if (c < K) ids[c] = c < L.count ? hp[c] : -1;
+                        if (c < L.count && c < K) ids[c] = hp[c];
                 }
-            } else {
-                for (int c = L.count; c < K; ++c) ids[c] = -1;
             }
-            if (soff) st_nt(soff + i, (int64_t)-1);
-        } else {
+        } else if (L.count > K) {
             // more crossings than slots: reserve the full list's range in the
             // pool and put the first K there; k_spill_place adds the arena
             // records, k_spill_finish orders the list and fills the slots
@@ -410,6 +413,8 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     Lane L;
     L.retry = false;
     L.e = -1;
+    L.ent_cur = 0;
+    L.arn_cur = 0;
     // work items number below 2^30 (checked at the boundary), so item and
     // chunk arithmetic is 32-bit; the chunk bounds are wave-uniform
     int32_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
@@ -781,6 +786,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
         }
 
     }
+    if constexpr ((MODE & M_ALL) != 0) {
+        // void the unused rest of the lane's blocks: k_spill_finish skips an
+        // entry whose count is negative, k_spill_place a record whose entry is
+        for (int32_t e = L.ent_cur; (e & (kEntBlock - 1)) != 0; ++e)
+            if (e >= 0 && e < a.ovf_cap) a.ovf_cnt[e] = -1;
+        for (int32_t r = L.arn_cur; (r & (kArenaBlock - 1)) != 0; ++r)
+            if (r >= 0 && r < a.arena_cap) a.arena[r] = make_int4(-1, 0, 0, 0);
+    }
     if (COUNT) {
         wave_add_u64(&a.counters->node_visits, visits);
         wave_add_u64(&a.counters->box_tests, boxes);
@@ -843,6 +856,7 @@ __global__ __launch_bounds__(256) void k_spill_place(QArgs a)
         const int64_t off = a.ovf_off[rec.x];
         if (off < 0 || off + cnt > a.o.pool_cap) continue;
         a.o.pool_ids[off + rec.y] = rec.z;
+        atomicAdd(&a.scalars[kArenaUsed], 1);
     }
 }
 
@@ -860,6 +874,7 @@ __global__ __launch_bounds__(256) void k_spill_finish(QArgs a)
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         const int32_t cnt = a.ovf_cnt[e];
         if (cnt < 0) continue;
+        atomicAdd(&a.scalars[kOvfUsed], 1);
         const int64_t off = a.ovf_off[e];
         if (off < 0 || off + cnt > a.o.pool_cap) continue;
         const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
@@ -925,6 +940,7 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
         const int32_t *cnt = a.o.count;
         int32_t *ids = a.o.ids;
         float *ts = a.o.ts;
+        int64_t *soff = a.o.spill_off;
         if (BATCH) {
             const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
             i = k - a.bt.seg_off[m];
@@ -933,11 +949,27 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
             cnt = a.bt.count[m];
             ids = a.bt.ids[m];
             ts = a.bt.ts[m];
+            soff = a.bt.spill_off[m];
         }
         const int32_t n = cnt[i];
-        if (n < 1 || n > K) continue;
+        if (n > K) continue;  // overflowed: k_spill_finish fills the slots, the walk set the offset
+        if (soff) st_nt(soff + i, (int64_t)-1);
         ids += i * (int64_t)K;
         ts += i * (int64_t)K;
+        const bool vec = K == kRegSlots && ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
+        if (n == 0) {
+            // no crossing: padding only (no segment data needed)
+            if (vec) {
+                st_nt4(ids, -1, -1, -1, -1);
+                st_nt4(ts, INFINITY, INFINITY, INFINITY, INFINITY);
+            } else {
+                for (int c = 0; c < K; ++c) {
+                    ids[c] = -1;
+                    ts[c] = INFINITY;
+                }
+            }
+            continue;
+        }
         const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
         const float ex = ld_nt(E + 3 * i), ey = ld_nt(E + 3 * i + 1), ez = ld_nt(E + 3 * i + 2);
         if (K <= kRegSlots) {
@@ -977,15 +1009,13 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
 #pragma unroll
             for (int c = 0; c < kRegSlots; ++c)
                 if (c >= n) id[c] = -1;
-            const bool vec = K == kRegSlots &&
-                             ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
             if (vec) {
                 st_nt4(ids, id[0], id[1], id[2], id[3]);
                 st_nt4(ts, t[0], t[1], t[2], t[3]);
             } else {
                 for (int c = 0; c < K; ++c) {
-                    st_nt(ids + c, id[c]);
-                    st_nt(ts + c, t[c]);
+                    ids[c] = id[c];
+                    ts[c] = t[c];
                 }
             }
         } else {
@@ -1080,7 +1110,7 @@ __global__ void k_parity(const int32_t *__restrict__ count, int64_t n, uint8_t *
 __global__ void k_reset(int32_t *scalars, Counters *c, int keep)
 {
     const int32_t zero[] = {kWorkNext, kWorkRetry, kRetryN, kOvfSegs, kOvfTotalLo, kOvfTotalHi, kArenaLo,
-                            kArenaHi, kOvfFull, kRetryLost, kStackDropped, kWalkCut};
+                            kArenaHi, kOvfFull, kOvfUsed, kArenaUsed, kRetryLost, kStackDropped, kWalkCut};
     const int n = (int)(sizeof(zero) / sizeof(zero[0])) - (keep ? 3 : 0);
     for (int k = 0; k < n; ++k) scalars[zero[k]] = 0;
     if (c && !keep) {
@@ -1115,9 +1145,16 @@ __global__ __launch_bounds__(256) void k_refine_first(QArgs a)
             pt = a.bt.point[m];
         }
         const int32_t pos = tri[i];
-        if (pos < 0) continue;
-        if (pos >= a.n_tris) {  // cannot come from a walk; never read through it
+        if (pos < 0 || pos >= a.n_tris) {
+            // a miss (a position past the triangles cannot come from a walk
+            // and is never read through)
             st_nt(tri + i, -1);
+            st_nt(tt + i, INFINITY);
+            st_nt(uv + 2 * i, 0.0f);
+            st_nt(uv + 2 * i + 1, 0.0f);
+            st_nt(pt + 3 * i, 0.0f);
+            st_nt(pt + 3 * i + 1, 0.0f);
+            st_nt(pt + 3 * i + 2, 0.0f);
             continue;
         }
         const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
@@ -1424,9 +1461,15 @@ hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
         grow(&h->retry_stack, h->retry_stack_cap, want, sizeof(int32_t));
     }
     if (all_hits) {
+        // lanes that can hold a block of entries or records at once: every
+        // resident lane of the main pass (at most 2,048 per CU) and of the
+        // deep pass (one workgroup of at most 256 per CU); each may leave
+        // its block's unused rest void
+        const int64_t lanes = (n < 2048 * (int64_t)device_cus() ? n : 2048 * (int64_t)device_cus()) +
+                              256 * (int64_t)device_cus();
         // one entry per segment, plus room for the entries that walks handed
-        // to the deep pass leave void
-        const int64_t want = n + n / 8 + 1024;
+        // to the deep pass leave void, plus the void block tails
+        const int64_t want = n + n / 8 + (kEntBlock - 1) * lanes + 1024;
         if (h->ovf_cap < want) {
             // the three arrays share one capacity: it holds only once all grew
             int64_t c0 = 0, c1 = 0, c2 = 0;
@@ -1436,8 +1479,8 @@ hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
             grow(&h->ovf_off, c2, want, sizeof(int64_t));
             if (e == hipSuccess) h->ovf_cap = want;
         }
-        const int64_t arena_want = h->pool_want > (n / 4 > (1 << 20) ? n / 4 : (1 << 20)) ? h->pool_want
-                                   : (n / 4 > (1 << 20) ? n / 4 : (1 << 20));
+        const int64_t arena_want = (h->pool_want > (n / 4 > (1 << 20) ? n / 4 : (1 << 20)) ? h->pool_want
+                                    : (n / 4 > (1 << 20) ? n / 4 : (1 << 20))) + (kArenaBlock - 1) * lanes;
         grow(&h->arena, h->arena_cap, arena_want, sizeof(int4));
     }
     return e;

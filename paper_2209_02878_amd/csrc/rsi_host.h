@@ -16,12 +16,12 @@ namespace rsi {
 enum Scalar {
     kBadIndex = 6,     // nonzero if a triangle index was out of range (1) or the build state was inconsistent (2)
     kBadGather = 7,    // nonzero if a batch gather met a triangle index outside its mesh
-    kOvfSegs = 9,      // all hits: entries taken in the overflow table (segments with more crossings than slots)
+    kOvfSegs = 9,      // all hits: overflow-table entries handed out (in blocks; unused ones are void)
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments: pool entries reserved (lo, hi words)
     kOvfTotalHi = 11,
     kWorkNext = 12,    // next unclaimed work item of the running main query pass
     kWalkCut = 13,     // walks stopped by the node-visit bound (damaged tree)
-    kArenaLo = 14,     // 64-bit count of arena records written during the walk (lo, hi words)
+    kArenaLo = 14,     // 64-bit count of arena records handed out during the walk, in blocks (lo, hi words)
     kArenaHi = 15,
     kSegBounds = 16,   // 6 ordered ints: bounding box of segment midpoints (segment order)
     kRetryN = 22,      // segments whose stack outgrew its LDS part, queued for the deep pass
@@ -29,6 +29,8 @@ enum Scalar {
     kRetryLost = 24,   // retry queue full (cannot happen with a queue of one entry per segment)
     kStackDropped = 25,  // pushes dropped by the deep pass (only a damaged tree is that deep)
     kOvfFull = 26,     // the overflow table, arena or pool was too small: lists incomplete
+    kOvfUsed = 27,     // all hits: overflow-table entries in use (segments with more crossings than slots)
+    kArenaUsed = 28,   // all hits: arena records placed into the pool (crossings past the slots)
     kNumScalars = 32
 };
 
