@@ -249,13 +249,34 @@ def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2, sectio
 
         f = time_events(fwd, 10)
         fb = time_events(fwd_bwd, 10)
-        out["heightfield_199712tri_4Mseg_first_hit_grad"] = {
+        rec = {
             "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
             "backward_ms": round(med(fb) - med(f), 4),
             "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
             "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
             "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
         log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms")
+        # the same training step with the segments put in Morton order once
+        # (a training loop's segments do not change between steps): the
+        # loss is a sum over segments, so its value and dL/dV are those
+        # of the input order
+        oc = time_events(lambda: m.segment_order(S, E), 3)
+        order, So, Eo = m.segment_order(S, E)
+        target_in = target
+        target = target_in[order.long()].contiguous()
+        S_in, E_in = S, E
+        S, E = So, Eo
+        fo = time_events(fwd, 10)
+        fbo = time_events(fwd_bwd, 10)
+        S, E, target = S_in, E_in, target_in
+        rec["morton_ordered_segments"] = {
+            "order_once_ms": round(med(oc), 4), "forward_ms": round(med(fo), 4),
+            "forward_backward_ms": round(med(fbo), 4), "backward_ms": round(med(fbo) - med(fo), 4),
+            "forward_backward_msegments_per_s": round(w.n_r / med(fbo) / 1e3, 2),
+            "fwd_bwd_over_fwd_time": round(med(fbo) / med(fo), 3)}
+        log(f"diff first hit, Morton-ordered segments: fwd {med(fo):.3f} ms, fwd+bwd {med(fbo):.3f} ms "
+            f"(order once {med(oc):.3f} ms)")
+        out["heightfield_199712tri_4Mseg_first_hit_grad"] = rec
         m.close()
         del V, T, S, E, Vp
 
