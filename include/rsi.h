@@ -216,7 +216,7 @@ rsi_status rsi_query_noalloc(rsi_handle h, const float *S, const float *E, int64
  * The vertex gradient is summed without atomic operations in a fixed order
  * (per triangle in FP64, then per vertex), so repeated calls give the same
  * bits.  Memory kept with the handle and released by rsi_destroy (allocated
- * on first use, grown for a larger batch): about 56 bytes per segment
+ * on first use, grown for a larger batch): about 64 bytes per segment
  * (records, sort pairs and the sort's scratch), 72 bytes per triangle and a
  * vertex incidence table of 36 bytes per triangle (rebuilt after
  * rsi_build / rsi_rebuild, kept across rsi_refit).

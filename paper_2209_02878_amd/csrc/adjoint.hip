@@ -67,8 +67,8 @@ struct AdjArgs {
     float *dV;
     float *dS;
     float *dE;
-    float4 *rec;          // per segment: lambda.x, lambda.y, lambda.z, 1 - u - v
-    float2 *rec_v;        // per segment: u, v
+    float4 *rec;          // per segment, 32 bytes (one line to gather): lambda.x, lambda.y,
+                          // lambda.z, 1 - u - v, then u, v and two unused words
     uint64_t *keys;       // per segment: sorted position of the hit triangle, n_t when none
     uint32_t *vals;       // per segment: its index
     double *tri_sum;      // per sorted triangle: 3 corners x 3 axes
@@ -149,8 +149,8 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
         a.dE[3 * i + 1] = (float)ge[1];
         a.dE[3 * i + 2] = (float)ge[2];
     }
-    a.rec[i] = r;
-    a.rec_v[i] = rv;
+    a.rec[2 * i] = r;
+    a.rec[2 * i + 1] = make_float4(rv.x, rv.y, 0.0f, 0.0f);
     a.keys[i] = key;
     a.vals[i] = (uint32_t)i;
 }
@@ -199,12 +199,20 @@ __global__ __launch_bounds__(kThreads) void k_adj_tri(AdjArgs a, const uint64_t 
             dig[r] = sel[r] ? (uint32_t)(key & (kRadix - 1)) : 0u;
             seg[r] = sel[r] ? vals[k] : 0u;
         }
+        // a tile without pairs of this group is skipped (segments in Morton
+        // order put most of a cell's tiles in one or two of its groups)
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < kTriItems; ++r) any = any || sel[r];
+        if (!__syncthreads_or(any)) continue;
         rank::rank_tile<kTriItems>(dig, sel, pos, wcnt, run, start);
 #pragma unroll
         for (int r = 0; r < kTriItems; ++r) {
             if (sel[r]) {
-                srec[pos[r]] = a.rec[seg[r]];
-                srv[pos[r]] = a.rec_v[seg[r]];
+                const float4 *rp = a.rec + 2 * (int64_t)seg[r];
+                srec[pos[r]] = rp[0];
+                const float4 b = rp[1];
+                srv[pos[r]] = make_float2(b.x, b.y);
             }
         }
         __syncthreads();
@@ -317,8 +325,7 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
     }
     if ((e = grow(&h->seg_keys, h->seg_key_cap, n_r)) != hipSuccess) return e;
     if ((e = grow(&h->adj_vals, h->adj_val_cap, n_r)) != hipSuccess) return e;
-    if ((e = grow(&h->adj_rec, h->adj_rec_cap, n_r)) != hipSuccess) return e;
-    if ((e = grow(&h->adj_rec_v, h->adj_rec_v_cap, n_r)) != hipSuccess) return e;
+    if ((e = grow(&h->adj_rec, h->adj_rec_cap, 2 * n_r)) != hipSuccess) return e;
     const int64_t n_groups = (h->n_t + (1 << kGroupBits) - 1) >> kGroupBits;
     const int64_t n_cells = (n_groups + kGroupsPerCell - 1) / kGroupsPerCell;
     if ((e = grow(&h->tri_sum, h->tri_sum_cap, 9 * n_cells * (1 << kCellBits))) != hipSuccess) return e;
@@ -341,7 +348,6 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
         h->inc_valid = true;
     }
     a.rec = h->adj_rec;
-    a.rec_v = h->adj_rec_v;
     a.keys = h->seg_keys;
     a.vals = h->adj_vals;
     a.tri_sum = h->tri_sum;

@@ -47,11 +47,11 @@ void free_handle_memory(rsi_bvh *h)
 {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->adj_rec, h->adj_rec_v, h->tri_sum, h->inc_keys,
+    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->adj_rec, h->tri_sum, h->inc_keys,
                     h->inc_vals, h->compact_counts, h->nodes4, h->aux_E, h->aux_count,
                     h->retry_q, h->retry_stack, h->arena, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys,
                     h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb, h->split_prefix, h->scalars,
-                    h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->pool_ids, h->pool_ts, h->tri_off,
+                    h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->ovf_part, h->pool_ids, h->pool_ts, h->tri_off,
                     h->vert_off, h->mesh_bounds, h->mesh_height, h->mesh_root, h->mesh_entry};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

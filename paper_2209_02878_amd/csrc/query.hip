@@ -86,6 +86,7 @@ struct QArgs {
     int64_t ovf_cap;
     int4 *arena;
     int64_t arena_cap;
+    unsigned long long *ovf_part;  // all hits: per-part count sums of the pool-offset scan
     int32_t *scalars;
     Counters *counters;
     int32_t depth;       // stack entries per lane: the LDS part (main pass) or the height bound (deep pass)
@@ -193,11 +194,14 @@ __device__ inline void load_top(const Node4 *__restrict__ nodes4, int32_t entry,
     top[4 * l + 3] = make_uint4((uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w);
 }
 
-// All hits: overflow-table entries and arena records are handed to lanes in
-// blocks, so the counters see one atomic per block instead of one per entry
-// or crossing (one address serialises them across the whole GPU).
-constexpr int32_t kEntBlock = 4;
-constexpr int32_t kArenaBlock = 8;
+// All hits: overflow-table entries and arena records are handed out in
+// blocks held by a wave (its next and end index in LDS), so the two counters
+// that the whole GPU shares see one atomic per block rather than one per
+// entry or crossing: atomics on one address are serialised device-wide, and
+// at a few thousand per launch they already cost more than the walk's tests.
+constexpr int32_t kEntBlock = 64;
+constexpr int32_t kArenaBlock = 64;
+constexpr int kWavesPerBlock = 4;  // the kernels' launch bound: 256 threads
 
 // Per-lane query state for the segment it currently owns.
 // All-hits capacities up to this many keep the hit list in registers.
@@ -217,12 +221,6 @@ struct Lane {
     const float *ep;
     int32_t mesh;      // batched queries: the segment's mesh
     int32_t hp0, hp1, hp2, hp3;  // all hits, capacity <= 4: the hit positions found so far
-    // all hits: the lane's next overflow-table entry and arena record, taken
-    // from blocks of kEntBlock / kArenaBlock claimed with one atomic each
-    // (a cursor at a multiple of the block size has used its block up);
-    // kept across the lane's segments, unused tails voided when it exits
-    int32_t ent_cur;
-    int32_t arn_cur;
     bool found;
     bool retry;        // the stack outgrew the pass's stack: the deep pass walks this segment again
 };
@@ -232,9 +230,55 @@ __device__ inline int32_t *slot_ids(const QArgs &a, const Lane &L) { return BATC
 template <bool BATCH>
 __device__ inline float *slot_ts(const QArgs &a, const Lane &L) { return BATCH ? a.bt.ts[L.mesh] : a.o.ts; }
 
+// Void slot j of an overflow-table block (KIND 0: a negative count) or of
+// an arena block (KIND 1: a record without entry).
+template <int KIND>
+__device__ inline void void_slot(const QArgs &a, int32_t j)
+{
+    if (KIND == 0) {
+        if (j >= 0 && j < a.ovf_cap) a.ovf_cnt[j] = -1;
+    } else {
+        if (j >= 0 && j < a.arena_cap) a.arena[j] = make_int4(-1, 0, 0, 0);
+    }
+}
+
+// Hand each active lane with `need` one slot of the block its wave holds
+// (KIND 0: overflow-table entries, KIND 1: arena records); returns the slot,
+// or -1 for a lane without `need`.  wst: the wave's (next, end) pairs in LDS,
+// read by every active lane and written by one (LDS operations of a wave
+// execute in order).  When the block cannot serve every requesting lane,
+// the active lanes void its rest and the first claims a new block of
+// kEntBlock / kArenaBlock slots (at least 64: one always suffices).
+template <int KIND>
+__device__ inline int32_t wave_take(const QArgs &a, volatile int32_t *wst, bool need)
+{
+    const uint64_t m = ballot(need);
+    if (m == 0) return -1;
+    const int32_t n = (int32_t)__popcll(m);
+    const uint64_t act = ballot(true);
+    const int leader = __builtin_ctzll(act);
+    int32_t nxt = __builtin_amdgcn_readfirstlane(wst[2 * KIND]);
+    int32_t end = __builtin_amdgcn_readfirstlane(wst[2 * KIND + 1]);
+    if (nxt + n > end) {
+        const int32_t na = (int32_t)__popcll(act);
+        for (int32_t j = nxt + (int32_t)lanes_below(act); j < end; j += na) void_slot<KIND>(a, j);
+        int32_t base = 0;
+        if ((int)__lane_id() == leader)
+            base = atomicAdd(&a.scalars[KIND == 0 ? kOvfSegs : kArenaLo], KIND == 0 ? kEntBlock : kArenaBlock);
+        nxt = __builtin_amdgcn_readfirstlane(__shfl(base, leader, 64));
+        end = nxt + (KIND == 0 ? kEntBlock : kArenaBlock);
+    }
+    if ((int)__lane_id() == leader) {
+        wst[2 * KIND] = nxt + n;
+        wst[2 * KIND + 1] = end;
+    }
+    return need ? nxt + (int32_t)lanes_below(m) : -1;
+}
+
 // Test the triangles of one leaf; returns true when the lane may stop.
+// wst: the wave's block state for all-hits overflow (see wave_take).
 template <uint32_t MODE, bool BATCH, bool COUNT>
-__device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t &tests)
+__device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t &tests, volatile int32_t *wst)
 {
     const int32_t first = leaf_first(ref);
     const int32_t cnt = leaf_count(ref);
@@ -273,13 +317,11 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
                     slot_ids<BATCH>(a, L)[(int64_t)L.seg_i * K + c] = pos;
                 }
             } else {
-                // past the slots: an arena record (entry, rank, position)
-                if (c == K) {
-                    if ((L.ent_cur & (kEntBlock - 1)) == 0) L.ent_cur = atomicAdd(&a.scalars[kOvfSegs], kEntBlock);
-                    L.e = L.ent_cur++;
-                }
-                if ((L.arn_cur & (kArenaBlock - 1)) == 0) L.arn_cur = atomicAdd(&a.scalars[kArenaLo], kArenaBlock);
-                const int32_t r = L.arn_cur++;
+                // past the slots: an arena record (entry, rank, position);
+                // the segment's overflow-table entry is taken at its first
+                const int32_t e = wave_take<0>(a, wst, c == K);
+                if (c == K) L.e = e;
+                const int32_t r = wave_take<1>(a, wst, true);
                 if (L.e < a.ovf_cap && r >= 0 && r < a.arena_cap)
                     a.arena[r] = make_int4(L.e, c, pos, 0);
                 else
@@ -329,60 +371,38 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
         st_nt(cnt_out + i, L.count);
         int32_t *ids = slot_ids<BATCH>(a, L) + i * K;
         float *ts = slot_ts<BATCH>(a, L) + i * K;
-        // A segment with at most K crossings writes only its hits' sorted
-        // positions (kept in registers up to four, else already in the
-        // slots): k_refine_slots, running in segment order, re-solves them,
-        // orders them by (t, id), pads the slots and writes the spill
-        // offset, with stores that fill whole lines.  Stores from here land
-        // wherever the finishing lanes' segments lie, each a partial line.
-        if (L.count >= 1 && L.count <= K) {
-            if (K <= kRegSlots) {
-                const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
-                const bool vec = K == kRegSlots && (reinterpret_cast<uintptr_t>(ids) & 15) == 0;
-                if (vec) {
-                    st_nt4(ids, hp[0], L.count > 1 ? hp[1] : -1, L.count > 2 ? hp[2] : -1, L.count > 3 ? hp[3] : -1);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < kRegSlots; ++c)
-                        if (c < L.count && c < K) ids[c] = hp[c];
-                }
-            }
-        } else if (L.count > K) {
-            // more crossings than slots: reserve the full list's range in the
-            // pool and put the first K there; k_spill_place adds the arena
-            // records, k_spill_finish orders the list and fills the slots
-            int64_t off = -1;
-            if (L.e < a.ovf_cap) {
-                off = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(&a.scalars[kOvfTotalLo]),
-                                         (unsigned long long)L.count);
-                a.ovf_seg[L.e] = L.item;
-                a.ovf_off[L.e] = off;
-                a.ovf_cnt[L.e] = L.count;
-                if (off + L.count <= a.o.pool_cap) {
-                    int32_t *q = a.o.pool_ids + off;
-                    if (K <= kRegSlots) {
-                        const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
-#pragma unroll
-                        for (int k = 0; k < kRegSlots; ++k)
-                            if (k < K) q[k] = hp[k];
-                    } else {
-                        for (int c = 0; c < K; ++c) q[c] = ids[c];
-                    }
-                } else {
-                    atomicOr(&a.scalars[kOvfFull], 1);
-                    off = -1;
-                }
+        // The walk writes only the hits' sorted positions (the first K,
+        // kept in registers up to four, else already in the slots):
+        // k_refine_slots, running in segment order, re-solves them, orders
+        // them by (t, id), pads the slots and writes the spill offset, with
+        // stores that fill whole lines (stores from here land wherever the
+        // finishing lanes' segments lie, each a partial line).  A segment
+        // with more than K crossings also fills in its overflow-table entry;
+        // the pool offsets are taken by a scan after the walk.
+        if (L.count >= 1 && K <= kRegSlots) {
+            const int32_t hp[kRegSlots] = {L.hp0, L.hp1, L.hp2, L.hp3};
+            const bool vec = K == kRegSlots && (reinterpret_cast<uintptr_t>(ids) & 15) == 0;
+            if (vec) {
+                st_nt4(ids, hp[0], L.count > 1 ? hp[1] : -1, L.count > 2 ? hp[2] : -1, L.count > 3 ? hp[3] : -1);
             } else {
-                atomicOr(&a.scalars[kOvfFull], 1);
+#pragma unroll
+                for (int c = 0; c < kRegSlots; ++c)
+                    if (c < L.count && c < K) ids[c] = hp[c];
             }
-            if (off < 0) {
-                // no room for the list: the slots say so (the count stays exact)
+        }
+        if (L.count > K) {
+            if (L.e >= 0 && L.e < a.ovf_cap) {
+                a.ovf_seg[L.e] = L.item;
+                a.ovf_cnt[L.e] = L.count;
+            } else {
+                // no entry (a full table, reported): the slots say so (the count stays exact)
+                atomicOr(&a.scalars[kOvfFull], 1);
                 for (int c = 0; c < K; ++c) {
                     ids[c] = -1;
                     ts[c] = INFINITY;
                 }
+                if (soff) st_nt(soff + i, (int64_t)-1);
             }
-            if (soff) st_nt(soff + i, off);
         }
     }
 }
@@ -392,8 +412,10 @@ __device__ inline void finish(const QArgs &a, const Lane &L)
 // device memory up to a bound on the tree height, so it never outgrows it
 // in a valid tree.  WIDE: walk the four-way view (Node4 records) instead of
 // the binary nodes; leaves and triangles are the same, so are the results.
+// The all-hits variants are held to six waves per SIMD (80 VGPRs): without
+// the bound the compiler gives them 94 and five waves.
 template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH, bool WIDE>
-__global__ __launch_bounds__(256) void k_query(QArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_ALL) ? 6 : 1))) void k_query(QArgs a)
 {
     constexpr bool HYB = RETRY;
     extern __shared__ int32_t lds_stack[];
@@ -413,8 +435,14 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
     Lane L;
     L.retry = false;
     L.e = -1;
-    L.ent_cur = 0;
-    L.arn_cur = 0;
+    // all hits: the wave's blocks of overflow-table entries and arena
+    // records, (next, end) each, none held at first
+    __shared__ int32_t wave_blocks[(MODE & M_ALL) ? 4 * kWavesPerBlock : 1];
+    volatile int32_t *const wst = wave_blocks + ((MODE & M_ALL) ? 4 * (threadIdx.x >> 6) : 0);
+    if ((MODE & M_ALL) && __lane_id() == 0) {
+        wst[0] = wst[1] = 0;
+        wst[2] = wst[3] = 0;
+    }
     // work items number below 2^30 (checked at the boundary), so item and
     // chunk arithmetic is 32-bit; the chunk bounds are wave-uniform
     int32_t item = -1;   // >= 0 owned work item; -1 idle; -2 no work left
@@ -759,7 +787,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 do {
                     const int32_t cur = leaf0 ? leaf0 : (leaf1 ? leaf1 : (leaf2 ? leaf2 : leaf3));
                     if (cur != 0) {
-                        const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, cur, tests);
+                        const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, cur, tests, wst);
                         if (stop) {
                             leaf0 = leaf1 = leaf2 = leaf3 = 0;
                             node = -1;
@@ -776,7 +804,7 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
                 } while (ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
             } else do {
                 if (leaf0 != 0) {
-                    const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, leaf0, tests);
+                    const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, leaf0, tests, wst);
                     leaf0 = stop ? 0 : leaf1;
                     leaf1 = stop ? 0 : leaf2;
                     leaf2 = 0;
@@ -787,12 +815,12 @@ __global__ __launch_bounds__(256) void k_query(QArgs a)
 
     }
     if constexpr ((MODE & M_ALL) != 0) {
-        // void the unused rest of the lane's blocks: k_spill_finish skips an
-        // entry whose count is negative, k_spill_place a record whose entry is
-        for (int32_t e = L.ent_cur; (e & (kEntBlock - 1)) != 0; ++e)
-            if (e >= 0 && e < a.ovf_cap) a.ovf_cnt[e] = -1;
-        for (int32_t r = L.arn_cur; (r & (kArenaBlock - 1)) != 0; ++r)
-            if (r >= 0 && r < a.arena_cap) a.arena[r] = make_int4(-1, 0, 0, 0);
+        // every lane of the wave is here: void the unused rest of the wave's
+        // blocks (the offset scan and k_spill_finish skip an entry whose
+        // count is negative, k_spill_place a record without entry)
+        const int32_t lane = (int32_t)__lane_id();
+        for (int32_t j = wst[0] + lane; j < wst[1]; j += 64) void_slot<0>(a, j);
+        for (int32_t j = wst[2] + lane; j < wst[3]; j += 64) void_slot<1>(a, j);
     }
     if (COUNT) {
         wave_add_u64(&a.counters->node_visits, visits);
@@ -840,8 +868,126 @@ __device__ inline ItemView<BATCH> item_view(const QArgs &a, int64_t it)
     return v;
 }
 
+// All hits, after the walk: pool offsets of the overflowed segments' full
+// lists, the exclusive prefix sums of their counts in table order (a void
+// entry counts 0), so the lists fill the pool contiguously, in exactly the
+// entries they need.  The table [0, n) is cut into kOvfParts contiguous
+// parts (n is read on the device): k_ovf_sums adds up each part's counts,
+// k_ovf_scan_parts scans the part sums in one workgroup, and
+// k_ovf_offsets scans each part again from its base.
+constexpr int kOvfParts = 1024;
+
+__device__ inline int64_t ovf_entries(const QArgs &a)
+{
+    const int32_t ne = a.scalars[kOvfSegs];
+    return ne < a.ovf_cap ? ne : a.ovf_cap;
+}
+
+// Sum over the 256 threads of a workgroup (every thread gets it).
+__device__ inline unsigned long long block_sum256(unsigned long long v, unsigned long long *sh)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (__lane_id() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const unsigned long long t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_ovf_sums(QArgs a)
+{
+    __shared__ unsigned long long sh[4];
+    const int64_t n = ovf_entries(a);
+    const int64_t chunk = (n + kOvfParts - 1) / kOvfParts;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    unsigned long long v = 0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+        const int32_t c = a.ovf_cnt[e];
+        if (c > 0) v += (unsigned long long)c;
+    }
+    v = block_sum256(v, sh);
+    if (threadIdx.x == 0) a.ovf_part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kOvfParts) void k_ovf_scan_parts(QArgs a)
+{
+    __shared__ unsigned long long sh[kOvfParts / 64];
+    const int tid = threadIdx.x;
+    const unsigned long long mine = a.ovf_part[tid];
+    unsigned long long incl = mine;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long u = __shfl_up(incl, off, 64);
+        if ((int)__lane_id() >= off) incl += u;
+    }
+    if (__lane_id() == 63) sh[tid >> 6] = incl;
+    __syncthreads();
+    unsigned long long before = 0;
+    for (int w = 0; w < (tid >> 6); ++w) before += sh[w];
+    a.ovf_part[tid] = before + incl - mine;
+    if (tid == kOvfParts - 1) {
+        const unsigned long long tot = before + incl;
+        a.scalars[kOvfTotalLo] = (int32_t)(uint32_t)tot;
+        a.scalars[kOvfTotalHi] = (int32_t)(uint32_t)(tot >> 32);
+    }
+}
+
+// Per entry: its pool offset; its first min(K, count) positions (in its
+// segment's slots) go to the head of its range, and its spill offset is
+// written.  A list the pool cannot hold is reported (the count stays exact)
+// and its slots say so.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_ovf_offsets(QArgs a)
+{
+    __shared__ unsigned long long sh[4];
+    const int64_t n = ovf_entries(a);
+    const int64_t chunk = (n + kOvfParts - 1) / kOvfParts;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const int K = a.o.cap;
+    unsigned long long base = a.ovf_part[blockIdx.x];
+    for (int64_t t0 = lo; t0 < hi; t0 += 256) {
+        const int64_t e = t0 + threadIdx.x;
+        const int32_t c = e < hi ? a.ovf_cnt[e] : -1;
+        const unsigned long long mine = c > 0 ? (unsigned long long)c : 0ull;
+        // exclusive scan of the tile's counts
+        unsigned long long incl = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long u = __shfl_up(incl, off, 64);
+            if ((int)__lane_id() >= off) incl += u;
+        }
+        if (__lane_id() == 63) sh[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        unsigned long long before = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += sh[w];
+        const unsigned long long tile = sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();
+        if (c > 0) {
+            const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
+            int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, a.ovf_seg[e])] : a.o.spill_off;
+            int32_t *ids = v.ids + v.i * K;
+            const int64_t off = (int64_t)(base + before + incl - mine);
+            if (off + c <= a.o.pool_cap) {
+                a.ovf_off[e] = off;
+                for (int k = 0; k < K; ++k) a.o.pool_ids[off + k] = ids[k];
+                if (soff) soff[v.i] = off;
+            } else {
+                a.ovf_off[e] = -1;
+                atomicOr(&a.scalars[kOvfFull], 1);
+                float *ts = v.ts + v.i * K;
+                for (int k = 0; k < K; ++k) {
+                    ids[k] = -1;
+                    ts[k] = INFINITY;
+                }
+                if (soff) soff[v.i] = -1;
+            }
+        }
+        base += tile;
+    }
+}
+
 // All hits, after the walk: move every arena record (entry e, rank c,
-// sorted position) into slot c of its segment's reserved pool range.
+// sorted position) into slot c of its segment's pool range.
 // Records of a void entry (a walk handed to the deep pass) are skipped.
 __global__ __launch_bounds__(256) void k_spill_place(QArgs a)
 {
@@ -923,72 +1069,162 @@ __global__ __launch_bounds__(256) void k_spill_finish(QArgs a)
     }
 }
 
+// Exclusive prefix over the 256 threads of a workgroup of one count per
+// thread; *total gets the sum.  sh: 4 ints of LDS.  Every thread must call it.
+__device__ inline int32_t block_prefix256(int32_t v, int32_t *sh, int32_t &total)
+{
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    int32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t u = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    int32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += sh[w];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Segment ends of work item k (a segment, or a (mesh, segment) pair).
+template <bool BATCH>
+__device__ inline void item_ends(const QArgs &a, int64_t k, float &sx, float &sy, float &sz, float &ex, float &ey,
+                                 float &ez)
+{
+    const ItemView<BATCH> v = item_view<BATCH>(a, k);
+    sx = ld_nt(v.S + 3 * v.i);
+    sy = ld_nt(v.S + 3 * v.i + 1);
+    sz = ld_nt(v.S + 3 * v.i + 2);
+    ex = ld_nt(v.E + 3 * v.i);
+    ey = ld_nt(v.E + 3 * v.i + 1);
+    ez = ld_nt(v.E + 3 * v.i + 2);
+}
+
 // All hits, after the walk: every segment with 1..K crossings has their
-// sorted positions in its first slots (the rest -1).  Re-solve them in FP64
-// (positions become triangle ids), order by (t, id) and write ids and t.
-// Segments with no crossing were completed by the walk; those with more
-// than K by k_spill_finish.  Kept out of the walk, whose register count
-// (hence waves per SIMD) the FP64 solves would otherwise set.
+// sorted positions in its first slots.  Re-solve them in FP64 (positions
+// become triangle ids), order by (t, id), pad the slots (-1, +inf) and write
+// ids and t; also the padding of segments without crossing and their spill
+// offsets (-1).  Segments with more than K crossings are completed by
+// k_spill_finish.  Kept out of the walk, whose register count (hence waves
+// per SIMD) the FP64 solves would otherwise set.  A workgroup takes tiles
+// of 256 segments in order; for K <= 4 the tile's (segment, slot) pairs are
+// packed so that the FP64 solves run on full waves, their results pass
+// through LDS, and every lane then writes its own segment's slots (the
+// lanes' rows are contiguous, so the stores fill whole lines).
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int K = a.o.cap;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_items; k += stride) {
-        int64_t i = k;
-        const float *S = a.S, *E = a.E;
-        const int32_t *cnt = a.o.count;
-        int32_t *ids = a.o.ids;
-        float *ts = a.o.ts;
-        int64_t *soff = a.o.spill_off;
-        if (BATCH) {
-            const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
-            i = k - a.bt.seg_off[m];
-            S = a.bt.S[m];
-            E = a.bt.E[m];
-            cnt = a.bt.count[m];
-            ids = a.bt.ids[m];
-            ts = a.bt.ts[m];
-            soff = a.bt.spill_off[m];
-        }
-        const int32_t n = cnt[i];
-        if (n > K) continue;  // overflowed: k_spill_finish fills the slots, the walk set the offset
-        if (soff) st_nt(soff + i, (int64_t)-1);
-        ids += i * (int64_t)K;
-        ts += i * (int64_t)K;
-        const bool vec = K == kRegSlots && ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
-        if (n == 0) {
-            // no crossing: padding only (no segment data needed)
-            if (vec) {
-                st_nt4(ids, -1, -1, -1, -1);
-                st_nt4(ts, INFINITY, INFINITY, INFINITY, INFINITY);
-            } else {
-                for (int c = 0; c < K; ++c) {
-                    ids[c] = -1;
-                    ts[c] = INFINITY;
+    const int tid = threadIdx.x;
+    if (K > kRegSlots) {
+        // a segment per lane, its slots in order
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + tid; k < a.n_items; k += stride) {
+            const ItemView<BATCH> v = item_view<BATCH>(a, k);
+            const int32_t *cnt = BATCH ? a.bt.count[mesh_of(a.bt.seg_off, a.M, k)] : a.o.count;
+            int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, k)] : a.o.spill_off;
+            const int32_t n = cnt[v.i];
+            if (n > K) continue;
+            if (soff) st_nt(soff + v.i, (int64_t)-1);
+            int32_t *ids = v.ids + v.i * (int64_t)K;
+            float *ts = v.ts + v.i * (int64_t)K;
+            if (n > 0) {
+                float sx, sy, sz, ex, ey, ez;
+                item_ends<BATCH>(a, k, sx, sy, sz, ex, ey, ez);
+                for (int c = 0; c < n; ++c) {
+                    const int32_t pos = ids[c];
+                    if (pos < 0 || pos >= a.n_tris) {
+                        ids[c] = 0x7FFFFFFF;
+                        ts[c] = INFINITY;
+                        continue;
+                    }
+                    float w[9];
+                    int32_t tid3;
+                    tri_load(a.tris, pos, w, tid3);
+                    double tt, u, ww;
+                    mt_refine64(sx, sy, sz, ex, ey, ez, w, tt, u, ww);
+                    ids[c] = tid3;
+                    ts[c] = (float)tt;
+                }
+                for (int x = 1; x < n; ++x) {  // insertion sort by (t, id): lists are short
+                    const float kt = ts[x];
+                    const int32_t ki = ids[x];
+                    int y = x - 1;
+                    while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                        ts[y + 1] = ts[y];
+                        ids[y + 1] = ids[y];
+                        --y;
+                    }
+                    ts[y + 1] = kt;
+                    ids[y + 1] = ki;
                 }
             }
-            continue;
+            for (int c = n; c < K; ++c) {
+                ids[c] = -1;
+                ts[c] = INFINITY;
+            }
         }
-        const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
-        const float ex = ld_nt(E + 3 * i), ey = ld_nt(E + 3 * i + 1), ez = ld_nt(E + 3 * i + 2);
-        if (K <= kRegSlots) {
+        return;
+    }
+    __shared__ int32_t sh[4];
+    __shared__ int32_t q_pair[256 * kRegSlots];  // (lane << 2) | slot
+    __shared__ int32_t q_pos[256 * kRegSlots];
+    __shared__ int32_t r_id[256 * kRegSlots];
+    __shared__ float r_t[256 * kRegSlots];
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.n_items; base += (int64_t)gridDim.x * 256) {
+        const int64_t k = base + tid;
+        int32_t n = -1;
+        int32_t *ids = nullptr;
+        float *ts = nullptr;
+        if (k < a.n_items) {
+            const ItemView<BATCH> v = item_view<BATCH>(a, k);
+            const int32_t m = BATCH ? mesh_of(a.bt.seg_off, a.M, k) : 0;
+            const int32_t *cnt = BATCH ? a.bt.count[m] : a.o.count;
+            int64_t *soff = BATCH ? a.bt.spill_off[m] : a.o.spill_off;
+            n = cnt[v.i];
+            if (n <= K) {
+                ids = v.ids + v.i * (int64_t)K;
+                ts = v.ts + v.i * (int64_t)K;
+                if (soff) st_nt(soff + v.i, (int64_t)-1);
+            } else {
+                n = -1;  // overflowed: k_spill_finish fills the slots
+            }
+        }
+        // pack the tile's (segment, slot) pairs
+        int32_t total;
+        const int32_t q = block_prefix256(n > 0 ? n : 0, sh, total);
+        for (int c = 0; c < n; ++c) {
+            q_pair[q + c] = (tid << 2) | c;
+            q_pos[q + c] = ids[c];
+        }
+        __syncthreads();
+        for (int j = tid; j < total; j += 256) {
+            const int lt = q_pair[j] >> 2, c = q_pair[j] & 3;
+            const int32_t pos = q_pos[j];
+            int32_t id = 0x7FFFFFFF;
+            float t = INFINITY;
+            if (pos >= 0 && pos < a.n_tris) {  // an entry no walk wrote is never read through
+                float sx, sy, sz, ex, ey, ez;
+                item_ends<BATCH>(a, base + lt, sx, sy, sz, ex, ey, ez);
+                float w[9];
+                tri_load(a.tris, pos, w, id);
+                double tt, u, ww;
+                mt_refine64(sx, sy, sz, ex, ey, ez, w, tt, u, ww);
+                t = (float)tt;
+            }
+            r_id[lt * kRegSlots + c] = id;
+            r_t[lt * kRegSlots + c] = t;
+        }
+        __syncthreads();
+        if (n >= 0) {
             int32_t id[kRegSlots];
             float t[kRegSlots];
 #pragma unroll
             for (int c = 0; c < kRegSlots; ++c) {
-                id[c] = 0x7FFFFFFF;
-                t[c] = INFINITY;
-                const int32_t pos = c < n ? ids[c] : -1;
-                if (pos >= 0 && pos < a.n_tris) {
-                    float v[9];
-                    int32_t tid;
-                    tri_load(a.tris, pos, v, tid);
-                    double tt, u, w;
-                    mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
-                    id[c] = tid;
-                    t[c] = (float)tt;
-                }
+                id[c] = c < n ? r_id[tid * kRegSlots + c] : 0x7FFFFFFF;
+                t[c] = c < n ? r_t[tid * kRegSlots + c] : INFINITY;
             }
             // five-comparator network (unused entries sort last)
             auto cs = [&](int x, int y) {
@@ -1009,48 +1245,19 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
 #pragma unroll
             for (int c = 0; c < kRegSlots; ++c)
                 if (c >= n) id[c] = -1;
+            const bool vec = K == kRegSlots &&
+                             ((reinterpret_cast<uintptr_t>(ids) | reinterpret_cast<uintptr_t>(ts)) & 15) == 0;
             if (vec) {
                 st_nt4(ids, id[0], id[1], id[2], id[3]);
                 st_nt4(ts, t[0], t[1], t[2], t[3]);
             } else {
                 for (int c = 0; c < K; ++c) {
-                    ids[c] = id[c];
-                    ts[c] = t[c];
+                    st_nt(ids + c, id[c]);
+                    st_nt(ts + c, t[c]);
                 }
-            }
-        } else {
-            for (int c = 0; c < n; ++c) {
-                const int32_t pos = ids[c];
-                if (pos < 0 || pos >= a.n_tris) {
-                    ids[c] = 0x7FFFFFFF;
-                    ts[c] = INFINITY;
-                    continue;
-                }
-                float v[9];
-                int32_t tid;
-                tri_load(a.tris, pos, v, tid);
-                double tt, u, w;
-                mt_refine64(sx, sy, sz, ex, ey, ez, v, tt, u, w);
-                ids[c] = tid;
-                ts[c] = (float)tt;
-            }
-            for (int x = 1; x < n; ++x) {  // insertion sort by (t, id): lists are short
-                const float kt = ts[x];
-                const int32_t ki = ids[x];
-                int y = x - 1;
-                while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
-                    ts[y + 1] = ts[y];
-                    ids[y + 1] = ids[y];
-                    --y;
-                }
-                ts[y + 1] = kt;
-                ids[y + 1] = ki;
-            }
-            for (int c = n; c < K; ++c) {
-                ids[c] = -1;
-                ts[c] = INFINITY;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -1120,57 +1327,78 @@ __global__ void k_reset(int32_t *scalars, Counters *c, int keep)
     }
 }
 
-// FP64 re-solve of every first hit, after a walk without all hits: the walk
-// leaves the sorted position of the hit triangle in tri (misses are
-// complete), and this pass writes the triangle's id, t, (u, v) and the
-// point.  Kept out of the walk, whose registers (hence waves per SIMD) it
-// would otherwise raise for the whole traversal.
+// FP64 re-solve of every first hit, after the walk: the walk leaves the
+// sorted position of the hit triangle in tri, or -1 for a miss, and this
+// pass writes the triangle's id, t, (u, v) and the point, or the miss values.
+// Kept out of the walk, whose registers (hence waves per SIMD) it would
+// otherwise raise for the whole traversal.  A workgroup takes tiles of 256
+// segments in order; the tile's hits are packed so that the FP64 solves run
+// on full waves, their results pass through LDS, and every lane then writes
+// its own segment's outputs (consecutive lanes, consecutive segments: the
+// stores fill whole lines).
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_refine_first(QArgs a)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < a.n_items; k += stride) {
+    __shared__ int32_t sh[4];
+    __shared__ int32_t q_lane[256];
+    __shared__ int32_t q_pos[256];
+    __shared__ int32_t r_id[256];
+    __shared__ float r_f[6 * 256];  // t, u, v, Px, Py, Pz
+    const int tid = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.n_items; base += (int64_t)gridDim.x * 256) {
+        const int64_t k = base + tid;
         int64_t i = k;
-        const float *S = a.S, *E = a.E;
         int32_t *tri = a.o.tri;
         float *tt = a.o.t, *uv = a.o.uv, *pt = a.o.point;
-        if (BATCH) {
-            const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
-            i = k - a.bt.seg_off[m];
-            S = a.bt.S[m];
-            E = a.bt.E[m];
-            tri = a.bt.tri[m];
-            tt = a.bt.t[m];
-            uv = a.bt.uv[m];
-            pt = a.bt.point[m];
+        int32_t pos = -1;
+        if (k < a.n_items) {
+            if (BATCH) {
+                const int32_t m = mesh_of(a.bt.seg_off, a.M, k);
+                i = k - a.bt.seg_off[m];
+                tri = a.bt.tri[m];
+                tt = a.bt.t[m];
+                uv = a.bt.uv[m];
+                pt = a.bt.point[m];
+            }
+            pos = tri[i];
         }
-        const int32_t pos = tri[i];
-        if (pos < 0 || pos >= a.n_tris) {
-            // a miss (a position past the triangles cannot come from a walk
-            // and is never read through)
-            st_nt(tri + i, -1);
-            st_nt(tt + i, INFINITY);
-            st_nt(uv + 2 * i, 0.0f);
-            st_nt(uv + 2 * i + 1, 0.0f);
-            st_nt(pt + 3 * i, 0.0f);
-            st_nt(pt + 3 * i + 1, 0.0f);
-            st_nt(pt + 3 * i + 2, 0.0f);
-            continue;
+        // a position past the triangles cannot come from a walk and is never read through
+        const bool hit = pos >= 0 && pos < a.n_tris;
+        int32_t nq;
+        const int32_t q = block_prefix256(hit ? 1 : 0, sh, nq);
+        if (hit) {
+            q_lane[q] = tid;
+            q_pos[q] = pos;
         }
-        const float sx = ld_nt(S + 3 * i), sy = ld_nt(S + 3 * i + 1), sz = ld_nt(S + 3 * i + 2);
-        const float ex = ld_nt(E + 3 * i), ey = ld_nt(E + 3 * i + 1), ez = ld_nt(E + 3 * i + 2);
-        float v[9];
-        int32_t id;
-        tri_load(a.tris, pos, v, id);
-        double t, u, w;
-        mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
-        st_nt(tri + i, id);
-        st_nt(tt + i, (float)t);
-        st_nt(uv + 2 * i, (float)u);
-        st_nt(uv + 2 * i + 1, (float)w);
-        st_nt(pt + 3 * i, (float)((double)sx + t * ((double)ex - (double)sx)));
-        st_nt(pt + 3 * i + 1, (float)((double)sy + t * ((double)ey - (double)sy)));
-        st_nt(pt + 3 * i + 2, (float)((double)sz + t * ((double)ez - (double)sz)));
+        __syncthreads();
+        if (tid < nq) {
+            const int lt = q_lane[tid];
+            float sx, sy, sz, ex, ey, ez;
+            item_ends<BATCH>(a, base + lt, sx, sy, sz, ex, ey, ez);
+            float v[9];
+            int32_t id;
+            tri_load(a.tris, q_pos[tid], v, id);
+            double t, u, w;
+            mt_refine64(sx, sy, sz, ex, ey, ez, v, t, u, w);
+            r_id[lt] = id;
+            r_f[lt] = (float)t;
+            r_f[256 + lt] = (float)u;
+            r_f[512 + lt] = (float)w;
+            r_f[768 + lt] = (float)((double)sx + t * ((double)ex - (double)sx));
+            r_f[1024 + lt] = (float)((double)sy + t * ((double)ey - (double)sy));
+            r_f[1280 + lt] = (float)((double)sz + t * ((double)ez - (double)sz));
+        }
+        __syncthreads();
+        if (k < a.n_items) {
+            st_nt(tri + i, hit ? r_id[tid] : -1);
+            st_nt(tt + i, hit ? r_f[tid] : INFINITY);
+            st_nt(uv + 2 * i, hit ? r_f[256 + tid] : 0.0f);
+            st_nt(uv + 2 * i + 1, hit ? r_f[512 + tid] : 0.0f);
+            st_nt(pt + 3 * i, hit ? r_f[768 + tid] : 0.0f);
+            st_nt(pt + 3 * i + 1, hit ? r_f[1024 + tid] : 0.0f);
+            st_nt(pt + 3 * i + 2, hit ? r_f[1280 + tid] : 0.0f);
+        }
+        __syncthreads();
     }
 }
 
@@ -1312,6 +1540,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.ovf_cap = h->ovf_cap;
     a.arena = h->arena;
     a.arena_cap = h->arena_cap;
+    a.ovf_part = h->ovf_part;
     a.scalars = h->scalars;
     a.counters = h->counters;
     a.depth = 0;
@@ -1348,6 +1577,10 @@ hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
     const unsigned rgrid = (unsigned)(blocks < 8192 ? blocks : 8192);
     if (batch) hipLaunchKernelGGL(k_refine_slots<true>, dim3(rgrid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_refine_slots<false>, dim3(rgrid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ovf_sums, dim3(kOvfParts), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ovf_scan_parts, dim3(1), dim3(kOvfParts), 0, s, a);
+    if (batch) hipLaunchKernelGGL(k_ovf_offsets<true>, dim3(kOvfParts), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_ovf_offsets<false>, dim3(kOvfParts), dim3(256), 0, s, a);
     const unsigned grid = (unsigned)(2 * device_cus());
     hipLaunchKernelGGL(k_spill_place, dim3(grid), dim3(256), 0, s, a);
     if (batch) hipLaunchKernelGGL(k_spill_finish<true>, dim3(grid), dim3(256), 0, s, a);
@@ -1461,15 +1694,16 @@ hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
         grow(&h->retry_stack, h->retry_stack_cap, want, sizeof(int32_t));
     }
     if (all_hits) {
-        // lanes that can hold a block of entries or records at once: every
-        // resident lane of the main pass (at most 2,048 per CU) and of the
-        // deep pass (one workgroup of at most 256 per CU); each may leave
-        // its block's unused rest void
-        const int64_t lanes = (n < 2048 * (int64_t)device_cus() ? n : 2048 * (int64_t)device_cus()) +
-                              256 * (int64_t)device_cus();
+        // waves that can hold a block of entries and one of records at
+        // once: every resident wave of the main pass (at most 32 per CU,
+        // and no more than the segments fill) and of the deep pass (one
+        // workgroup of at most 4 waves per CU); each may leave its blocks'
+        // unused rest void
+        const int64_t cus = device_cus();
+        const int64_t waves = ((n + 63) / 64 < 32 * cus ? (n + 63) / 64 : 32 * cus) + 4 * cus;
         // one entry per segment, plus room for the entries that walks handed
         // to the deep pass leave void, plus the void block tails
-        const int64_t want = n + n / 8 + (kEntBlock - 1) * lanes + 1024;
+        const int64_t want = n + n / 8 + (int64_t)(kEntBlock - 1) * waves + 1024;
         if (h->ovf_cap < want) {
             // the three arrays share one capacity: it holds only once all grew
             int64_t c0 = 0, c1 = 0, c2 = 0;
@@ -1480,8 +1714,9 @@ hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
             if (e == hipSuccess) h->ovf_cap = want;
         }
         const int64_t arena_want = (h->pool_want > (n / 4 > (1 << 20) ? n / 4 : (1 << 20)) ? h->pool_want
-                                    : (n / 4 > (1 << 20) ? n / 4 : (1 << 20))) + (kArenaBlock - 1) * lanes;
+                                    : (n / 4 > (1 << 20) ? n / 4 : (1 << 20))) + (int64_t)(kArenaBlock - 1) * waves;
         grow(&h->arena, h->arena_cap, arena_want, sizeof(int4));
+        grow(&h->ovf_part, h->ovf_part_cap, kOvfParts, sizeof(unsigned long long));
     }
     return e;
 }

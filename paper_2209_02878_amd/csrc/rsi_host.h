@@ -121,6 +121,8 @@ struct rsi_bvh {
     int64_t ovf_cap = 0;
     int4 *arena = nullptr;
     int64_t arena_cap = 0;
+    unsigned long long *ovf_part = nullptr;  // part sums of the pool-offset scan
+    int64_t ovf_part_cap = 0;
     int32_t *pool_ids = nullptr;
     float *pool_ts = nullptr;
     int64_t pool_cap = 0;
@@ -163,8 +165,6 @@ struct rsi_bvh {
     // the vertex incidence table of the current topology
     float4 *adj_rec = nullptr;
     int64_t adj_rec_cap = 0;
-    float2 *adj_rec_v = nullptr;
-    int64_t adj_rec_v_cap = 0;
     double *tri_sum = nullptr;
     int64_t tri_sum_cap = 0;
     uint64_t *inc_keys = nullptr;
