@@ -22,11 +22,13 @@
 //   (sort.hip)    one stable pass per 8 bits of the cell index (position >>
 //                 10): the pairs of each cell of 1,024 consecutive
 //                 triangles become contiguous, in input order within a cell
-//   k_adj_tri     one workgroup per 256 triangles of a cell: it walks its
-//                 cell's pairs in tiles, ranks the tile's own pairs stably by
-//                 triangle in LDS, and thread t adds the records of triangle
-//                 t in that order, in FP64, to nine running sums (three
-//                 corners x three axes), stored per triangle at the end
+//   k_adj_tri     four workgroups per cell, each taking a quarter of the
+//                 cell's pairs in order: tiles of 1,024 pairs are ranked
+//                 stably by (cell triangle mod 256) in LDS, and thread t adds
+//                 the records of its four triangles (t + 256 j) in that order,
+//                 in FP64, to nine running sums per triangle (three corners x
+//                 three axes); each quarter's sums are stored
+//   k_adj_combine one lane per triangle: the four quarters' sums, in order
 //   k_adj_vertex  one lane per vertex: the sums of the (triangle, corner)
 //                 pairs incident to it (a table sorted by vertex, built once
 //                 per topology), added to dV
@@ -46,8 +48,9 @@ using rank::kWaves;
 using rank::kRadix;
 
 constexpr int kCellBits = 10;                    // triangles per cell: 1,024
-constexpr int kGroupBits = 8;                    // triangles per k_adj_tri workgroup: 256
-constexpr int kGroupsPerCell = 1 << (kCellBits - kGroupBits);
+constexpr int kCellTris = 1 << kCellBits;
+constexpr int kTriPerThread = kCellTris / kThreads;  // 4: thread t owns cell triangles t + 256 j
+constexpr int kChunks = 4;                       // k_adj_tri workgroups per cell (each a quarter of its pairs)
 constexpr int kTriItems = 4;                     // pairs per thread per tile of k_adj_tri
 constexpr int kTriTile = kThreads * kTriItems;
 
@@ -67,11 +70,12 @@ struct AdjArgs {
     float *dV;
     float *dS;
     float *dE;
-    float4 *rec;          // per segment, 32 bytes (one line to gather): lambda.x, lambda.y,
-                          // lambda.z, 1 - u - v, then u, v and two unused words
+    float4 *rec;          // per segment: lambda.x, lambda.y, lambda.z, 1 - u - v
+    float2 *rec_v;        // per segment: u, v
     uint64_t *keys;       // per segment: sorted position of the hit triangle, n_t when none
     uint32_t *vals;       // per segment: its index
     double *tri_sum;      // per sorted triangle: 3 corners x 3 axes
+    double *part;         // per (cell, chunk, cell triangle): the chunk's 9 sums
 };
 
 struct d3 {
@@ -149,94 +153,130 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
         a.dE[3 * i + 1] = (float)ge[1];
         a.dE[3 * i + 2] = (float)ge[2];
     }
-    a.rec[2 * i] = r;
-    a.rec[2 * i + 1] = make_float4(rv.x, rv.y, 0.0f, 0.0f);
+    a.rec[i] = r;
+    a.rec_v[i] = rv;
     a.keys[i] = key;
     a.vals[i] = (uint32_t)i;
 }
 
-// First index k in [lo, hi) with (keys[k] >> shift) >= x (keys ordered by that field).
-__device__ inline int64_t lower_bound_field(const uint64_t *keys, int64_t lo, int64_t hi, uint64_t x, int shift)
+// Bucket starts of keys ordered by the field (key >> shift): for b in
+// [0, nb], first[b] = the first index whose field is >= b (n if none).  One
+// thread per key writes the starts of the buckets between its predecessor's
+// field and its own, so a single coalesced pass fills every entry, empty
+// buckets included.
+__global__ __launch_bounds__(256) void k_bucket_starts(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                       int64_t nb, int64_t *__restrict__ first)
 {
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((keys[mid] >> shift) < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n) return;
+    // k is the first index of every bucket b with field(k - 1) < b <= field(k)
+    // (field(-1) = -1, field(n) = nb + 1)
+    const int64_t cur = k < n ? (int64_t)(keys[k] >> shift) : nb + 1;
+    const int64_t prev = k > 0 ? (int64_t)(keys[k - 1] >> shift) : -1;
+    for (int64_t b = prev + 1; b <= cur && b <= nb; ++b) first[b] = k;
 }
 
-// One workgroup per 256 consecutive sorted triangles (quarter q of cell g).
-// keys/vals: the pairs ordered by cell (stable, so input order within a cell).
+// One workgroup per (cell g, chunk c): the c-th quarter of the cell's pairs
+// (in order).  keys/vals: the pairs ordered by cell (stable, so input order
+// within a cell).  Thread t owns the cell's triangles t + 256 j (j < 4); the
+// tile's pairs are ranked stably by (cell triangle mod 256), so thread t
+// meets the records of its four triangles in tile order and adds each to
+// its triangle's nine FP64 sums.  Every pair is ranked once; the chunk's
+// sums of all 1,024 triangles go to `part`, which k_adj_combine adds up in
+// chunk order.
 __global__ __launch_bounds__(kThreads) void k_adj_tri(AdjArgs a, const uint64_t *__restrict__ keys,
-                                                      const uint32_t *__restrict__ vals, int64_t n)
+                                                      const uint32_t *__restrict__ vals,
+                                                      const int64_t *__restrict__ cell_first)
 {
     __shared__ uint32_t wcnt[kTriItems * kWaves * kRadix];
     __shared__ uint32_t run[kRadix], start[kRadix];
     __shared__ float4 srec[kTriTile];
     __shared__ float2 srv[kTriTile];
+    __shared__ uint8_t sj[kTriTile];
     __shared__ int64_t range[2];
     const int tid = threadIdx.x;
-    const int64_t g = blockIdx.x / kGroupsPerCell;
-    const int32_t group = (int32_t)blockIdx.x;  // == (position >> kGroupBits) of its triangles
+    const int64_t g = blockIdx.x / kChunks;
+    const int chunk = (int)(blockIdx.x % kChunks);
     if (tid == 0) {
-        range[0] = lower_bound_field(keys, 0, n, (uint64_t)g, kCellBits);
-        range[1] = lower_bound_field(keys, range[0], n, (uint64_t)g + 1, kCellBits);
+        const int64_t clo = cell_first[g];
+        const int64_t chi = cell_first[g + 1];
+        const int64_t len = chi - clo;
+        range[0] = clo + len * chunk / kChunks;
+        range[1] = clo + len * (chunk + 1) / kChunks;
     }
     __syncthreads();
     const int64_t lo = range[0], hi = range[1];
-    double acc[9];
+    double acc[kTriPerThread][9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    for (int j = 0; j < kTriPerThread; ++j)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) acc[j][q] = 0.0;
     for (int64_t c0 = lo; c0 < hi; c0 += kTriTile) {
-        uint32_t dig[kTriItems], pos[kTriItems], seg[kTriItems];
+        uint32_t dig[kTriItems], pos[kTriItems], seg[kTriItems], jj[kTriItems];
         bool sel[kTriItems];
 #pragma unroll
         for (int r = 0; r < kTriItems; ++r) {
             const int64_t k = c0 + r * kThreads + tid;
             const uint64_t key = k < hi ? keys[k] : ~0ull;
-            sel[r] = k < hi && key < (uint64_t)a.n_t && (int32_t)(key >> kGroupBits) == group;
-            dig[r] = sel[r] ? (uint32_t)(key & (kRadix - 1)) : 0u;
+            sel[r] = k < hi && key < (uint64_t)a.n_t;  // misses sort last (key n_t), past every cell
+            const uint32_t local = (uint32_t)(key & (kCellTris - 1));
+            dig[r] = sel[r] ? (local & (kRadix - 1)) : 0u;
+            jj[r] = local >> 8;
             seg[r] = sel[r] ? vals[k] : 0u;
         }
-        // a tile without pairs of this group is skipped (segments in Morton
-        // order put most of a cell's tiles in one or two of its groups)
-        bool any = false;
-#pragma unroll
-        for (int r = 0; r < kTriItems; ++r) any = any || sel[r];
-        if (!__syncthreads_or(any)) continue;
         rank::rank_tile<kTriItems>(dig, sel, pos, wcnt, run, start);
 #pragma unroll
         for (int r = 0; r < kTriItems; ++r) {
             if (sel[r]) {
-                const float4 *rp = a.rec + 2 * (int64_t)seg[r];
-                srec[pos[r]] = rp[0];
-                const float4 b = rp[1];
-                srv[pos[r]] = make_float2(b.x, b.y);
+                srec[pos[r]] = a.rec[seg[r]];
+                srv[pos[r]] = a.rec_v[seg[r]];
+                sj[pos[r]] = (uint8_t)jj[r];
             }
         }
         __syncthreads();
-        // triangle tid: its records of this tile, in input order
+        // the records of this thread's four triangles, in tile order: one
+        // sweep of the run per triangle, adding the records that belong to it
         const uint32_t b = start[tid], e = b + run[tid];
-        for (uint32_t p = b; p < e; ++p) {
-            const float4 rr = srec[p];
-            const float2 uv = srv[p];
-            const double w[3] = {-(double)rr.w, -(double)uv.x, -(double)uv.y};
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                acc[3 * c] += w[c] * (double)rr.x;
-                acc[3 * c + 1] += w[c] * (double)rr.y;
-                acc[3 * c + 2] += w[c] * (double)rr.z;
+        for (int jt = 0; jt < kTriPerThread; ++jt) {
+            for (uint32_t p = b; p < e; ++p) {
+                if (sj[p] != jt) continue;
+                const float4 rr = srec[p];
+                const float2 uv = srv[p];
+                const double w[3] = {-(double)rr.w, -(double)uv.x, -(double)uv.y};
+                const double l[3] = {(double)rr.x, (double)rr.y, (double)rr.z};
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc[jt][3 * c + d] += w[c] * l[d];
             }
         }
         __syncthreads();
     }
-    const int64_t t = (int64_t)group * kRadix + tid;
-    if (t < a.n_t) {
-        double *o = a.tri_sum + 9 * t;
+    double *o = a.part + ((g * kChunks + chunk) * kCellTris) * 9;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) o[q] = acc[q];
+    for (int j = 0; j < kTriPerThread; ++j)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) o[(j * kThreads + tid) * 9 + q] = acc[j][q];
+}
+
+// Per sorted triangle: its chunks' sums, added in chunk order.
+__global__ __launch_bounds__(256) void k_adj_combine(AdjArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_t) return;
+    const int64_t g = t >> kCellBits, local = t & (kCellTris - 1);
+    double s[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = 0.0;
+    for (int c = 0; c < kChunks; ++c) {
+        const double *p = a.part + ((g * kChunks + c) * kCellTris + local) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s[q] += p[q];
     }
+    double *o = a.tri_sum + 9 * t;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o[q] = s[q];
 }
 
 // Incidence table of a topology: pairs (vertex, 3 * sorted position + corner).
@@ -255,11 +295,12 @@ __global__ __launch_bounds__(256) void k_adj_incidence(const int32_t *__restrict
 
 // One lane per vertex: its incident (triangle, corner) sums, in table order.
 __global__ __launch_bounds__(256) void k_adj_vertex(AdjArgs a, const uint64_t *__restrict__ inc_keys,
-                                                    const uint32_t *__restrict__ inc_vals, int64_t n_inc)
+                                                    const uint32_t *__restrict__ inc_vals, int64_t n_inc,
+                                                    const int64_t *__restrict__ inc_first)
 {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.n_v) return;
-    const int64_t b = lower_bound_field(inc_keys, 0, n_inc, (uint64_t)v, 0);
+    const int64_t b = inc_first[v];
     double x = 0.0, y = 0.0, z = 0.0;
     for (int64_t k = b; k < n_inc && inc_keys[k] == (uint64_t)v; ++k) {
         const uint32_t tc = inc_vals[k];
@@ -325,10 +366,11 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
     }
     if ((e = grow(&h->seg_keys, h->seg_key_cap, n_r)) != hipSuccess) return e;
     if ((e = grow(&h->adj_vals, h->adj_val_cap, n_r)) != hipSuccess) return e;
-    if ((e = grow(&h->adj_rec, h->adj_rec_cap, 2 * n_r)) != hipSuccess) return e;
-    const int64_t n_groups = (h->n_t + (1 << kGroupBits) - 1) >> kGroupBits;
-    const int64_t n_cells = (n_groups + kGroupsPerCell - 1) / kGroupsPerCell;
-    if ((e = grow(&h->tri_sum, h->tri_sum_cap, 9 * n_cells * (1 << kCellBits))) != hipSuccess) return e;
+    if ((e = grow(&h->adj_rec, h->adj_rec_cap, n_r)) != hipSuccess) return e;
+    if ((e = grow(&h->adj_rec_v, h->adj_rec_v_cap, n_r)) != hipSuccess) return e;
+    const int64_t n_cells = (h->n_t + kCellTris - 1) >> kCellBits;
+    if ((e = grow(&h->tri_sum, h->tri_sum_cap, 9 * h->n_t)) != hipSuccess) return e;
+    if ((e = grow(&h->adj_part, h->adj_part_cap, 9 * n_cells * kChunks * kCellTris)) != hipSuccess) return e;
     // incidence table of the current topology (kept until a build changes it)
     if (!h->inc_valid) {
         const int64_t n_inc = 3 * h->n_t;
@@ -345,12 +387,19 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
         if ((e = hipGetLastError()) != hipSuccess) return e;
         e = radix_sort_pairs(h->inc_keys, h->inc_vals, n_inc, bits_for(h->n_v), h->seg_sort, s);
         if (e != hipSuccess) return e;
+        // first table entry of every vertex (CSR starts; an invalid index sorts last, at n_v)
+        if ((e = grow(&h->inc_first, h->inc_first_cap, h->n_v + 2)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bucket_starts, dim3((unsigned)((n_inc + 1 + 255) / 256)), dim3(256), 0, s, h->inc_keys,
+                           n_inc, 0, h->n_v, h->inc_first);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         h->inc_valid = true;
     }
     a.rec = h->adj_rec;
+    a.rec_v = h->adj_rec_v;
     a.keys = h->seg_keys;
     a.vals = h->adj_vals;
     a.tri_sum = h->tri_sum;
+    a.part = h->adj_part;
     const unsigned grid = (unsigned)((n_r + 255) / 256);
     hipLaunchKernelGGL(k_adj_solve, dim3(grid), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -360,11 +409,19 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
     e = radix_sort_pairs(h->seg_keys, h->adj_vals, n_r, bits_for(h->n_t), h->seg_sort, s, nullptr, 1, kCellBits, &ks,
                          &vs);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_tri, dim3((unsigned)(n_cells * kGroupsPerCell)), dim3(kThreads), 0, s, a, ks, vs, n_r);
+    // pairs of cell g: [cell_first[g], cell_first[g + 1]); misses (key n_t) sort last
+    if ((e = grow(&h->adj_cell_first, h->adj_cell_first_cap, n_cells + 2)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_starts, dim3((unsigned)((n_r + 1 + 255) / 256)), dim3(256), 0, s, ks, n_r, kCellBits,
+                       n_cells, h->adj_cell_first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_tri, dim3((unsigned)(n_cells * kChunks)), dim3(kThreads), 0, s, a, ks, vs,
+                       h->adj_cell_first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_combine, dim3((unsigned)((h->n_t + 255) / 256)), dim3(256), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dV) {
         hipLaunchKernelGGL(k_adj_vertex, dim3((unsigned)((h->n_v + 255) / 256)), dim3(256), 0, s, a, h->inc_keys,
-                           h->inc_vals, 3 * h->n_t);
+                           h->inc_vals, 3 * h->n_t, h->inc_first);
         e = hipGetLastError();
     }
     return e;

@@ -47,7 +47,7 @@ void free_handle_memory(rsi_bvh *h)
 {
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->adj_rec, h->tri_sum, h->inc_keys,
+    void *ptrs[] = {h->rank, h->adj_vals, h->seg_keys, h->adj_rec, h->adj_rec_v, h->tri_sum, h->adj_part, h->adj_cell_first, h->inc_first, h->inc_keys,
                     h->inc_vals, h->compact_counts, h->nodes4, h->aux_E, h->aux_count,
                     h->retry_q, h->retry_stack, h->arena, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys,
                     h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb, h->split_prefix, h->scalars,

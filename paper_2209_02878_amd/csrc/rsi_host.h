@@ -165,8 +165,16 @@ struct rsi_bvh {
     // the vertex incidence table of the current topology
     float4 *adj_rec = nullptr;
     int64_t adj_rec_cap = 0;
+    float2 *adj_rec_v = nullptr;
+    int64_t adj_rec_v_cap = 0;
     double *tri_sum = nullptr;
     int64_t tri_sum_cap = 0;
+    double *adj_part = nullptr;  // per (cell, chunk, cell triangle): partial sums
+    int64_t adj_part_cap = 0;
+    int64_t *adj_cell_first = nullptr;  // first sorted pair of every cell
+    int64_t adj_cell_first_cap = 0;
+    int64_t *inc_first = nullptr;       // first incidence-table entry of every vertex
+    int64_t inc_first_cap = 0;
     uint64_t *inc_keys = nullptr;
     uint32_t *inc_vals = nullptr;
     int64_t inc_cap = 0;

@@ -315,6 +315,45 @@ __device__ inline void sort_bucket_lds(const uint64_t *__restrict__ kin, const u
         }
 }
 
+// A small bucket (at most 2 * kThreads keys, all with the same top digit):
+// every key's place is the number of keys below it, equal keys counted by
+// their index, i.e. the place of a stable sort by the whole key, which is
+// what the low passes compute; the keys are read from LDS by all threads at
+// the same index (broadcast).  About bn compares per thread instead of
+// nlow stable ranking rounds.
+__device__ inline void sort_bucket_count(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                         uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint32_t b0,
+                                         uint32_t bn, uint64_t *skey)
+{
+    const int tid = threadIdx.x;
+    uint64_t key[2];
+    uint32_t val[2], below[2] = {0u, 0u};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t i = (uint32_t)(r * kThreads + tid);
+        key[r] = i < bn ? kin[b0 + i] : ~0ull;
+        val[r] = i < bn ? vin[b0 + i] : 0u;
+        if (i < bn) skey[i] = key[r];
+    }
+    __syncthreads();
+    for (uint32_t j = 0; j < bn; ++j) {
+        const uint64_t kj = skey[j];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t i = (uint32_t)(r * kThreads + tid);
+            below[r] += (kj < key[r] || (kj == key[r] && j < i)) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t i = (uint32_t)(r * kThreads + tid);
+        if (i < bn) {
+            kout[b0 + below[r]] = key[r];
+            vout[b0 + below[r]] = val[r];
+        }
+    }
+}
+
 // A larger bucket: the same stable low passes over its range in device
 // memory, one histogram sweep and one tile-by-tile scatter sweep per pass,
 // alternating between the range in kin and in kout (the result ends in kout).
@@ -412,8 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(uint64_t *__restrict__
         __syncthreads();
     }
     if (bn == 0) return;
-    if (bn <= (uint32_t)kThreads)
-        sort_bucket_lds<1>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
+    if (bn <= 2u * kThreads)
+        sort_bucket_count(kin, vin, kout, vout, b0, bn, skey);
     else if (bn <= (uint32_t)kTile)
         sort_bucket_lds<kItems>(kin, vin, kout, vout, b0, bn, nlow, wcnt, run, start, skey, sval);
     else if (bn <= (uint32_t)kBucketLds)

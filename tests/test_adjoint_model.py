@@ -4,21 +4,23 @@ and checked against the FP64 oracle's gradient.
 
 The device kernels (adjoint.hip) solve every segment in input order, group
 the (hit triangle's Morton position, segment) pairs by cells of 1,024
-positions with a stable pass, let each 256-position group walk its cell's
-pairs tile by tile (1,024 pairs), rank the tile's own pairs stably by
-position, sum each triangle's records in that order in FP64, and finally sum
-the (triangle, corner) terms of each vertex from a table sorted by vertex.
-No atomic operation is involved, so the only ways to lose a contribution
-would be a wrong grouping or a wrong range; this model walks exactly those
-ranges (including cells that span several tiles, empty cells, misses and
-groups past the last triangle) and must reproduce the oracle's gradient.
+positions with a stable pass, cut each cell's pairs into four consecutive
+quarters, and in each quarter walk the pairs tile by tile (1,024 pairs),
+rank the tile's pairs stably by (position mod 256) and add each triangle's
+records in that order in FP64; the four quarters' sums are then added in
+order, and finally the (triangle, corner) terms of each vertex from a table
+sorted by vertex.  No atomic operation is involved, so the only ways to lose
+a contribution would be a wrong grouping or a wrong range; this model walks
+exactly those ranges (including cells that span several tiles, empty cells,
+misses and the last, partly filled cell) and must reproduce the oracle's
+gradient.
 """
 import numpy as np
 
 import oracle
 from paper_2209_02878_amd import workloads as wl
 
-CELL_BITS, GROUP_BITS, TILE = 10, 8, 1024
+CELL_BITS, TILE, CHUNKS = 10, 1024, 4
 
 
 def _model(V, T, S, E, tri, g_p, rank, corner0="fp64"):
@@ -51,27 +53,33 @@ def _model(V, T, S, E, tri, g_p, rank, corner0="fp64"):
     # stable grouping by cell
     order = np.argsort(keys >> CELL_BITS, kind="stable")
     sk = keys[order]
-    n_groups = (n_t + (1 << GROUP_BITS) - 1) >> GROUP_BITS
-    n_cells = (n_groups + 3) // 4
+    n_cells = (n_t + (1 << CELL_BITS) - 1) >> CELL_BITS
     tri_sum = np.zeros((n_t, 3, 3))
-    for group in range(4 * n_cells):
-        g = group >> 2
-        lo = np.searchsorted(sk >> CELL_BITS, g, side="left")
-        hi = np.searchsorted(sk >> CELL_BITS, g + 1, side="left")
-        acc = np.zeros((1 << GROUP_BITS, 3, 3))
-        for c0 in range(lo, hi, TILE):
-            ks = sk[c0:min(c0 + TILE, hi)]
-            segs = order[c0:min(c0 + TILE, hi)]
-            sel = (ks < n_t) & ((ks >> GROUP_BITS) == group)
-            # stable rank by position within the tile, then per-triangle order
-            local = ks[sel] & 0xFF
-            for p in np.argsort(local, kind="stable"):
-                r = rec[segs[sel][p]]
-                lam, w = r[:3], -r[3:6]
-                acc[local[p]] += w[:, None] * lam[None, :]
-        base = group << GROUP_BITS
-        m = min(1 << GROUP_BITS, max(0, n_t - base))
-        tri_sum[base:base + m] = acc[:m]
+    for g in range(n_cells):
+        clo = np.searchsorted(sk >> CELL_BITS, g, side="left")
+        chi = np.searchsorted(sk >> CELL_BITS, g + 1, side="left")
+        parts = []
+        for c in range(CHUNKS):
+            lo, hi = clo + (chi - clo) * c // CHUNKS, clo + (chi - clo) * (c + 1) // CHUNKS
+            acc = np.zeros((1 << CELL_BITS, 3, 3))
+            for c0 in range(lo, hi, TILE):
+                ks = sk[c0:min(c0 + TILE, hi)]
+                segs = order[c0:min(c0 + TILE, hi)]
+                sel = ks < n_t
+                local = ks[sel] & ((1 << CELL_BITS) - 1)
+                # stable rank by (local mod 256) within the tile; each
+                # thread then adds its records in that order
+                for p in np.argsort(local & 255, kind="stable"):
+                    r = rec[segs[sel][p]]
+                    lam, w = r[:3], -r[3:6]
+                    acc[local[p]] += w[:, None] * lam[None, :]
+            parts.append(acc)
+        total = np.zeros((1 << CELL_BITS, 3, 3))
+        for acc in parts:  # the quarters in order
+            total += acc
+        base = g << CELL_BITS
+        m = min(1 << CELL_BITS, n_t - base)
+        tri_sum[base:base + m] = total[:m]
     # vertex incidence table sorted by vertex (stable): (vertex, 3 * position + corner)
     inc_v = T.reshape(-1)
     inc_tc = 3 * np.repeat(rank, 3) + np.tile(np.arange(3), n_t)
