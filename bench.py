@@ -249,13 +249,34 @@ def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2, sectio
 
         f = time_events(fwd, 10)
         fb = time_events(fwd_bwd, 10)
+
+        def adjoint_call():
+            # the library's backward alone (the autograd step adds torch's loss
+            # gradient and buffer set-up around it)
+            with torch.no_grad():
+                _, _, P, tri = rsi.FirstHit.apply(Vp, S, E, m)
+                g_p = torch.zeros_like(P)
+                g_p[:, 2] = 2 * (P[:, 2] - target)
+            torch.cuda.synchronize()
+            return time_events(lambda: rsi.rsi_first_hit_backward(m.handle, Vp.detach(), S, E, tri, None, None, g_p),
+                               10)
+
+        def adjoint_roofline(times):
+            t_ms = med(times)
+            # algorithmic traffic per segment: S, E (24 B), triangle id (4 B) and
+            # upstream dL/dP (12 B) in, dS and dE (24 B) out, plus t and (u, v)
+            # gradients when given (12 B): 76 B
+            return {"library_backward_ms": round(t_ms, 4),
+                    "hbm_frac_of_76B_per_segment": round(76.0 * w.n_r / (t_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 5)}
+
+        adj = adjoint_roofline(adjoint_call())
         rec = {
             "forward_ms": round(med(f), 4), "forward_backward_ms": round(med(fb), 4),
             "backward_ms": round(med(fb) - med(f), 4),
             "forward_msegments_per_s": round(w.n_r / med(f) / 1e3, 2),
             "forward_backward_msegments_per_s": round(w.n_r / med(fb) / 1e3, 2),
-            "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3)}
-        log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms")
+            "fwd_bwd_over_fwd_time": round(med(fb) / med(f), 3), "adjoint": adj}
+        log(f"diff first hit: fwd {med(f):.3f} ms, fwd+bwd {med(fb):.3f} ms, adjoint {adj}")
         # the same training step with the segments put in Morton order once
         # (a training loop's segments do not change between steps): the
         # loss is a sum over segments, so its value and dL/dV are those
@@ -268,12 +289,13 @@ def extra_workloads(torch, rsi, wl, dev, time_events, w2, V2, T2, S2, E2, sectio
         S, E = So, Eo
         fo = time_events(fwd, 10)
         fbo = time_events(fwd_bwd, 10)
+        adj_o = adjoint_roofline(adjoint_call())
         S, E, target = S_in, E_in, target_in
         rec["morton_ordered_segments"] = {
             "order_once_ms": round(med(oc), 4), "forward_ms": round(med(fo), 4),
             "forward_backward_ms": round(med(fbo), 4), "backward_ms": round(med(fbo) - med(fo), 4),
             "forward_backward_msegments_per_s": round(w.n_r / med(fbo) / 1e3, 2),
-            "fwd_bwd_over_fwd_time": round(med(fbo) / med(fo), 3)}
+            "fwd_bwd_over_fwd_time": round(med(fbo) / med(fo), 3), "adjoint": adj_o}
         log(f"diff first hit, Morton-ordered segments: fwd {med(fo):.3f} ms, fwd+bwd {med(fbo):.3f} ms "
             f"(order once {med(oc):.3f} ms)")
         out["heightfield_199712tri_4Mseg_first_hit_grad"] = rec
@@ -461,6 +483,29 @@ def main():
     lane_visit_share = cnt["node_visits"] / max(1, 64 * cnt["wave_node_steps"])
     log(f"counters: {cnt}; hit fraction {hits / w.n_r:.4f}; lane-visit share {lane_visit_share:.3f}")
 
+    # the FP32 roofline of the other query modes on the same workload: the
+    # counting variant gives the tests of each launch, HIP events its time
+    out_f = mesh.alloc_outputs(w.n_r, "first")
+    q_first = time_events(lambda: mesh.query_into(S, E, "first", out_f), max(5, reps // 2))
+    mode_rooflines = {}
+    for name, mode, o, times in (("all_hits_k4", "all", out_a, q_all), ("first_hit", "first", out_f, q_first)):
+        mesh.set_counting(True)
+        mesh.query_into(S, E, mode, o, capacity=4)
+        torch.cuda.synchronize()
+        c = mesh.counters()
+        mesh.set_counting(False)
+        ops = OPS_PER_BOX_TEST * c["box_tests"] + OPS_PER_TRI_TEST * c["tri_tests"]
+        t_ms = float(np.median(times))
+        mode_rooflines[name] = {
+            "query_ms": round(t_ms, 4), "fp32_ops_per_launch": int(ops),
+            "achieved_tflops": round(ops / (t_ms / 1e3) / 1e12, 4),
+            "frac": round(ops / (t_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS, 5),
+            "frac_of_unpacked_fp32_78p6": round(ops / (t_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS_UNPACKED, 5),
+            "node_visits_per_segment": round(c["node_visits"] / w.n_r, 4),
+            "lane_visit_share": round(c["node_visits"] / max(1, 64 * c["wave_node_steps"]), 4)}
+    del out_f
+    log(f"other modes: {mode_rooflines}")
+
     traffic = measured_traffic()
     traffic = None if traffic is None else round(traffic)
     l2 = measured_l2()
@@ -492,6 +537,8 @@ def main():
         "all_hits_overflowed_segments": int(st_all["overflow_segments"]),
         "deep_pass_segments_bool": int(st_bool["deep_segments"]),
         "rebuild_ms": round(float(np.median(b_only)), 4),
+        "query_first_hit_ms": mode_rooflines["first_hit"]["query_ms"],
+        "mode_rooflines": mode_rooflines,
         "hit_fraction": round(hits / w.n_r, 5),
         "work_per_segment": {"node_visits": cnt["node_visits"] / w.n_r, "box_tests": cnt["box_tests"] / w.n_r,
                              "tri_tests": cnt["tri_tests"] / w.n_r},
