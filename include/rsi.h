@@ -340,7 +340,10 @@ rsi_status rsi_inside(rsi_handle h, const float *P, int64_t n_p, uint8_t *inside
  * a leaf phase, a refill.  node_visits / (64 * wave_node_steps) is the share
  * of lanes busy in node steps; of the others, summed over node steps,
  * lanes_blocked had a node but waited for pending leaf tests and
- * lanes_waiting had no node (walk over, or no segment). */
+ * lanes_waiting had no node (walk over, or no segment).  wave_leaf_rounds
+ * counts the rounds of the leaf phases (one triangle-leaf test per lane and
+ * round) and leaf_lanes the lanes that tested a leaf in them, so
+ * leaf_lanes / (64 * wave_leaf_rounds) is the share of lanes busy there. */
 typedef struct {
     uint64_t node_visits;
     uint64_t box_tests;
@@ -352,6 +355,8 @@ typedef struct {
     uint64_t wave_refills;
     uint64_t lanes_blocked;
     uint64_t lanes_waiting;
+    uint64_t wave_leaf_rounds;
+    uint64_t leaf_lanes;
 } rsi_counters;
 rsi_status rsi_set_counting(rsi_handle h, int enable);
 rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out);

@@ -914,6 +914,8 @@ rsi_status rsi_get_counters(rsi_handle h, rsi_counters *out)
     out->wave_refills = c.wave_refills;
     out->lanes_blocked = c.lanes_blocked;
     out->lanes_waiting = c.lanes_waiting;
+    out->wave_leaf_rounds = c.wave_leaf_rounds;
+    out->leaf_lanes = c.leaf_lanes;
     return RSI_OK;
 }
 

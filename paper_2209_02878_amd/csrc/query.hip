@@ -55,6 +55,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/rsi.h"
 #include "rsi_host.h"
 
@@ -275,6 +277,52 @@ __device__ inline int32_t wave_take(const QArgs &a, volatile int32_t *wst, bool 
     return need ? nxt + (int32_t)lanes_below(m) : -1;
 }
 
+// A crossing of the lane's segment with the triangle at sorted position pos
+// (original id `id`, parameter t): the first-hit candidate.
+template <uint32_t MODE>
+__device__ inline void take_first(Lane &L, float t, int32_t id, int32_t pos)
+{
+    if (t < L.best_t || (t == L.best_t && id < L.best_id)) {
+        L.best_t = t;
+        L.best_id = id;
+        L.best_pos = pos;
+        if (!(MODE & M_FULL)) L.tlim = fminf(1.0f, t * (1.0f + 0x1p-20f));
+    }
+}
+
+// A crossing at sorted position pos, counted and (all hits) recorded: the
+// first K positions in the lane's slots, the rest as arena records.
+template <uint32_t MODE, bool BATCH>
+__device__ inline void take_crossing(const QArgs &a, Lane &L, int32_t pos, volatile int32_t *wst)
+{
+    if ((MODE & M_COUNT) && !(MODE & M_ALL)) ++L.count;
+    if (MODE & M_ALL) {
+        const int32_t c = L.count++;
+        const int32_t K = a.o.cap;
+        if (c < K) {
+            if (K <= kRegSlots) {
+                // kept in registers until the segment is finished
+                L.hp3 = L.hp2;
+                L.hp2 = L.hp1;
+                L.hp1 = L.hp0;
+                L.hp0 = pos;
+            } else {
+                slot_ids<BATCH>(a, L)[(int64_t)L.seg_i * K + c] = pos;
+            }
+        } else {
+            // past the slots: an arena record (entry, rank, position);
+            // the segment's overflow-table entry is taken at its first
+            const int32_t e = wave_take<0>(a, wst, c == K);
+            if (c == K) L.e = e;
+            const int32_t r = wave_take<1>(a, wst, true);
+            if (L.e < a.ovf_cap && r >= 0 && r < a.arena_cap)
+                a.arena[r] = make_int4(L.e, c, pos, 0);
+            else
+                atomicOr(&a.scalars[kOvfFull], 1);
+        }
+    }
+}
+
 // Test the triangles of one leaf; returns true when the lane may stop.
 // wst: the wave's block state for all-hits overflow (see wave_take).
 template <uint32_t MODE, bool BATCH, bool COUNT>
@@ -293,43 +341,173 @@ __device__ inline bool visit_leaf(const QArgs &a, Lane &L, int32_t ref, uint32_t
         if (!h.hit) continue;
         L.found = true;
         if (MODE == M_BOOL) return true;
-        const float t = h.tn / h.det;
-        if (MODE & M_FIRST) {
-            if (t < L.best_t || (t == L.best_t && id < L.best_id)) {
-                L.best_t = t;
-                L.best_id = id;
-                L.best_pos = pos;
-                if (!(MODE & M_FULL)) L.tlim = fminf(1.0f, t * (1.0f + 0x1p-20f));
-            }
-        }
-        if ((MODE & M_COUNT) && !(MODE & M_ALL)) ++L.count;
-        if (MODE & M_ALL) {
-            const int32_t c = L.count++;
-            const int32_t K = a.o.cap;
-            if (c < K) {
-                if (K <= kRegSlots) {
-                    // kept in registers until the segment is finished
-                    L.hp3 = L.hp2;
-                    L.hp2 = L.hp1;
-                    L.hp1 = L.hp0;
-                    L.hp0 = pos;
-                } else {
-                    slot_ids<BATCH>(a, L)[(int64_t)L.seg_i * K + c] = pos;
-                }
-            } else {
-                // past the slots: an arena record (entry, rank, position);
-                // the segment's overflow-table entry is taken at its first
-                const int32_t e = wave_take<0>(a, wst, c == K);
-                if (c == K) L.e = e;
-                const int32_t r = wave_take<1>(a, wst, true);
-                if (L.e < a.ovf_cap && r >= 0 && r < a.arena_cap)
-                    a.arena[r] = make_int4(L.e, c, pos, 0);
-                else
-                    atomicOr(&a.scalars[kOvfFull], 1);
-            }
-        }
+        if (MODE & M_FIRST) take_first<MODE>(L, h.tn / h.det, id, pos);
+        take_crossing<MODE, BATCH>(a, L, pos, wst);
     }
     return false;
+}
+
+// Order the wave's LDS accesses on either side (its lanes exchange data
+// through LDS).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Leaf phase of the four-way walk.  A lane holds up to four pending leaves
+// (one per child slot of its last node); tested by their owners, a phase
+// would take as many rounds as the busiest lane has leaves, with few lanes
+// busy in each.  Instead the wave's pending (lane, leaf) pairs are gathered,
+// slot by slot, into a queue of 64 in LDS and each lane tests one pair per
+// round against the owner's segment (read from the owner's registers); the
+// owners then take the outcomes back.  Pairs past the 64th wait for the next
+// round.  The outcome of a leaf is the set of its triangles crossed (a bit
+// mask) and, for the first hit, its best crossing in (t, id) order: the
+// owner's results are the same as from testing its leaves itself, in any
+// order.  The plain boolean query needs one bit per leaf and takes it from
+// a ballot; the other modes get the outcome back through the queue entry.
+template <uint32_t MODE>
+using LeafEnt = typename std::conditional<MODE == M_BOOL, int2, int4>::type;
+
+template <uint32_t MODE, bool BATCH, bool COUNT>
+__device__ inline void leaf_phase4(const QArgs &a, Lane &L, int32_t &leaf0, int32_t &leaf1, int32_t &leaf2,
+                                   int32_t &leaf3, int32_t &node, uint32_t &tests, volatile int32_t *wst,
+                                   LeafEnt<MODE> *q, uint32_t &w_rounds, unsigned long long &w_lanes)
+{
+    const int32_t lane = (int32_t)__lane_id();
+    for (;;) {
+        const uint64_t b0 = ballot(leaf0 != 0), b1 = ballot(leaf1 != 0);
+        const uint64_t b2 = ballot(leaf2 != 0), b3 = ballot(leaf3 != 0);
+        const int32_t c0 = (int32_t)__popcll(b0), c1 = (int32_t)__popcll(b1);
+        const int32_t c2 = (int32_t)__popcll(b2), c3 = (int32_t)__popcll(b3);
+        const int32_t total = c0 + c1 + c2 + c3;
+        if (total == 0) break;
+        const int32_t p0 = (int32_t)lanes_below(b0);
+        const int32_t p1 = c0 + (int32_t)lanes_below(b1);
+        const int32_t p2 = c0 + c1 + (int32_t)lanes_below(b2);
+        const int32_t p3 = c0 + c1 + c2 + (int32_t)lanes_below(b3);
+        const bool in0 = leaf0 != 0 && p0 < 64, in1 = leaf1 != 0 && p1 < 64;
+        const bool in2 = leaf2 != 0 && p2 < 64, in3 = leaf3 != 0 && p3 < 64;
+        auto put = [&](bool in, int32_t p, int32_t ref) {
+            if (!in) return;
+            LeafEnt<MODE> e;
+            e.x = ref;
+            e.y = lane;
+            q[p] = e;
+        };
+        put(in0, p0, leaf0);
+        put(in1, p1, leaf1);
+        put(in2, p2, leaf2);
+        put(in3, p3, leaf3);
+        wave_lds_sync();
+        const int32_t n = total < 64 ? total : 64;
+        const bool mine = lane < n;
+        int2 ent = make_int2(0, lane);
+        if (mine) {
+            const LeafEnt<MODE> e = q[lane];
+            ent = make_int2(e.x, e.y);
+        }
+        wave_lds_sync();
+        if (COUNT) {
+            ++w_rounds;
+            w_lanes += (unsigned long long)n;
+        }
+        // the owner's segment and t limit
+        const int32_t own = ent.y;
+        Seg s;
+        s.ox = __shfl(L.seg.ox, own, 64);
+        s.oy = __shfl(L.seg.oy, own, 64);
+        s.oz = __shfl(L.seg.oz, own, 64);
+        s.dx = __shfl(L.seg.dx, own, 64);
+        s.dy = __shfl(L.seg.dy, own, 64);
+        s.dz = __shfl(L.seg.dz, own, 64);
+        s.ix = s.iy = s.iz = 0.0f;
+        float lim = (MODE & M_FULL) || MODE == M_BOOL ? 1.0f : __shfl(L.tlim, own, 64);
+        uint32_t mask = 0;
+        float bt = INFINITY;
+        int32_t bid = 0x7FFFFFFF, bpos = -1;
+        if (mine) {
+            const int32_t first = leaf_first(ent.x);
+            const int32_t cnt = leaf_count(ent.x);
+            for (int32_t k = 0; k < cnt; ++k) {
+                const int32_t pos = first + k;
+                float v[9];
+                int32_t id;
+                tri_load(a.tris, pos, v, id);
+                if (COUNT) ++tests;
+                const MTHit h = mt_test(s, v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], lim);
+                if (!h.hit) continue;
+                mask |= 1u << k;
+                if (MODE == M_BOOL) break;
+                if (MODE & M_FIRST) {
+                    const float t = h.tn / h.det;
+                    if (t < bt || (t == bt && id < bid)) {
+                        bt = t;
+                        bid = id;
+                        bpos = pos;
+                        if (!(MODE & M_FULL)) lim = fminf(1.0f, t * (1.0f + 0x1p-20f));
+                    }
+                }
+            }
+        }
+        // outcomes back to the owners
+        if constexpr (MODE == M_BOOL) {
+            const uint64_t H = ballot(mask != 0);
+            const bool hit = (in0 && ((H >> p0) & 1)) || (in1 && ((H >> p1) & 1)) || (in2 && ((H >> p2) & 1)) ||
+                             (in3 && ((H >> p3) & 1));
+            if (hit) {
+                L.found = true;
+                leaf0 = leaf1 = leaf2 = leaf3 = 0;
+                node = -1;
+            }
+        } else {
+            // each lane's outcome replaces the entry it tested
+            q[lane] = make_int4((int32_t)mask, __float_as_int(bt), bid, bpos);
+            wave_lds_sync();
+            // the owner's outcomes; all hits: then its crossings, one per
+            // iteration (the recording code appears once)
+            uint32_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+            auto back = [&](bool in, int32_t p, uint32_t &m) {
+                if (!in) return;
+                const int4 r = q[p];
+                m = (uint32_t)r.x;
+                if (m == 0) return;
+                L.found = true;
+                if (MODE & M_FIRST) take_first<MODE>(L, __int_as_float(r.y), r.z, r.w);
+                if ((MODE & M_COUNT) && !(MODE & M_ALL)) L.count += (int32_t)__popc(m);
+            };
+            back(in0, p0, m0);
+            back(in1, p1, m1);
+            back(in2, p2, m2);
+            back(in3, p3, m3);
+            wave_lds_sync();
+            if constexpr ((MODE & M_ALL) != 0) {
+                while ((m0 | m1 | m2 | m3) != 0) {
+                    int32_t pos;
+                    if (m0) {
+                        pos = leaf_first(leaf0) + (int32_t)__builtin_ctz(m0);
+                        m0 &= m0 - 1;
+                    } else if (m1) {
+                        pos = leaf_first(leaf1) + (int32_t)__builtin_ctz(m1);
+                        m1 &= m1 - 1;
+                    } else if (m2) {
+                        pos = leaf_first(leaf2) + (int32_t)__builtin_ctz(m2);
+                        m2 &= m2 - 1;
+                    } else {
+                        pos = leaf_first(leaf3) + (int32_t)__builtin_ctz(m3);
+                        m3 &= m3 - 1;
+                    }
+                    take_crossing<MODE, BATCH>(a, L, pos, wst);
+                }
+            }
+        }
+        if (in0) leaf0 = 0;
+        if (in1) leaf1 = 0;
+        if (in2) leaf2 = 0;
+        if (in3) leaf3 = 0;
+    }
 }
 
 // Write the results of a finished segment (or queue it for the deep pass).
@@ -418,7 +596,8 @@ template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_ALL) ? 6 : 1))) void k_query(QArgs a)
 {
     constexpr bool HYB = RETRY;
-    extern __shared__ int32_t lds_stack[];
+    extern __shared__ int32_t lds_dyn[];
+    int32_t *const lds_stack = lds_dyn;
     constexpr bool TOP = WIDE && !BATCH && top_copy(MODE);
     __shared__ uint4 top4[TOP ? 4 * kTopNodes : 4];
     if constexpr (TOP) {
@@ -438,6 +617,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
     // all hits: the wave's blocks of overflow-table entries and arena
     // records, (next, end) each, none held at first
     __shared__ int32_t wave_blocks[(MODE & M_ALL) ? 4 * kWavesPerBlock : 1];
+    // four-way walk: the wave's leaf queue, past the stack's LDS part
+    LeafEnt<MODE> *const leafq =
+        reinterpret_cast<LeafEnt<MODE> *>(lds_dyn + (size_t)a.lds_depth * blockDim.x) + 64 * (threadIdx.x >> 6);
     volatile int32_t *const wst = wave_blocks + ((MODE & M_ALL) ? 4 * (threadIdx.x >> 6) : 0);
     if ((MODE & M_ALL) && __lane_id() == 0) {
         wst[0] = wst[1] = 0;
@@ -470,6 +652,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
     uint32_t visits = 0, boxes = 0, tests = 0, segs = 0;
     uint32_t w_loops = 0, w_steps = 0, w_leaf = 0, w_refill = 0;  // wave-uniform
     unsigned long long w_blocked = 0, w_waiting = 0;               // wave-uniform
+    uint32_t w_lrounds = 0;                                        // wave-uniform
+    unsigned long long w_llanes = 0;                               // wave-uniform
     int32_t chunk_next = 0, chunk_end = 0;  // the wave's claimed, not yet handed out items
     int32_t n_items = (int32_t)a.n_items;
     if (RETRY) {
@@ -782,16 +966,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
         const uint64_t pend = ballot(WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) != 0 : leaf0 != 0);
         if (pend != 0) {
             if (COUNT) ++w_leaf;
-            if constexpr (WIDE) {
-                // one pending leaf per lane and round, the first occupied slot
+            if constexpr (WIDE && !(MODE & M_ALL)) {
+                leaf_phase4<MODE, BATCH, COUNT>(a, L, leaf0, leaf1, leaf2, leaf3, node, tests, wst, leafq,
+                                                w_lrounds, w_llanes);
+            } else if constexpr (WIDE) {
+                // all hits: one pending leaf per lane and round, the first
+                // occupied slot (the gathered phase needs more registers
+                // than these variants have)
                 do {
                     const int32_t cur = leaf0 ? leaf0 : (leaf1 ? leaf1 : (leaf2 ? leaf2 : leaf3));
+                    if (COUNT) {
+                        ++w_lrounds;
+                        w_llanes += (unsigned long long)__popcll(ballot(cur != 0));
+                    }
                     if (cur != 0) {
-                        const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, cur, tests, wst);
-                        if (stop) {
-                            leaf0 = leaf1 = leaf2 = leaf3 = 0;
-                            node = -1;
-                        } else if (leaf0 == cur) {
+                        visit_leaf<MODE, BATCH, COUNT>(a, L, cur, tests, wst);
+                        if (leaf0 == cur) {
                             leaf0 = 0;
                         } else if (leaf1 == cur) {
                             leaf1 = 0;
@@ -803,6 +993,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
                     }
                 } while (ballot((leaf0 | leaf1 | leaf2 | leaf3) != 0) != 0);
             } else do {
+                if (COUNT) {
+                    ++w_lrounds;
+                    w_llanes += (unsigned long long)__popcll(ballot(leaf0 != 0));
+                }
                 if (leaf0 != 0) {
                     const bool stop = visit_leaf<MODE, BATCH, COUNT>(a, L, leaf0, tests, wst);
                     leaf0 = stop ? 0 : leaf1;
@@ -834,6 +1028,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
             atomicAdd(&a.counters->wave_refills, (unsigned long long)w_refill);
             atomicAdd(&a.counters->lanes_blocked, w_blocked);
             atomicAdd(&a.counters->lanes_waiting, w_waiting);
+            atomicAdd(&a.counters->wave_leaf_rounds, (unsigned long long)w_lrounds);
+            atomicAdd(&a.counters->leaf_lanes, w_llanes);
         }
     }
 }
@@ -1324,6 +1520,7 @@ __global__ void k_reset(int32_t *scalars, Counters *c, int keep)
         c->node_visits = c->box_tests = c->tri_tests = c->segments = 0;
         c->wave_loops = c->wave_node_steps = c->wave_leaf_phases = c->wave_refills = 0;
         c->lanes_blocked = c->lanes_waiting = 0;
+        c->wave_leaf_rounds = c->leaf_lanes = 0;
     }
 }
 
@@ -1492,12 +1689,21 @@ hipError_t dispatch(uint32_t mode, const QArgs &a, const QArgs &d, int block, si
     }
 }
 
+// Dynamic LDS of a query launch: the stack's LDS part, then in the
+// four-way walk (all-hits modes aside) each wave's leaf queue (64 entries).
+size_t query_lds(int block, int depth, int width, uint32_t mode)
+{
+    const size_t ent = mode == M_BOOL ? sizeof(int2) : sizeof(int4);
+    const bool queue = width == 4 && !(mode & M_ALL);
+    return (size_t)block * depth * sizeof(int32_t) + (queue ? (size_t)(block / 64) * 64 * ent : 0);
+}
+
 // Largest multiple of 64 not above `want` (and at most 256, the kernels'
-// launch bound) whose LDS part of the stack fits in 64 KiB.
-int fit_block(int want, int depth)
+// launch bound) whose LDS part fits in 64 KiB.
+int fit_block(int want, int depth, int width, uint32_t mode)
 {
     int b = want < 256 ? want : 256;
-    while (b > 64 && (size_t)b * depth * sizeof(int32_t) > 65536) b -= 64;
+    while (b > 64 && query_lds(b, depth, width, mode) > 65536) b -= 64;
     return b;
 }
 
@@ -1593,7 +1799,7 @@ hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
 int64_t deep_stack_entries(const rsi_bvh *h, uint32_t mode)
 {
     const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
-    const int block = fit_block(h->block_size, ld);
+    const int block = fit_block(h->block_size, ld, h->width_built, mode);
     const int need = stack_need(h->height_bound, h->width_built);
     return need > ld ? (int64_t)kRetryBlocksPerCU * device_cus() * block * (need - ld) : 0;
 }
@@ -1610,8 +1816,8 @@ hipError_t launch_query_scratch(rsi_bvh *h, const float *S, const float *E, int6
 {
     if (n_r == 0) return hipSuccess;
     const int ld = lds_part(h, h->width_built == 4 && top_copy(mode));
-    const int block = fit_block(h->block_size, ld);
-    const size_t lds = (size_t)block * ld * sizeof(int32_t);
+    const int block = fit_block(h->block_size, ld, h->width_built, mode);
+    const size_t lds = query_lds(block, ld, h->width_built, mode);
     QArgs a = make_args(h, S, E, n_r, o), d;
     a.retry_q = sc.retry_q;
     a.retry_cap = sc.retry_cap;
@@ -1632,8 +1838,8 @@ hipError_t launch_batch_query(rsi_bvh *h, const BatchTables &bt, int64_t n_total
 {
     if (n_total == 0) return hipSuccess;
     const int ld = lds_part(h, false);
-    const int block = fit_block(h->block_size, ld);
-    const size_t lds = (size_t)block * ld * sizeof(int32_t);
+    const int block = fit_block(h->block_size, ld, h->width_built, mode);
+    const size_t lds = query_lds(block, ld, h->width_built, mode);
     QueryOut o = {};
     o.cap = cap;
     o.pool_ids = h->pool_ids;

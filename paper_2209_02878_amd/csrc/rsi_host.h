@@ -40,6 +40,8 @@ struct Counters {
     // phase, with a refill
     unsigned long long wave_loops, wave_node_steps, wave_leaf_phases, wave_refills;
     unsigned long long lanes_blocked, lanes_waiting;
+    // leaf phases: rounds (one leaf test per lane and round), lanes testing
+    unsigned long long wave_leaf_rounds, leaf_lanes;
 };
 
 // Radix-sort scratch sized for n elements.

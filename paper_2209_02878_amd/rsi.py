@@ -74,7 +74,8 @@ class rsi_counters(ctypes.Structure):
                 ("tri_tests", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("wave_loops", ctypes.c_uint64), ("wave_node_steps", ctypes.c_uint64),
                 ("wave_leaf_phases", ctypes.c_uint64), ("wave_refills", ctypes.c_uint64),
-                ("lanes_blocked", ctypes.c_uint64), ("lanes_waiting", ctypes.c_uint64)]
+                ("lanes_blocked", ctypes.c_uint64), ("lanes_waiting", ctypes.c_uint64),
+                ("wave_leaf_rounds", ctypes.c_uint64), ("leaf_lanes", ctypes.c_uint64)]
 
 
 class rsi_tree_info(ctypes.Structure):

@@ -45,4 +45,7 @@ def test_counters_account_for_every_lane(branching, mode):
     hits = int((got["hit"] if "hit" in got else (got["count"] > 0) if "count" in got else (got["tri"] >= 0)).sum())
     assert c["tri_tests"] >= hits
     assert 0 < c["wave_refills"] <= c["wave_loops"]
+    assert c["wave_leaf_phases"] <= c["wave_leaf_rounds"]
+    assert c["wave_leaf_rounds"] <= c["leaf_lanes"] <= 64 * c["wave_leaf_rounds"]
+    assert c["leaf_lanes"] <= c["tri_tests"]
     mesh.close()
