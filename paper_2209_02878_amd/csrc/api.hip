@@ -51,7 +51,7 @@ void free_handle_memory(rsi_bvh *h)
                     h->inc_vals, h->compact_counts, h->nodes4, h->aux_E, h->aux_count,
                     h->retry_q, h->retry_stack, h->arena, h->T, h->V_all, h->src_V, h->src_T, h->cent, h->keys,
                     h->order, h->nodes, h->tris, h->arrive, h->heights, h->climb, h->split_prefix, h->scalars,
-                    h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_off, h->ovf_part, h->pool_ids, h->pool_ts, h->tri_off,
+                    h->counters, h->ovf_seg, h->ovf_cnt, h->ovf_list, h->ovf_off, h->ovf_part, h->pool_ids, h->pool_ts, h->tri_off,
                     h->vert_off, h->mesh_bounds, h->mesh_height, h->mesh_root, h->mesh_entry};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);

@@ -85,6 +85,7 @@ struct QArgs {
     int32_t *ovf_seg;
     int32_t *ovf_cnt;
     int64_t *ovf_off;
+    int32_t *ovf_list;  // all hits: entries that are not void, in table order (kOvfValid of them)
     int64_t ovf_cap;
     int4 *arena;
     int64_t arena_cap;
@@ -1090,6 +1091,16 @@ __device__ inline unsigned long long block_sum256(unsigned long long v, unsigned
     return t;
 }
 
+// The scans run over one 64-bit value per entry: the entry's crossings in
+// the low 40 bits (the pool is far smaller) and 1 above them for an entry
+// that is not void, so one pass yields pool offsets and list positions.
+constexpr int kOvfCrossBits = 40;
+constexpr unsigned long long kOvfCrossMask = (1ull << kOvfCrossBits) - 1;
+__device__ inline unsigned long long ovf_packed(int32_t c)
+{
+    return c > 0 ? (1ull << kOvfCrossBits) + (unsigned long long)c : 0ull;
+}
+
 __global__ __launch_bounds__(256) void k_ovf_sums(QArgs a)
 {
     __shared__ unsigned long long sh[4];
@@ -1098,10 +1109,7 @@ __global__ __launch_bounds__(256) void k_ovf_sums(QArgs a)
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
     unsigned long long v = 0;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
-        const int32_t c = a.ovf_cnt[e];
-        if (c > 0) v += (unsigned long long)c;
-    }
+    for (int64_t e = lo + threadIdx.x; e < hi; e += 256) v += ovf_packed(a.ovf_cnt[e]);
     v = block_sum256(v, sh);
     if (threadIdx.x == 0) a.ovf_part[blockIdx.x] = v;
 }
@@ -1122,9 +1130,10 @@ __global__ __launch_bounds__(kOvfParts) void k_ovf_scan_parts(QArgs a)
     for (int w = 0; w < (tid >> 6); ++w) before += sh[w];
     a.ovf_part[tid] = before + incl - mine;
     if (tid == kOvfParts - 1) {
-        const unsigned long long tot = before + incl;
+        const unsigned long long tot = (before + incl) & kOvfCrossMask;
         a.scalars[kOvfTotalLo] = (int32_t)(uint32_t)tot;
         a.scalars[kOvfTotalHi] = (int32_t)(uint32_t)(tot >> 32);
+        a.scalars[kOvfValid] = (int32_t)((before + incl) >> kOvfCrossBits);
     }
 }
 
@@ -1145,7 +1154,7 @@ __global__ __launch_bounds__(256) void k_ovf_offsets(QArgs a)
     for (int64_t t0 = lo; t0 < hi; t0 += 256) {
         const int64_t e = t0 + threadIdx.x;
         const int32_t c = e < hi ? a.ovf_cnt[e] : -1;
-        const unsigned long long mine = c > 0 ? (unsigned long long)c : 0ull;
+        const unsigned long long mine = ovf_packed(c);
         // exclusive scan of the tile's counts
         unsigned long long incl = mine;
         for (int off = 1; off < 64; off <<= 1) {
@@ -1162,10 +1171,18 @@ __global__ __launch_bounds__(256) void k_ovf_offsets(QArgs a)
             const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
             int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, a.ovf_seg[e])] : a.o.spill_off;
             int32_t *ids = v.ids + v.i * K;
-            const int64_t off = (int64_t)(base + before + incl - mine);
+            const unsigned long long at = base + before + incl - mine;
+            const int64_t off = (int64_t)(at & kOvfCrossMask);
+            a.ovf_list[at >> kOvfCrossBits] = (int32_t)e;
             if (off + c <= a.o.pool_cap) {
                 a.ovf_off[e] = off;
                 for (int k = 0; k < K; ++k) a.o.pool_ids[off + k] = ids[k];
+                // the rest of the range is filled from the arena (an entry
+                // no record reaches, after a full arena, stays a miss)
+                for (int k = K; k < c; ++k) {
+                    a.o.pool_ids[off + k] = -1;
+                    a.o.pool_ts[off + k] = INFINITY;
+                }
                 if (soff) soff[v.i] = off;
             } else {
                 a.ovf_off[e] = -1;
@@ -1182,85 +1199,215 @@ __global__ __launch_bounds__(256) void k_ovf_offsets(QArgs a)
     }
 }
 
-// All hits, after the walk: move every arena record (entry e, rank c,
-// sorted position) into slot c of its segment's pool range.
+// Add a workgroup's per-thread counts to a device counter with one atomic.
+__device__ inline void block_count(int32_t v, int32_t *sh, int32_t *counter)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (__lane_id() == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+        if (t) atomicAdd(counter, t);
+    }
+    __syncthreads();
+}
+
+// All hits, after the walk: every crossing of an overflowed segment is
+// re-solved in FP64 into its place in the segment's pool range, one thread
+// per crossing: items [0, n_arena) are the arena records (entry e, rank c,
+// sorted position), the next n_valid * K items the first K crossings of
+// each listed entry (their positions were copied to the head of its range).
 // Records of a void entry (a walk handed to the deep pass) are skipped.
+template <bool BATCH>
 __global__ __launch_bounds__(256) void k_spill_place(QArgs a)
 {
+    __shared__ int32_t sh[4];
     const unsigned long long na = (uint32_t)a.scalars[kArenaLo] | ((unsigned long long)(uint32_t)a.scalars[kArenaHi] << 32);
-    const int64_t n = (int64_t)(na < (unsigned long long)a.arena_cap ? na : (unsigned long long)a.arena_cap);
+    const int64_t n_arena = (int64_t)(na < (unsigned long long)a.arena_cap ? na : (unsigned long long)a.arena_cap);
+    const int32_t K = a.o.cap;
+    const int64_t n_valid = a.scalars[kOvfValid];
+    const int64_t n = n_arena + n_valid * K;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-        const int4 rec = a.arena[r];
-        if (rec.x < 0 || rec.x >= a.ovf_cap) continue;
-        const int32_t cnt = a.ovf_cnt[rec.x];
-        if (cnt < 0 || rec.y >= cnt) continue;
-        const int64_t off = a.ovf_off[rec.x];
-        if (off < 0 || off + cnt > a.o.pool_cap) continue;
-        a.o.pool_ids[off + rec.y] = rec.z;
-        atomicAdd(&a.scalars[kArenaUsed], 1);
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    for (int64_t r0 = first; r0 < n; r0 += stride) {
+        const int64_t r = r0 + threadIdx.x;
+        int32_t placed = 0;
+        if (r < n) {
+            int32_t e, c, pos = -1;
+            if (r < n_arena) {
+                const int4 rec = a.arena[r];
+                e = rec.x;
+                c = rec.y;
+                pos = rec.z;
+            } else {
+                const int64_t j = (r - n_arena) / K;
+                e = a.ovf_list[j];
+                c = (int32_t)((r - n_arena) - j * K);
+            }
+            const int32_t cnt = (e >= 0 && e < a.ovf_cap) ? a.ovf_cnt[e] : -1;
+            const int64_t off = cnt >= 0 ? a.ovf_off[e] : -1;
+            if (cnt >= 0 && c < cnt && off >= 0 && off + cnt <= a.o.pool_cap) {
+                if (r >= n_arena) pos = a.o.pool_ids[off + c];
+                else placed = 1;
+                int32_t id = 0x7FFFFFFF;
+                float t = INFINITY;
+                if (pos >= 0 && pos < a.n_tris) {
+                    const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
+                    float w[9];
+                    tri_load(a.tris, pos, w, id);
+                    double td, u, vv;
+                    mt_refine64(v.S[3 * v.i], v.S[3 * v.i + 1], v.S[3 * v.i + 2], v.E[3 * v.i], v.E[3 * v.i + 1],
+                                v.E[3 * v.i + 2], w, td, u, vv);
+                    t = (float)td;
+                }
+                a.o.pool_ids[off + c] = id;
+                a.o.pool_ts[off + c] = t;
+            }
+        }
+        block_count(placed, sh, &a.scalars[kArenaUsed]);
     }
 }
 
-// All hits: one thread per overflowed segment re-solves its crossings in
-// FP64 (sorted positions become triangle ids), orders them by (t, id) in the
-// pool (shell sort, gaps 13, 4, 1, then insertion: lists are short) and
-// copies the first K into the segment's slots.
+// Order a list of n <= N crossings by (t, id) in registers: loaded at
+// once, odd-even transposition rounds over fixed indices (entries past n
+// are (inf, max) and stay behind the list), written back.
+template <int N>
+__device__ inline void sort_in_registers(int32_t *ids, float *ts, int32_t n)
+{
+    float t[N];
+    int32_t id[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        t[c] = c < n ? ts[c] : INFINITY;
+        id[c] = c < n ? ids[c] : 0x7FFFFFFF;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+        for (int c = r & 1; c + 1 < N; c += 2) {
+            if (t[c + 1] < t[c] || (t[c + 1] == t[c] && id[c + 1] < id[c])) {
+                const float tf = t[c];
+                t[c] = t[c + 1];
+                t[c + 1] = tf;
+                const int32_t tk = id[c];
+                id[c] = id[c + 1];
+                id[c + 1] = tk;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        if (c < n) {
+            ts[c] = t[c];
+            ids[c] = id[c];
+        }
+    }
+}
+
+// Order a longer list in place (shell sort, gaps 13, 4, 1).
+__device__ inline void shell_sort(int32_t *ids, float *ts, int32_t n)
+{
+    const int gaps[3] = {13, 4, 1};
+    for (int g = 0; g < 3; ++g) {
+        const int gap = gaps[g];
+        for (int x = gap; x < n; ++x) {
+            const float kt = ts[x];
+            const int32_t ki = ids[x];
+            int y = x - gap;
+            while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                ts[y + gap] = ts[y];
+                ids[y + gap] = ids[y];
+                y -= gap;
+            }
+            ts[y + gap] = kt;
+            ids[y + gap] = ki;
+        }
+    }
+}
+
+// All hits: every overflowed segment's re-solved crossings are ordered by
+// (t, id) in the pool and the first K copied into the segment's slots.  A
+// list of up to 16 is sorted by its own thread in registers; a longer one
+// by the whole wave: staged in LDS, each lane ranks entries against the
+// whole list (ties by position, so ranks are distinct) and writes them to
+// their places.  Lists longer than the LDS stage fall back to one thread.
+constexpr int kLongListStage = 1024;
+
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_spill_finish(QArgs a)
 {
-    const int32_t ne = a.scalars[kOvfSegs];
-    const int64_t n = ne < a.ovf_cap ? ne : a.ovf_cap;
+    __shared__ int32_t sh[4];
+    __shared__ float st_t[4][kLongListStage];
+    __shared__ int32_t st_id[4][kLongListStage];
+    const int64_t n = a.scalars[kOvfValid];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int K = a.o.cap;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        const int32_t cnt = a.ovf_cnt[e];
-        if (cnt < 0) continue;
-        atomicAdd(&a.scalars[kOvfUsed], 1);
-        const int64_t off = a.ovf_off[e];
-        if (off < 0 || off + cnt > a.o.pool_cap) continue;
-        const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
-        const float sx = v.S[3 * v.i], sy = v.S[3 * v.i + 1], sz = v.S[3 * v.i + 2];
-        const float ex = v.E[3 * v.i], ey = v.E[3 * v.i + 1], ez = v.E[3 * v.i + 2];
-        int32_t *ids = a.o.pool_ids + off;
-        float *ts = a.o.pool_ts + off;
-        for (int c = 0; c < cnt; ++c) {
-            // an entry no record reached (a full arena, reported) is never read through
-            const int32_t pos = ids[c];
-            if (pos < 0 || pos >= a.n_tris) {
-                ids[c] = 0x7FFFFFFF;
-                ts[c] = INFINITY;
-                continue;
+    const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < n; j0 += stride) {
+        const int64_t j = j0 + threadIdx.x;
+        const int32_t e = j < n ? a.ovf_list[j] : -1;
+        int32_t cnt = e >= 0 ? a.ovf_cnt[e] : -1;
+        block_count(cnt >= 0 ? 1 : 0, sh, &a.scalars[kOvfUsed]);
+        int64_t off = -1;
+        int32_t *sid = nullptr;
+        float *sts = nullptr;
+        if (cnt >= 0) {
+            off = a.ovf_off[e];
+            if (off < 0 || off + cnt > a.o.pool_cap) {
+                cnt = -1;
+            } else {
+                const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[e]);
+                sid = v.ids + v.i * (int64_t)K;
+                sts = v.ts + v.i * (int64_t)K;
             }
-            float w[9];
-            int32_t id;
-            tri_load(a.tris, pos, w, id);
-            double t, u, vv;
-            mt_refine64(sx, sy, sz, ex, ey, ez, w, t, u, vv);
-            ids[c] = id;
-            ts[c] = (float)t;
         }
-        const int gaps[3] = {13, 4, 1};
-        for (int g = 0; g < 3; ++g) {
-            const int gap = gaps[g];
-            for (int x = gap; x < cnt; ++x) {
-                const float kt = ts[x];
-                const int32_t ki = ids[x];
-                int y = x - gap;
-                while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
-                    ts[y + gap] = ts[y];
-                    ids[y + gap] = ids[y];
-                    y -= gap;
+        if (cnt >= 0 && (cnt <= 16 || cnt > kLongListStage)) {
+            int32_t *ids = a.o.pool_ids + off;
+            float *ts = a.o.pool_ts + off;
+            if (cnt <= 8) sort_in_registers<8>(ids, ts, cnt);
+            else if (cnt <= 16) sort_in_registers<16>(ids, ts, cnt);
+            else shell_sort(ids, ts, cnt);
+            for (int c = 0; c < K; ++c) {
+                sid[c] = ids[c];
+                sts[c] = ts[c];
+            }
+        }
+        // the wave's long lists, one at a time
+        uint64_t longm = ballot(cnt > 16 && cnt <= kLongListStage);
+        while (longm != 0) {
+            const int src = __builtin_ctzll(longm);
+            longm &= longm - 1;
+            const int32_t es = __shfl(e, src, 64);
+            const int32_t m = __shfl(cnt, src, 64);
+            const int64_t o = a.ovf_off[es];
+            const ItemView<BATCH> v = item_view<BATCH>(a, a.ovf_seg[es]);
+            int32_t *s_id = v.ids + v.i * (int64_t)K;
+            float *s_t = v.ts + v.i * (int64_t)K;
+            int32_t *ids = a.o.pool_ids + o;
+            float *ts = a.o.pool_ts + o;
+            for (int j = lane; j < m; j += 64) {
+                st_t[wave][j] = ts[j];
+                st_id[wave][j] = ids[j];
+            }
+            wave_lds_sync();
+            for (int j = lane; j < m; j += 64) {
+                const float tj = st_t[wave][j];
+                const int32_t ij = st_id[wave][j];
+                int32_t rank = 0;
+                for (int i = 0; i < m; ++i) {
+                    const float ti = st_t[wave][i];
+                    const int32_t ii = st_id[wave][i];
+                    rank += (ti < tj || (ti == tj && (ii < ij || (ii == ij && i < j)))) ? 1 : 0;
                 }
-                ts[y + gap] = kt;
-                ids[y + gap] = ki;
+                ts[rank] = tj;
+                ids[rank] = ij;
+                if (rank < K) {
+                    s_t[rank] = tj;
+                    s_id[rank] = ij;
+                }
             }
-        }
-        int32_t *sid = v.ids + v.i * (int64_t)K;
-        float *sts = v.ts + v.i * (int64_t)K;
-        for (int c = 0; c < K; ++c) {
-            sid[c] = ids[c];
-            sts[c] = ts[c];
+            wave_lds_sync();
         }
     }
 }
@@ -1308,106 +1455,83 @@ __device__ inline void item_ends(const QArgs &a, int64_t k, float &sx, float &sy
 // of 256 segments in order; for K <= 4 the tile's (segment, slot) pairs are
 // packed so that the FP64 solves run on full waves, their results pass
 // through LDS, and every lane then writes its own segment's slots (the
-// lanes' rows are contiguous, so the stores fill whole lines).
+// lanes' rows are contiguous, so the stores fill whole lines).  A tile's
+// counts are loaded while the previous tile is packed, its positions and
+// segment ends while the previous tile's pairs are solved.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
 {
     const int K = a.o.cap;
     const int tid = threadIdx.x;
-    if (K > kRegSlots) {
-        // a segment per lane, its slots in order
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        for (int64_t k = (int64_t)blockIdx.x * blockDim.x + tid; k < a.n_items; k += stride) {
-            const ItemView<BATCH> v = item_view<BATCH>(a, k);
-            const int32_t *cnt = BATCH ? a.bt.count[mesh_of(a.bt.seg_off, a.M, k)] : a.o.count;
-            int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, k)] : a.o.spill_off;
-            const int32_t n = cnt[v.i];
-            if (n > K) continue;
-            if (soff) st_nt(soff + v.i, (int64_t)-1);
-            int32_t *ids = v.ids + v.i * (int64_t)K;
-            float *ts = v.ts + v.i * (int64_t)K;
-            if (n > 0) {
-                float sx, sy, sz, ex, ey, ez;
-                item_ends<BATCH>(a, k, sx, sy, sz, ex, ey, ez);
-                for (int c = 0; c < n; ++c) {
-                    const int32_t pos = ids[c];
-                    if (pos < 0 || pos >= a.n_tris) {
-                        ids[c] = 0x7FFFFFFF;
-                        ts[c] = INFINITY;
-                        continue;
-                    }
-                    float w[9];
-                    int32_t tid3;
-                    tri_load(a.tris, pos, w, tid3);
-                    double tt, u, ww;
-                    mt_refine64(sx, sy, sz, ex, ey, ez, w, tt, u, ww);
-                    ids[c] = tid3;
-                    ts[c] = (float)tt;
-                }
-                for (int x = 1; x < n; ++x) {  // insertion sort by (t, id): lists are short
-                    const float kt = ts[x];
-                    const int32_t ki = ids[x];
-                    int y = x - 1;
-                    while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
-                        ts[y + 1] = ts[y];
-                        ids[y + 1] = ids[y];
-                        --y;
-                    }
-                    ts[y + 1] = kt;
-                    ids[y + 1] = ki;
-                }
-            }
-            for (int c = n; c < K; ++c) {
-                ids[c] = -1;
-                ts[c] = INFINITY;
-            }
-        }
-        return;
-    }
     __shared__ int32_t sh[4];
     __shared__ int32_t q_pair[256 * kRegSlots];  // (lane << 2) | slot
-    __shared__ int32_t q_pos[256 * kRegSlots];
-    __shared__ int32_t r_id[256 * kRegSlots];
+    __shared__ int32_t r_id[256 * kRegSlots];    // a pair's position, then its triangle id
     __shared__ float r_t[256 * kRegSlots];
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.n_items; base += (int64_t)gridDim.x * 256) {
+    __shared__ float s_end[6][256];              // ends of the tile's segments with crossings
+    // A thread's loads for its segment of a tile, in two steps so that they
+    // overlap the previous tile's work: first the crossing count, then (with
+    // the count known) the slot positions and the segment ends.
+    struct Pre {
+        int32_t n;  // crossings; -2: no segment
+        int32_t pos[kRegSlots];
+        float e[6];
+    };
+    auto fetch_count = [&](int64_t base, Pre &f) {
         const int64_t k = base + tid;
-        int32_t n = -1;
-        int32_t *ids = nullptr;
-        float *ts = nullptr;
+        f.n = -2;
         if (k < a.n_items) {
             const ItemView<BATCH> v = item_view<BATCH>(a, k);
-            const int32_t m = BATCH ? mesh_of(a.bt.seg_off, a.M, k) : 0;
-            const int32_t *cnt = BATCH ? a.bt.count[m] : a.o.count;
-            int64_t *soff = BATCH ? a.bt.spill_off[m] : a.o.spill_off;
-            n = cnt[v.i];
-            if (n <= K) {
-                ids = v.ids + v.i * (int64_t)K;
-                ts = v.ts + v.i * (int64_t)K;
-                if (soff) st_nt(soff + v.i, (int64_t)-1);
-            } else {
-                n = -1;  // overflowed: k_spill_finish fills the slots
-            }
+            const int32_t *cnt = BATCH ? a.bt.count[mesh_of(a.bt.seg_off, a.M, k)] : a.o.count;
+            f.n = cnt[v.i];
         }
+    };
+    auto fetch_rest = [&](int64_t base, Pre &f) {
+        const int64_t k = base + tid;
+        if (f.n > 0 && f.n <= K) {
+            const ItemView<BATCH> v = item_view<BATCH>(a, k);
+            const int32_t *ids = v.ids + v.i * (int64_t)K;
+#pragma unroll
+            for (int c = 0; c < kRegSlots; ++c) f.pos[c] = c < f.n ? ids[c] : -1;
+            item_ends<BATCH>(a, k, f.e[0], f.e[1], f.e[2], f.e[3], f.e[4], f.e[5]);
+        }
+    };
+    const int64_t gstride = (int64_t)gridDim.x * 256;
+    Pre cur;
+    fetch_count((int64_t)blockIdx.x * 256, cur);
+    fetch_rest((int64_t)blockIdx.x * 256, cur);
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < a.n_items; base += gstride) {
+        Pre nxt;
+        fetch_count(base + gstride, nxt);
+        // overflowed segments (more than K crossings) are k_spill_finish's
+        const int32_t n = cur.n <= K ? cur.n : -1;
         // pack the tile's (segment, slot) pairs
         int32_t total;
         const int32_t q = block_prefix256(n > 0 ? n : 0, sh, total);
-        for (int c = 0; c < n; ++c) {
-            q_pair[q + c] = (tid << 2) | c;
-            q_pos[q + c] = ids[c];
+#pragma unroll
+        for (int c = 0; c < kRegSlots; ++c) {
+            if (c < n) {
+                q_pair[q + c] = (tid << 2) | c;
+                r_id[tid * kRegSlots + c] = cur.pos[c];
+            }
+        }
+        if (n > 0) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) s_end[d][tid] = cur.e[d];
         }
         __syncthreads();
+        fetch_rest(base + gstride, nxt);
+#pragma unroll 1
         for (int j = tid; j < total; j += 256) {
             const int lt = q_pair[j] >> 2, c = q_pair[j] & 3;
-            const int32_t pos = q_pos[j];
+            const int32_t pos = r_id[lt * kRegSlots + c];
             int32_t id = 0x7FFFFFFF;
             float t = INFINITY;
             if (pos >= 0 && pos < a.n_tris) {  // an entry no walk wrote is never read through
-                float sx, sy, sz, ex, ey, ez;
-                item_ends<BATCH>(a, base + lt, sx, sy, sz, ex, ey, ez);
                 float w[9];
                 tri_load(a.tris, pos, w, id);
                 double tt, u, ww;
-                mt_refine64(sx, sy, sz, ex, ey, ez, w, tt, u, ww);
+                mt_refine64(s_end[0][lt], s_end[1][lt], s_end[2][lt], s_end[3][lt], s_end[4][lt], s_end[5][lt], w,
+                            tt, u, ww);
                 t = (float)tt;
             }
             r_id[lt * kRegSlots + c] = id;
@@ -1415,6 +1539,12 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
         }
         __syncthreads();
         if (n >= 0) {
+            const int64_t k = base + tid;
+            const ItemView<BATCH> v = item_view<BATCH>(a, k);
+            int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, k)] : a.o.spill_off;
+            if (soff) st_nt(soff + v.i, (int64_t)-1);
+            int32_t *ids = v.ids + v.i * (int64_t)K;
+            float *ts = v.ts + v.i * (int64_t)K;
             int32_t id[kRegSlots];
             float t[kRegSlots];
 #pragma unroll
@@ -1454,6 +1584,62 @@ __global__ __launch_bounds__(256) void k_refine_slots(QArgs a)
             }
         }
         __syncthreads();
+        cur = nxt;
+    }
+}
+
+// The same for K > 4: a segment per lane, its slots in order.
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_refine_slots_long(QArgs a)
+{
+    const int K = a.o.cap;
+    const int tid = threadIdx.x;
+    // a segment per lane, its slots in order
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + tid; k < a.n_items; k += stride) {
+        const ItemView<BATCH> v = item_view<BATCH>(a, k);
+        const int32_t *cnt = BATCH ? a.bt.count[mesh_of(a.bt.seg_off, a.M, k)] : a.o.count;
+        int64_t *soff = BATCH ? a.bt.spill_off[mesh_of(a.bt.seg_off, a.M, k)] : a.o.spill_off;
+        const int32_t n = cnt[v.i];
+        if (n > K) continue;
+        if (soff) st_nt(soff + v.i, (int64_t)-1);
+        int32_t *ids = v.ids + v.i * (int64_t)K;
+        float *ts = v.ts + v.i * (int64_t)K;
+        if (n > 0) {
+            float sx, sy, sz, ex, ey, ez;
+            item_ends<BATCH>(a, k, sx, sy, sz, ex, ey, ez);
+            for (int c = 0; c < n; ++c) {
+                const int32_t pos = ids[c];
+                if (pos < 0 || pos >= a.n_tris) {
+                    ids[c] = 0x7FFFFFFF;
+                    ts[c] = INFINITY;
+                    continue;
+                }
+                float w[9];
+                int32_t tid3;
+                tri_load(a.tris, pos, w, tid3);
+                double tt, u, ww;
+                mt_refine64(sx, sy, sz, ex, ey, ez, w, tt, u, ww);
+                ids[c] = tid3;
+                ts[c] = (float)tt;
+            }
+            for (int x = 1; x < n; ++x) {  // insertion sort by (t, id): lists are short
+                const float kt = ts[x];
+                const int32_t ki = ids[x];
+                int y = x - 1;
+                while (y >= 0 && (ts[y] > kt || (ts[y] == kt && ids[y] > ki))) {
+                    ts[y + 1] = ts[y];
+                    ids[y + 1] = ids[y];
+                    --y;
+                }
+                ts[y + 1] = kt;
+                ids[y + 1] = ki;
+            }
+        }
+        for (int c = n; c < K; ++c) {
+            ids[c] = -1;
+            ts[c] = INFINITY;
+        }
     }
 }
 
@@ -1747,6 +1933,7 @@ QArgs make_args(rsi_bvh *h, const float *S, const float *E, int64_t n_items, con
     a.arena = h->arena;
     a.arena_cap = h->arena_cap;
     a.ovf_part = h->ovf_part;
+    a.ovf_list = h->ovf_list;
     a.scalars = h->scalars;
     a.counters = h->counters;
     a.depth = 0;
@@ -1781,14 +1968,24 @@ hipError_t launch_all_hits_tail(const QArgs &a, bool batch, hipStream_t s)
 {
     const int64_t blocks = (a.n_items + 255) / 256;
     const unsigned rgrid = (unsigned)(blocks < 8192 ? blocks : 8192);
-    if (batch) hipLaunchKernelGGL(k_refine_slots<true>, dim3(rgrid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_refine_slots<false>, dim3(rgrid), dim3(256), 0, s, a);
+    if (a.o.cap > kRegSlots) {
+        if (batch) hipLaunchKernelGGL(k_refine_slots_long<true>, dim3(rgrid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_refine_slots_long<false>, dim3(rgrid), dim3(256), 0, s, a);
+    } else if (batch) {
+        hipLaunchKernelGGL(k_refine_slots<true>, dim3(rgrid), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_refine_slots<false>, dim3(rgrid), dim3(256), 0, s, a);
+    }
     hipLaunchKernelGGL(k_ovf_sums, dim3(kOvfParts), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_ovf_scan_parts, dim3(1), dim3(kOvfParts), 0, s, a);
     if (batch) hipLaunchKernelGGL(k_ovf_offsets<true>, dim3(kOvfParts), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_ovf_offsets<false>, dim3(kOvfParts), dim3(256), 0, s, a);
     const unsigned grid = (unsigned)(2 * device_cus());
-    hipLaunchKernelGGL(k_spill_place, dim3(grid), dim3(256), 0, s, a);
+    // one crossing per thread: enough workgroups that the usual few hundred
+    // thousand take one round
+    const unsigned pgrid = (unsigned)(8 * device_cus());
+    if (batch) hipLaunchKernelGGL(k_spill_place<true>, dim3(pgrid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_spill_place<false>, dim3(pgrid), dim3(256), 0, s, a);
     if (batch) hipLaunchKernelGGL(k_spill_finish<true>, dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_spill_finish<false>, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -1911,12 +2108,13 @@ hipError_t ensure_query_memory(rsi_bvh *h, int64_t n, bool all_hits)
         // to the deep pass leave void, plus the void block tails
         const int64_t want = n + n / 8 + (int64_t)(kEntBlock - 1) * waves + 1024;
         if (h->ovf_cap < want) {
-            // the three arrays share one capacity: it holds only once all grew
-            int64_t c0 = 0, c1 = 0, c2 = 0;
+            // the four arrays share one capacity: it holds only once all grew
+            int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
             h->ovf_cap = 0;
             grow(&h->ovf_seg, c0, want, sizeof(int32_t));
             grow(&h->ovf_cnt, c1, want, sizeof(int32_t));
             grow(&h->ovf_off, c2, want, sizeof(int64_t));
+            grow(&h->ovf_list, c3, want, sizeof(int32_t));
             if (e == hipSuccess) h->ovf_cap = want;
         }
         const int64_t arena_want = (h->pool_want > (n / 4 > (1 << 20) ? n / 4 : (1 << 20)) ? h->pool_want

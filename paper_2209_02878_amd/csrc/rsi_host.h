@@ -31,6 +31,7 @@ enum Scalar {
     kOvfFull = 26,     // the overflow table, arena or pool was too small: lists incomplete
     kOvfUsed = 27,     // all hits: overflow-table entries in use (segments with more crossings than slots)
     kArenaUsed = 28,   // all hits: arena records placed into the pool (crossings past the slots)
+    kOvfValid = 29,    // all hits: overflow-table entries that are not void (listed in table order)
     kNumScalars = 32
 };
 
@@ -119,6 +120,7 @@ struct rsi_bvh {
     // the library's pool of full lists (used when the caller passes none)
     int32_t *ovf_seg = nullptr;
     int32_t *ovf_cnt = nullptr;
+    int32_t *ovf_list = nullptr;  // the entries that are not void, in table order
     int64_t *ovf_off = nullptr;
     int64_t ovf_cap = 0;
     int4 *arena = nullptr;

@@ -167,6 +167,52 @@ def test_closed_sphere_all_hits_overflow():
     assert np.all(out["count"].cpu().numpy()[outside] % 2 == 0)
 
 
+def _stacked_layers(layers):
+    """Columns of parallel unit squares (two triangles each) stacked in z:
+    column c holds layers[c] squares at z = (k + 0.5) / layers[c]."""
+    V, T = [], []
+    n = len(layers)
+    for c, L in enumerate(layers):
+        x0, x1 = c / n + 0.01, (c + 1) / n - 0.01
+        for k in range(L):
+            z = (k + 0.5) / L
+            b = len(V)
+            V += [[x0, 0.0, z], [x1, 0.0, z], [x1, 1.0, z], [x0, 1.0, z]]
+            T += [[b, b + 1, b + 2], [b, b + 2, b + 3]]
+    return np.array(V, np.float32), np.array(T, np.int32)
+
+
+def test_long_overflow_lists_in_order():
+    """Near-vertical segments through columns of 5, 12, 40, 300 and 1,100
+    stacked layers: every segment overflows its 4 slots with that many
+    crossings, which covers each way the spilled lists are ordered (in
+    registers up to 16, ranked by a wave through LDS up to 1,024, by one
+    thread beyond).  Every list must be the oracle's, in (t, id) order, and
+    the slots its first four."""
+    layers = [5, 12, 40, 300, 1100]
+    V, T = _stacked_layers(layers)
+    rng = np.random.default_rng(11)
+    per = 150
+    col = np.repeat(np.arange(len(layers)), per)
+    x = (col + 0.1 + 0.8 * rng.uniform(size=col.size)) / len(layers)
+    y = 0.05 + 0.9 * rng.uniform(size=col.size)
+    S = np.stack([x, y, np.full_like(x, -0.05)], 1).astype(np.float32)
+    E = np.stack([x + 0.002 * rng.standard_normal(x.size), y + 0.002 * rng.standard_normal(x.size),
+                  np.full_like(x, 1.05)], 1).astype(np.float32)
+    ref = parity.oracle_reference(V, T, S, E, cap=4)
+    assert np.array_equal(ref["count"], np.repeat(layers, per))
+    mesh = _mesh(V, T)
+    out = _run(mesh, S, E, "all|first", cap=4)
+    sp = out.get("spill")
+    assert sp is not None and sp["seg"].numel() == S.shape[0]
+    ref["full_lists"] = _full_lists(V, T, S, E, np.arange(S.shape[0]), cap=1200)
+    rep = parity.compare(ref, out, {"all", "first"}, cap=4, spill=sp)
+    print(rep)
+    assert rep["spill_checked"] == int((ref["degenerate"] == 0).sum()) > 700
+    parity.assert_parity(rep)
+    mesh.close()
+
+
 # ------------------------------------------------------------------ edges ---
 
 def test_edge_cases():
