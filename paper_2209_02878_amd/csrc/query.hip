@@ -204,7 +204,14 @@ __device__ inline void load_top(const Node4 *__restrict__ nodes4, int32_t entry,
 // at a few thousand per launch they already cost more than the walk's tests.
 constexpr int32_t kEntBlock = 64;
 constexpr int32_t kArenaBlock = 64;
-constexpr int kWavesPerBlock = 4;  // the kernels' launch bound: 256 threads
+constexpr int kXcds = 8;            // MI355X: 8 XCDs of 32 CUs, each with its own L2
+constexpr int kWavesPerBlock = 4;
+
+// The XCD the calling wave runs on: hardware register XCC_ID, bits 3:0.
+__device__ inline int xcd_id()
+{
+    return (int)(__builtin_amdgcn_s_getreg(((4 - 1) << 11) | (0 << 6) | 20) & (kXcds - 1));
+}  // the kernels' launch bound: 256 threads
 
 // Per-lane query state for the segment it currently owns.
 // All-hits capacities up to this many keep the hit list in registers.
@@ -607,7 +614,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
     }
     int32_t *const stk = lds_stack + threadIdx.x;
     const int stride = blockDim.x;
-    int32_t *const work = &a.scalars[RETRY ? kWorkRetry : kWorkNext];
+    // work claiming: the main pass's items are cut into eight contiguous
+    // ranges, one per XCD, each with its own counter on its own 128-byte
+    // line; a wave takes chunks from its XCD's range first, then from the
+    // others in turn.  A single counter line shared by all XCDs serialises
+    // the claims in the memory fabric (measured: 0.83 against 0.69 ms for
+    // the 10M-segment boolean query); with the ranges each XCD also walks
+    // its own part of spatially ordered items.  The deep pass has one range.
+    constexpr int kRanges = RETRY ? 1 : kXcds;
+    int32_t *const work = &a.scalars[RETRY ? kWorkRetry : kWorkXcd];
+    int range = RETRY ? 0 : xcd_id();  // wave-uniform
+    int ranges_left = kRanges;
     // stack entry k >= lds_depth lives at gstack[(k - lds_depth) * gstride + gtid]
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -689,19 +706,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
             chunk_next += used;
             if (used < n_idle && !exhausted) {
                 const int leader = __builtin_ctzll(idle);
-                int32_t base = 0;
-                if ((int)__lane_id() == leader) base = atomicAdd(work, a.chunk);
-                base = __shfl(base, leader, 64);
-                if (base >= n_items) {
-                    exhausted = true;
-                } else {
-                    chunk_next = __builtin_amdgcn_readfirstlane(base);
-                    chunk_end = base + a.chunk < n_items ? base + a.chunk : n_items;
-                    chunk_end = __builtin_amdgcn_readfirstlane(chunk_end);
-                    const int32_t room = chunk_end - chunk_next;
-                    const int32_t more = n_idle - used < room ? n_idle - used : room;
-                    if (rank >= used && rank - used < more) k = chunk_next + (rank - used);
-                    chunk_next += more;
+                for (;;) {
+                    const int32_t lo = (int32_t)((int64_t)n_items * range / kRanges);
+                    const int32_t hi = (int32_t)((int64_t)n_items * (range + 1) / kRanges);
+                    int32_t base = 0;
+                    if ((int)__lane_id() == leader) base = atomicAdd(work + kWorkStride * range, a.chunk);
+                    base = __builtin_amdgcn_readfirstlane(__shfl(base, leader, 64));
+                    if (base < hi - lo) {
+                        chunk_next = lo + base;
+                        chunk_end = hi - chunk_next > a.chunk ? chunk_next + a.chunk : hi;
+                        const int32_t room = chunk_end - chunk_next;
+                        const int32_t more = n_idle - used < room ? n_idle - used : room;
+                        if (rank >= used && rank - used < more) k = chunk_next + (rank - used);
+                        chunk_next += more;
+                        break;
+                    }
+                    // this range is used up: the next one
+                    if (--ranges_left == 0) {
+                        exhausted = true;
+                        break;
+                    }
+                    range = range + 1 == kRanges ? 0 : range + 1;
                 }
             }
             if (item == -1) {
@@ -1698,8 +1723,9 @@ __global__ void k_parity(const int32_t *__restrict__ count, int64_t n, uint8_t *
 // so they describe every part.
 __global__ void k_reset(int32_t *scalars, Counters *c, int keep)
 {
-    const int32_t zero[] = {kWorkNext, kWorkRetry, kRetryN, kOvfSegs, kOvfTotalLo, kOvfTotalHi, kArenaLo,
-                            kArenaHi, kOvfFull, kOvfUsed, kArenaUsed, kRetryLost, kStackDropped, kWalkCut};
+    const int32_t zero[] = {kWorkRetry, kRetryN,  kOvfSegs, kOvfTotalLo, kOvfTotalHi,   kArenaLo, kArenaHi,
+                            kOvfFull,   kOvfUsed, kArenaUsed, kRetryLost, kStackDropped, kWalkCut};
+    for (int r = 0; r < kXcds; ++r) scalars[kWorkXcd + kWorkStride * r] = 0;
     const int n = (int)(sizeof(zero) / sizeof(zero[0])) - (keep ? 3 : 0);
     for (int k = 0; k < n; ++k) scalars[zero[k]] = 0;
     if (c && !keep) {

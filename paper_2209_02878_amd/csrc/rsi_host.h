@@ -19,7 +19,6 @@ enum Scalar {
     kOvfSegs = 9,      // all hits: overflow-table entries handed out (in blocks; unused ones are void)
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments: pool entries reserved (lo, hi words)
     kOvfTotalHi = 11,
-    kWorkNext = 12,    // next unclaimed work item of the running main query pass
     kWalkCut = 13,     // walks stopped by the node-visit bound (damaged tree)
     kArenaLo = 14,     // 64-bit count of arena records handed out during the walk, in blocks (lo, hi words)
     kArenaHi = 15,
@@ -32,7 +31,10 @@ enum Scalar {
     kOvfUsed = 27,     // all hits: overflow-table entries in use (segments with more crossings than slots)
     kArenaUsed = 28,   // all hits: arena records placed into the pool (crossings past the slots)
     kOvfValid = 29,    // all hits: overflow-table entries that are not void (listed in table order)
-    kNumScalars = 32
+    kWorkXcd = 32,     // 8 counters, kWorkStride ints (128 bytes) apart: items claimed from each
+                       // eighth of the main query pass's items
+    kWorkStride = 32,
+    kNumScalars = kWorkXcd + 8 * kWorkStride
 };
 
 struct Counters {
