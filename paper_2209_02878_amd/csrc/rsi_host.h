@@ -16,12 +16,9 @@ namespace rsi {
 enum Scalar {
     kBadIndex = 6,     // nonzero if a triangle index was out of range (1) or the build state was inconsistent (2)
     kBadGather = 7,    // nonzero if a batch gather met a triangle index outside its mesh
-    kOvfSegs = 9,      // all hits: overflow-table entries handed out (in blocks; unused ones are void)
     kOvfTotalLo = 10,  // 64-bit total crossings of those segments: pool entries reserved (lo, hi words)
     kOvfTotalHi = 11,
     kWalkCut = 13,     // walks stopped by the node-visit bound (damaged tree)
-    kArenaLo = 14,     // 64-bit count of arena records handed out during the walk, in blocks (lo, hi words)
-    kArenaHi = 15,
     kSegBounds = 16,   // 6 ordered ints: bounding box of segment midpoints (segment order)
     kRetryN = 22,      // segments whose stack outgrew its LDS part, queued for the deep pass
     kWorkRetry = 23,   // next unclaimed item of the deep pass
@@ -34,7 +31,12 @@ enum Scalar {
     kWorkXcd = 32,     // 8 counters, kWorkStride ints (128 bytes) apart: items claimed from each
                        // eighth of the main query pass's items
     kWorkStride = 32,
-    kNumScalars = kWorkXcd + 8 * kWorkStride
+    // the all-hits block counters, each on its own 128-byte line (waves claim
+    // blocks from them throughout the walk)
+    kOvfSegs = kWorkXcd + 8 * kWorkStride,  // overflow-table entries handed out (in blocks; unused ones are void)
+    kArenaLo = kOvfSegs + kWorkStride,      // 64-bit count of arena records handed out during the walk, in
+    kArenaHi = kArenaLo + 1,                // blocks (lo, hi words)
+    kNumScalars = kArenaLo + kWorkStride
 };
 
 struct Counters {
