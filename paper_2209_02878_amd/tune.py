@@ -25,7 +25,7 @@ STAGES = [
     [{"branching": w, "block_size": b} for w in (2, 4) for b in (64, 128, 256)],
     # LDS stack entries per lane of the main pass (deeper walks go to the deep pass)
     [{"stack_depth": s} for s in (8, 12, 16, 20, 24, 32)],
-    [{"defer_lanes": d, "refill_lanes": r} for d in (16, 32, 48) for r in (16, 32, 48)],
+    [{"defer_lanes": d, "refill_lanes": r} for d in (16, 32, 48) for r in (16, 24, 32, 48)],
     [{"leaf_size": leaf} for leaf in (1, 2, 4)],
 ]
 
