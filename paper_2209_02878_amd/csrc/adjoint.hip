@@ -23,7 +23,7 @@
 //                 10): the pairs of each cell of 1,024 consecutive
 //                 triangles become contiguous, in input order within a cell
 //   k_adj_tri     four workgroups per cell, each taking a quarter of the
-//                 cell's pairs in order: tiles of 1,024 pairs are ranked
+//                 cell's pairs in order: tiles of 512 pairs are ranked
 //                 stably by (cell triangle mod 256) in LDS, and thread t adds
 //                 the records of its four triangles (t + 256 j) in that order,
 //                 in FP64, to nine running sums per triangle (three corners x
@@ -51,7 +51,7 @@ constexpr int kCellBits = 10;                    // triangles per cell: 1,024
 constexpr int kCellTris = 1 << kCellBits;
 constexpr int kTriPerThread = kCellTris / kThreads;  // 4: thread t owns cell triangles t + 256 j
 constexpr int kChunks = 4;                       // k_adj_tri workgroups per cell (each a quarter of its pairs)
-constexpr int kTriItems = 4;                     // pairs per thread per tile of k_adj_tri
+constexpr int kTriItems = 2;                     // pairs per thread per tile of k_adj_tri
 constexpr int kTriTile = kThreads * kTriItems;
 
 struct AdjArgs {

@@ -20,7 +20,7 @@ import numpy as np
 import oracle
 from paper_2209_02878_amd import workloads as wl
 
-CELL_BITS, TILE, CHUNKS = 10, 1024, 4
+CELL_BITS, TILE, CHUNKS = 10, 512, 4
 
 
 def _model(V, T, S, E, tri, g_p, rank, corner0="fp64"):
