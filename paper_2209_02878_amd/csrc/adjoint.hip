@@ -60,6 +60,7 @@ struct AdjArgs {
     const int32_t *T;
     int64_t n_t;
     const int32_t *rank;  // sorted (Morton) position of each triangle
+    const Tri *tris;      // the tree's triangle records (vertices of the last build or refit), sorted
     const float *S;
     const float *E;
     int64_t n_r;
@@ -99,14 +100,19 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
     float2 rv = make_float2(0.0f, 0.0f);
     uint64_t key = (uint64_t)a.n_t;
     const int32_t j = a.tri[i];
-    if (j >= 0 && j < a.n_t) {
-        const int32_t ia = a.T[3 * (int64_t)j], ib = a.T[3 * (int64_t)j + 1], ic = a.T[3 * (int64_t)j + 2];
-        if (ia >= 0 && ia < a.n_v && ib >= 0 && ib < a.n_v && ic >= 0 && ic < a.n_v) {
+    // the hit triangle's vertices from its record in the tree (copied from
+    // V at the last build or refit, which is the V this call is given): one
+    // gather of 48 contiguous bytes at its sorted position instead of an
+    // index row and three vertex rows
+    const int32_t pos = (j >= 0 && j < a.n_t) ? a.rank[j] : -1;
+    if (pos >= 0 && pos < a.n_t) {
+        const float4 ta = a.tris[pos].a, tb4 = a.tris[pos].b, tc = a.tris[pos].c;
+        if (tc.w == 0.0f) {
             const d3 s = mk(a.S[3 * i], a.S[3 * i + 1], a.S[3 * i + 2]);
             const d3 e = mk(a.E[3 * i], a.E[3 * i + 1], a.E[3 * i + 2]);
-            const d3 v0 = mk(a.V[3 * ia], a.V[3 * ia + 1], a.V[3 * ia + 2]);
-            const d3 v1 = mk(a.V[3 * ib], a.V[3 * ib + 1], a.V[3 * ib + 2]);
-            const d3 v2 = mk(a.V[3 * ic], a.V[3 * ic + 1], a.V[3 * ic + 2]);
+            const d3 v0 = mk(ta.x, ta.y, ta.z);
+            const d3 v1 = mk(ta.w, tb4.x, tb4.y);
+            const d3 v2 = mk(tb4.z, tb4.w, tc.x);
             const d3 d = sub(e, s), e1 = sub(v1, v0), e2 = sub(v2, v0), q = sub(s, v0);
             const d3 md = {-d.x, -d.y, -d.z};
             // forward values by Cramer's rule on the columns of M
@@ -139,7 +145,7 @@ __global__ __launch_bounds__(256) void k_adj_solve(AdjArgs a)
                 // would lose its relative accuracy near the edge v1 v2
                 r = make_float4((float)lam.x, (float)lam.y, (float)lam.z, (float)(1.0 - u - v));
                 rv = make_float2((float)u, (float)v);
-                key = (uint64_t)a.rank[j];
+                key = (uint64_t)pos;
             }
         }
     }
@@ -348,6 +354,7 @@ hipError_t launch_first_hit_adjoint(rsi_bvh *h, const float *V, const float *S, 
     a.T = h->T;
     a.n_t = h->n_t;
     a.rank = h->rank;
+    a.tris = h->tris;
     a.S = S;
     a.E = E;
     a.n_r = n_r;

@@ -340,7 +340,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
         a.rank[id] = i;
         int32_t va = a.T[3 * id], vb = a.T[3 * id + 1], vd = a.T[3 * id + 2];
         // an out-of-range index is reported by k_centroids; read vertex 0
-        // instead so that no access leaves the vertex array
+        // instead so that no access leaves the vertex array, and mark the
+        // record (the adjoint skips it)
+        const bool bad = va < 0 || va >= a.n_v || vb < 0 || vb >= a.n_v || vd < 0 || vd >= a.n_v;
         if (va < 0 || va >= a.n_v) va = 0;
         if (vb < 0 || vb >= a.n_v) vb = 0;
         if (vd < 0 || vd >= a.n_v) vd = 0;
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_lbvh_local(BuildArgs a)
         Tri tr;
         tr.a = make_float4(v0x, v0y, v0z, v1x);
         tr.b = make_float4(v1y, v1z, v2x, v2y);
-        tr.c = make_float4(v2z, __int_as_float(id - lo), 0.0f, 0.0f);  // id within its mesh
+        tr.c = make_float4(v2z, __int_as_float(id - lo), 0.0f, bad ? 1.0f : 0.0f);  // id within its mesh
         a.tris[i] = tr;
         c.box[0] = fminf(v0x, fminf(v1x, v2x));
         c.box[1] = fminf(v0y, fminf(v1y, v2y));

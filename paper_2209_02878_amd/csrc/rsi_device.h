@@ -65,7 +65,7 @@ static_assert(sizeof(Node4) == 64, "Node4 must be 64 bytes");
 struct alignas(16) Tri {
     float4 a;  // v0.x v0.y v0.z v1.x
     float4 b;  // v1.y v1.z v2.x v2.y
-    float4 c;  // v2.z, id (int bits), 0, 0
+    float4 c;  // v2.z, id (int bits), 0, 1 when a vertex index was out of range (else 0)
 };
 static_assert(sizeof(Tri) == 48, "Tri must be 48 bytes");
 
