@@ -629,7 +629,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
     const int64_t gstride = (int64_t)gridDim.x * blockDim.x;
     const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
-    Lane L;
+    // a lane's state starts defined: the leaf phase reads any lane's segment
+    // and t limit with shuffles, including lanes that never take an item
+    Lane L = {};
+    L.tlim = 1.0f;
     L.retry = false;
     L.e = -1;
     // all hits: the wave's blocks of overflow-table entries and arena
