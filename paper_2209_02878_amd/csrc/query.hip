@@ -604,6 +604,9 @@ template <uint32_t MODE, bool RETRY, bool COUNT, bool BATCH, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_ALL) ? 6 : 1))) void k_query(QArgs a)
 {
     constexpr bool HYB = RETRY;
+    // the deep pass is launched after every main pass; with nothing queued
+    // (the usual case) every workgroup leaves before touching memory
+    if (RETRY && a.scalars[kRetryN] == 0) return;
     extern __shared__ int32_t lds_dyn[];
     int32_t *const lds_stack = lds_dyn;
     constexpr bool TOP = WIDE && !BATCH && top_copy(MODE);
