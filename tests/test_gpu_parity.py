@@ -296,6 +296,38 @@ def test_ragged_sizes_and_options():
         mesh.close()
 
 
+def test_multi_triangle_leaves_in_every_gathered_mode():
+    """Leaves of 2 to 16 triangles in the modes whose leaf tests are gathered
+    across the wave (first hit, count, boolean with first hit): a tested
+    leaf reports a mask of crossed triangles and its best crossing, which
+    must give the oracle's answers and exactly the answers of one-triangle
+    leaves."""
+    V, T = wl.noisy_sphere(12, 6, 0.3)
+    rng = np.random.default_rng(21)
+    S, E = wl.segments_in_box(rng, V.min(0), V.max(0), 40_000, scale=1.5)
+    ref = parity.oracle_reference(V, T, S, E)
+    for mode, keys in (("first", ("tri", "t", "uv", "point")), ("count", ("count",)),
+                       ("bool|first", ("hit", "tri", "t"))):
+        base = None
+        for leaf in (1, 2, 8, 16):
+            mesh = _mesh(V, T, leaf_size=leaf)
+            out = _run(mesh, S, E, mode)
+            mesh.close()
+            if base is None:
+                base = {k: out[k].cpu() for k in keys}
+                modes = {"first"} if "first" in mode else set()
+                if mode == "count":
+                    got = out["count"].cpu().numpy()
+                    ok = ref["degenerate"] == 0
+                    assert np.array_equal(got[ok], ref["count"][ok]), mode
+                else:
+                    rep = parity.compare(ref, out, modes | ({"bool"} if "bool" in mode else set()))
+                    parity.assert_parity(rep)
+            else:
+                for k in keys:
+                    assert torch.equal(base[k], out[k].cpu()), (mode, leaf, k)
+
+
 def test_deterministic_repeat():
     w = wl.config1(n_r=50_000)
     mesh = _mesh(w.V, w.T)
