@@ -49,3 +49,25 @@ def test_counters_account_for_every_lane(branching, mode):
     assert c["wave_leaf_rounds"] <= c["leaf_lanes"] <= 64 * c["wave_leaf_rounds"]
     assert c["leaf_lanes"] <= c["tri_tests"]
     mesh.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 63, 65, 257, 1001])
+def test_every_segment_claimed_once_at_small_sizes(n):
+    """Work items are claimed from eight ranges (one per XCD, some empty at
+    these sizes) and stolen across them: every segment must be walked once,
+    and the answers must be the oracle's."""
+    from tests import parity
+    w = wl.config1(n_r=max(n, 16))
+    S, E = w.S[:n], w.E[:n]
+    V, T = _t(w.V), _t(w.T, torch.int32)
+    mesh = rsi.Mesh(V, T)
+    mesh.set_counting(True)
+    out = mesh.query(_t(S), _t(E), "bool|count")
+    torch.cuda.synchronize()
+    c = mesh.counters()
+    mesh.close()
+    assert c["segments"] == n
+    ref = parity.oracle_reference(w.V, w.T, S, E)
+    ok = ref["degenerate"] == 0
+    assert np.array_equal(out["count"].cpu().numpy()[ok], ref["count"][ok])
+    assert np.array_equal(out["hit"].cpu().numpy()[ok].astype(bool), ref["count"][ok] > 0)
