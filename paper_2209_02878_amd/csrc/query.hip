@@ -205,13 +205,14 @@ __device__ inline void load_top(const Node4 *__restrict__ nodes4, int32_t entry,
 constexpr int32_t kEntBlock = 64;
 constexpr int32_t kArenaBlock = 64;
 constexpr int kXcds = 8;            // MI355X: 8 XCDs of 32 CUs, each with its own L2
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 4;   // the kernels' launch bound: 256 threads
 
-// The XCD the calling wave runs on: hardware register XCC_ID, bits 3:0.
+// The XCD the calling wave runs on: hardware register XCC_ID, bits 3:0
+// (s_getreg encoding: size - 1 in bits 15:11, offset in 10:6, register 20).
 __device__ inline int xcd_id()
 {
     return (int)(__builtin_amdgcn_s_getreg(((4 - 1) << 11) | (0 << 6) | 20) & (kXcds - 1));
-}  // the kernels' launch bound: 256 threads
+}
 
 // Per-lane query state for the segment it currently owns.
 // All-hits capacities up to this many keep the hit list in registers.
