@@ -296,6 +296,43 @@ def test_ragged_sizes_and_options():
         mesh.close()
 
 
+@pytest.mark.parametrize("cap", [5, 16])
+def test_more_than_four_slots_with_and_without_overflow(cap):
+    """Capacities above four keep the slots in device memory and re-solve
+    them one segment per lane; on the stacked layers (5, 12, 40, 300 and
+    1,100 crossings per segment) some lists fit their slots, some fill them
+    exactly and the rest overflow, with the first `cap` crossings moved to
+    the head of each pooled list."""
+    layers = [5, 12, 16, 40, 300, 1100]
+    V, T = _stacked_layers(layers)
+    rng = np.random.default_rng(12)
+    per = 60
+    col = np.repeat(np.arange(len(layers)), per)
+    x = (col + 0.1 + 0.8 * rng.uniform(size=col.size)) / len(layers)
+    y = 0.05 + 0.9 * rng.uniform(size=col.size)
+    S = np.stack([x, y, np.full_like(x, -0.05)], 1).astype(np.float32)
+    E = np.stack([x + 0.002 * rng.standard_normal(x.size), y + 0.002 * rng.standard_normal(x.size),
+                  np.full_like(x, 1.05)], 1).astype(np.float32)
+    ref = parity.oracle_reference(V, T, S, E, cap=cap)
+    mesh = _mesh(V, T)
+    out = _run(mesh, S, E, "all|first", cap=cap)
+    sp = out.get("spill")
+    over = np.nonzero(ref["count"] > cap)[0]
+    assert sp is not None and sp["seg"].numel() == over.size
+    ref["full_lists"] = _full_lists(V, T, S, E, np.sort(sp["seg"].cpu().numpy()), cap=1200)
+    rep = parity.compare(ref, out, {"all", "first"}, cap=cap, spill=sp)
+    print(rep)
+    assert rep["spill_checked"] == int((ref["degenerate"][over] == 0).sum())
+    parity.assert_parity(rep)
+    # slots past a short list are empty
+    cnt = out["count"].cpu().numpy()
+    ids = out["ids"].cpu().numpy()
+    short = np.nonzero(cnt < cap)[0]
+    for i in short[:50]:
+        assert np.all(ids[i, cnt[i]:] == -1)
+    mesh.close()
+
+
 def test_multi_triangle_leaves_in_every_gathered_mode():
     """Leaves of 2 to 16 triangles in the modes whose leaf tests are gathered
     across the wave (first hit, count, boolean with first hit): a tested
