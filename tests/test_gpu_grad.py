@@ -43,8 +43,8 @@ def _check_seg(g_gpu, g_ref, rel=1e-5):
 
 @pytest.mark.parametrize("n_half", [30_000, 120_000])
 def test_adjoint_matches_oracle_random_upstream(n_half):
-    """60k segments take the direct kernel; 240k (over 4 per triangle) take
-    the hit-ordered kernel with per-run sums."""
+    """60k and 240k segments (about one and four per triangle: cells with
+    few and with many records each)."""
     V, T = wl.noise_heightfield(60, 17, 0.2)
     rng = np.random.default_rng(3)
     S1, E1 = wl.segments_near_vertical(rng, n_half)
@@ -220,3 +220,30 @@ def test_c4_fwd_bwd_against_oracle_and_finite_differences():
         assert abs(gpu - fd) <= 1e-5 * abs_k[k, 2] + 1e-9, (int(k), gpu, fd, abs_k[k, 2])
         n_checked += 1
     assert n_checked >= 60
+
+
+def test_gradient_bits_independent_of_tree_options():
+    """The backward reads the hit triangles' records by sorted position and
+    sums in a fixed order over cells of sorted positions, so the leaf size
+    and the walk (binary or four-way) that produced the same first hits
+    must give the same dV, dS and dE bits."""
+    V, T = wl.noise_heightfield(60, 17, 0.2)
+    rng = np.random.default_rng(9)
+    S, E = wl.segments_near_vertical(rng, 100_000)
+    Vt, Tt, St, Et = _t(V), _t(T, torch.int32), _t(S), _t(E)
+    g = torch.zeros(S.shape[0], 3, device=DEV)
+    g[:, 2] = 1.0
+    base = None
+    for leaf, branching in ((1, 4), (4, 4), (1, 2), (8, 2)):
+        mesh = rsi.Mesh(Vt, Tt, leaf_size=leaf, branching=branching)
+        out = mesh.query(St, Et, "first")
+        dV, dS, dE = rsi.rsi_first_hit_backward(mesh.handle, Vt, St, Et, out["tri"], None, None, g)
+        torch.cuda.synchronize()
+        got = (out["tri"].cpu(), dV.cpu(), dS.cpu(), dE.cpu())
+        mesh.close()
+        if base is None:
+            base = got
+            assert int((got[0] >= 0).sum()) > 50_000
+        else:
+            for a, b in zip(base, got):
+                assert torch.equal(a, b), (leaf, branching)
