@@ -4,7 +4,8 @@
 // Persistent wave64 kernel.  The grid holds as many workgroups as the GPU
 // keeps resident; every lane owns one segment at a time and, when it is done,
 // takes the next unprocessed segment from its wave's chunk; a wave claims a
-// new chunk of segments from a global counter with one atomic.  The paper's
+// new chunk of segments with one atomic on the counter of its XCD's range of
+// the segments (the other ranges once its own is used up).  The paper's
 // kernel strides each thread over the rays instead (Section 3.3); with
 // segments whose traversal lengths vary by an order of magnitude, a wave that
 // waits for its slowest lane leaves most of its lanes idle, which the refill
@@ -101,7 +102,7 @@ struct QArgs {
     int32_t max_steps;   // node records: a walk of a valid tree visits each at most once
     int32_t defer;       // test pending leaves once fewer lanes than this can step
     int32_t refill;      // fetch new segments once this many lanes are idle
-    int32_t chunk;       // work items a wave claims per atomic on the global counter
+    int32_t chunk;       // work items a wave claims per atomic on a range counter
     // batched queries: work item k belongs to mesh m with bt.seg_off[m] <= k < bt.seg_off[m+1]
     int32_t M;
     const int32_t *mesh_entry;
@@ -685,14 +686,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((MODE & M_A
         const int32_t q = a.scalars[kRetryN];
         n_items = q < (int32_t)a.retry_cap ? q : (int32_t)a.retry_cap;
     }
-    bool exhausted = false;                 // the global counter has passed the last item
+    bool exhausted = false;                 // every range's counter has passed its last item
 
     for (;;) {
         // ---- lanes whose walk is over write their results and take a new
         // work item, batched: only once `refill` lanes are waiting (or no
         // lane can make progress), so the epilogue and the segment set-up run
         // with many lanes at once.  Items come from the wave's chunk; a new
-        // chunk is claimed from the global counter with one atomic.
+        // chunk is claimed from a range counter with one atomic.
         if (COUNT) ++w_loops;
         const bool done = item >= 0 && node < 0 && (WIDE ? (leaf0 | leaf1 | leaf2 | leaf3) == 0 : leaf0 == 0);
         const uint64_t waiting = ballot(done || item == -1);
@@ -1861,7 +1862,7 @@ hipError_t launch_kernel(const QArgs &a, int block, size_t lds, hipStream_t s)
         if (grid < 1) grid = 1;
         if (b.chunk <= 0) {
             // about eight chunks per resident wave keeps the tail short while the
-            // global counter sees one atomic per chunk
+            // range counters see one atomic per chunk
             const int64_t waves = grid * (block / 64);
             int64_t c = (a.n_items + 8 * waves - 1) / (8 * waves);
             c = (c + 63) / 64 * 64;

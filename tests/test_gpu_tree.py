@@ -150,10 +150,11 @@ def test_sort_clustered_buckets(n_cluster):
 
 @pytest.mark.parametrize("kind", ["sphere", "clustered"])
 def test_sort_large_inputs(kind):
-    """Above 131,072 keys the sort reads back the largest top-digit bucket:
-    a sphere of 180,500 triangles spreads over many buckets (bucket sort),
-    a mesh with most triangles in one corner cell does not (digit passes).
-    Either way the keys and the stable order must match numpy's."""
+    """Above 131,072 keys the bucket sort runs on a scanned histogram table:
+    a sphere of 180,500 triangles spreads over many buckets, each sorted in
+    LDS; a mesh with most triangles in one corner cell puts them in one
+    bucket, which streams through device memory.  Either way the keys and
+    the stable order must match numpy's."""
     if kind == "sphere":
         V, T = wl.noisy_sphere(95, 12, 0.3)
     else:
